@@ -1,0 +1,290 @@
+"""CPU FP64 oracle for one tile-NeRF training step (ctypes over snake_oracle.c).
+
+TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code
+with the HIP library (``paper_2507_01631_amd``) and never imports it.
+
+Every function takes and returns NumPy arrays.  Floating-point results are
+FP64; sample bounds/positions and hash indices come out at the FP32 / integer
+rounding points the library boundary defines, so they compare bit for bit.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "snake_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libsnake_oracle.so")
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+
+def build() -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP over rays)."""
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_level_resolutions.argtypes = [_I, _I, _I, _P]
+        L.orc_hash_index.argtypes = [ctypes.c_uint32] * 3 + [_I, _I, _I]
+        L.orc_hash_index.restype = ctypes.c_uint32
+        L.orc_hash_corners.argtypes = [_P, _I, _I, _I, _P, _P]
+        L.orc_sample_segmented.argtypes = [_I, _P, _P, _I, _P, _P, _P, _I, _P,
+                                           _P, _P, _P, _P, _P, _P, _P, _I64, _P]
+        L.orc_sample_segmented.restype = _I
+        L.orc_hashgrid_fwd.argtypes = [_I, _I, _I, _P, _I, _P, _I64, _P, _P, _I, _P, _P]
+        L.orc_hashgrid_bwd.argtypes = [_I, _I, _I, _P, _I, _I, _I64, _P, _P, _I, _P, _P]
+        L.orc_mlp_param_count.argtypes = [_I] * 6
+        L.orc_mlp_param_count.restype = _I64
+        L.orc_mlp_fwd.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P]
+        L.orc_mlp_bwd.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.orc_composite_fwd.argtypes = [_I, _P, _P, _P, _P, _P, _D, _P, _P, _D,
+                                        _P, _P, _P, _P, _P]
+        L.orc_composite_bwd.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _D, _P, _P]
+        L.orc_adam_step.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, _I, _D]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------------------
+# hash grid
+# ---------------------------------------------------------------------------
+def level_resolutions(L: int, n_min: int, n_max: int) -> np.ndarray:
+    out = np.zeros(L, dtype=np.int32)
+    lib().orc_level_resolutions(L, n_min, n_max, _ptr(out))
+    return out
+
+
+def hash_index(i: int, j: int, k: int, N: int, log2T: int, always_hash: bool = False) -> int:
+    return int(lib().orc_hash_index(i, j, k, N, log2T, int(always_hash)))
+
+
+def hash_corners(x, N: int, log2T: int, always_hash: bool = False):
+    x = _c(x, np.float32)
+    idx = np.zeros(8, dtype=np.uint32)
+    w = np.zeros(8, dtype=np.float64)
+    lib().orc_hash_corners(_ptr(x), N, log2T, int(always_hash), _ptr(idx), _ptr(w))
+    return idx, w
+
+
+def hashgrid_fwd(res, log2T, table, pos, tile_id=None, out_width=32, always_hash=False,
+                 return_index=False):
+    """table: float32 [K][L][T][F]; pos: float32 [n][3] -> feat float64 [n][out_width]."""
+    res = _c(res, np.int32)
+    table = _c(table, np.float32)
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    L, F = int(table.shape[1]), int(table.shape[3])
+    n = pos.shape[0]
+    feat = np.zeros((n, out_width), dtype=np.float64)
+    idx = np.zeros((n, L, 8), dtype=np.uint32) if return_index else None
+    tid = _c(tile_id, np.uint8)
+    lib().orc_hashgrid_fwd(L, F, log2T, _ptr(res), int(always_hash), _ptr(table), n,
+                           _ptr(pos), _ptr(tid), out_width, _ptr(feat), _ptr(idx))
+    return (feat, idx) if return_index else feat
+
+
+def hashgrid_bwd(res, log2T, table_shape, pos, dfeat, tile_id=None, always_hash=False):
+    """Gradient of sum(feat * dfeat) w.r.t. the table: float64 [K][L][T][F]."""
+    K, L, T, F = table_shape
+    res = _c(res, np.int32)
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    dfeat = _c(dfeat, np.float64)
+    n, W = dfeat.shape
+    dtable = np.zeros((K, L, T, F), dtype=np.float64)
+    tid = _c(tile_id, np.uint8)
+    lib().orc_hashgrid_bwd(L, F, log2T, _ptr(res), int(always_hash), K, n, _ptr(pos),
+                           _ptr(tid), W, _ptr(dfeat), _ptr(dtable))
+    return dtable
+
+
+# ---------------------------------------------------------------------------
+# MLP
+# ---------------------------------------------------------------------------
+def _mlp_args(m):
+    return (int(m.feat_width), int(m.hidden), int(m.dens_out), int(m.n_dir),
+            int(m.colour_layers), int(m.colour_out))
+
+
+def mlp_param_count(m) -> int:
+    return int(lib().orc_mlp_param_count(*_mlp_args(m)))
+
+
+def mlp_fwd(m, weights, feat, view, ray_id, sun=None):
+    """feat float64 [n][feat_width]; view/sun float32 [R][3] -> sigma [n], rgb [n][3]."""
+    weights = _c(weights, np.float32)
+    feat = _c(feat, np.float64)
+    n = feat.shape[0]
+    sigma = np.zeros(n)
+    rgb = np.zeros((n, 3))
+    lib().orc_mlp_fwd(*_mlp_args(m), _ptr(weights), n, _ptr(feat), _ptr(_c(view, np.float32)),
+                      _ptr(_c(sun, np.float32)), _ptr(_c(ray_id, np.int32)), _ptr(sigma), _ptr(rgb))
+    return sigma, rgb
+
+
+def mlp_bwd(m, weights, feat, view, ray_id, dsigma, drgb, sun=None):
+    weights = _c(weights, np.float32)
+    feat = _c(feat, np.float64)
+    n = feat.shape[0]
+    dW = np.zeros(weights.shape[0])
+    dfeat = np.zeros_like(feat)
+    lib().orc_mlp_bwd(*_mlp_args(m), _ptr(weights), n, _ptr(feat), _ptr(_c(view, np.float32)),
+                      _ptr(_c(sun, np.float32)), _ptr(_c(ray_id, np.int32)),
+                      _ptr(_c(dsigma, np.float64)), _ptr(_c(drgb, np.float64)),
+                      _ptr(dW), _ptr(dfeat))
+    return dW, dfeat
+
+
+# ---------------------------------------------------------------------------
+# sampler
+# ---------------------------------------------------------------------------
+def sample_segmented(rays_o, rays_d, boxes, S, zband=None, samples_per_ray=None,
+                     max_count=None, cap=None):
+    rays_o = _c(rays_o, np.float64).reshape(-1, 3)
+    rays_d = _c(rays_d, np.float64).reshape(-1, 3)
+    boxes = _c(boxes, np.float64).reshape(-1, 6)
+    R, K = rays_o.shape[0], boxes.shape[0]
+    spr = _c(samples_per_ray, np.int32)
+    if cap is None:
+        cap = int(spr.sum()) if spr is not None else R * int(S)
+    cap = max(int(cap), 0)
+    info = np.zeros((R, 2), dtype=np.int32)
+    t0 = np.zeros(cap, dtype=np.float32)
+    t1 = np.zeros(cap, dtype=np.float32)
+    pos = np.zeros((cap, 3), dtype=np.float32)
+    rid = np.zeros(cap, dtype=np.int32)
+    tid = np.zeros(cap, dtype=np.uint8)
+    view = np.zeros((R, 3), dtype=np.float32)
+    n_out = np.zeros(1, dtype=np.int64)
+    rc = lib().orc_sample_segmented(R, _ptr(rays_o), _ptr(rays_d), K, _ptr(boxes),
+                                    _ptr(_c(zband, np.float64)), _ptr(spr), int(S),
+                                    _ptr(_c(max_count, np.int32)), _ptr(info), _ptr(t0),
+                                    _ptr(t1), _ptr(pos), _ptr(rid), _ptr(tid), _ptr(view),
+                                    cap, _ptr(n_out))
+    n = int(n_out[0])
+    if rc != 0:
+        raise ValueError("oracle sampler: %d samples exceed capacity %d (rc=%d)" % (n, cap, rc))
+    return dict(packed_info=info, t0=t0[:n], t1=t1[:n], pos=pos[:n], ray_id=rid[:n],
+                tile_id=tid[:n], view=view, n=n)
+
+
+# ---------------------------------------------------------------------------
+# volume rendering
+# ---------------------------------------------------------------------------
+def composite_fwd(packed_info, sigma, rgb, t0, t1, target=None, loss_scale=0.0,
+                  early_stop=0.0, alive=None):
+    info = _c(packed_info, np.int32)
+    R = info.shape[0]
+    rgb_out = np.zeros((R, 3))
+    opacity = np.zeros(R)
+    depth = np.zeros(R)
+    n_alive = np.zeros(R, dtype=np.int32)
+    loss = np.zeros(1)
+    lib().orc_composite_fwd(R, _ptr(info), _ptr(_c(sigma, np.float64)), _ptr(_c(rgb, np.float64)),
+                            _ptr(_c(t0, np.float32)), _ptr(_c(t1, np.float32)), float(early_stop),
+                            _ptr(_c(alive, np.int32)), _ptr(_c(target, np.float32)),
+                            float(loss_scale), _ptr(rgb_out), _ptr(opacity), _ptr(depth),
+                            _ptr(n_alive), _ptr(loss))
+    return dict(rgb=rgb_out, opacity=opacity, depth=depth, n_alive=n_alive, loss=float(loss[0]))
+
+
+def composite_bwd(packed_info, sigma, rgb, t0, t1, target, loss_scale, n_alive=None):
+    info = _c(packed_info, np.int32)
+    R = info.shape[0]
+    n = np.asarray(sigma).shape[0]
+    dsigma = np.zeros(n)
+    drgb = np.zeros((n, 3))
+    lib().orc_composite_bwd(R, _ptr(info), _ptr(_c(sigma, np.float64)), _ptr(_c(rgb, np.float64)),
+                            _ptr(_c(t0, np.float32)), _ptr(_c(t1, np.float32)),
+                            _ptr(_c(n_alive, np.int32)), _ptr(_c(target, np.float32)),
+                            float(loss_scale), _ptr(dsigma), _ptr(drgb))
+    return dsigma, drgb
+
+
+# ---------------------------------------------------------------------------
+# Adam
+# ---------------------------------------------------------------------------
+def adam_step(p, g, m, v, lr, step, b1=0.9, b2=0.99, eps=1e-15, l2=0.0):
+    """In place on float64 arrays p, m, v."""
+    assert p.dtype == m.dtype == v.dtype == np.float64
+    g = _c(g, np.float64)
+    lib().orc_adam_step(p.size, _ptr(p), _ptr(g), _ptr(m), _ptr(v), float(lr), float(b1),
+                        float(b2), float(eps), int(step), float(l2))
+
+
+# ---------------------------------------------------------------------------
+# one training step, composed in the paper's order
+# ---------------------------------------------------------------------------
+def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=1,
+               alive=None, rays=None, timings=None):
+    """One step of the tile-NeRF: segmented sampling -> hash encoding -> density
+    and colour nets -> volume rendering + MSE loss -> adjoints -> Adam.
+
+    ``wl`` supplies the rays, boxes, band, targets and configs (any object with
+    the attributes of ``synth.Workload``).  ``alive`` optionally fixes the
+    per-ray early-stop counts (to follow another implementation's decision
+    where floating point rounding makes it ambiguous).  Returns a dict of every
+    intermediate, the gradients and the updated FP64 parameters."""
+    t_start = time.perf_counter()
+    g, m = wl.grid, wl.mlp
+    if res is None:
+        res = level_resolutions(g.n_levels, g.res_min, g.res_max)
+    table = wl.table if table is None else table
+    mlp_params = wl.mlp_params if mlp_params is None else mlp_params
+    rays_o, rays_d = (wl.rays_o, wl.rays_d) if rays is None else rays
+    target = wl.target if rays is None else rays[2]
+    sun = wl.sun if rays is None else rays[3]
+    R = rays_o.shape[0]
+    out = {}
+    smp = sample_segmented(rays_o, rays_d, wl.boxes, wl.samples_per_ray, zband=wl.zband)
+    out["sample"] = smp
+    feat = hashgrid_fwd(res, g.log2_table, table, smp["pos"], smp["tile_id"], g.out_width)
+    sigma, rgb = mlp_fwd(m, mlp_params, feat, smp["view"], smp["ray_id"], sun=sun)
+    loss_scale = 1.0 / (3.0 * R)
+    comp = composite_fwd(smp["packed_info"], sigma, rgb, smp["t0"], smp["t1"], target,
+                         loss_scale, early_stop=wl.early_stop, alive=alive)
+    n_alive = comp["n_alive"] if alive is None else np.asarray(alive, dtype=np.int32)
+    dsigma, drgb = composite_bwd(smp["packed_info"], sigma, rgb, smp["t0"], smp["t1"],
+                                 target, loss_scale, n_alive=n_alive)
+    dW, dfeat = mlp_bwd(m, mlp_params, feat, smp["view"], smp["ray_id"], dsigma, drgb, sun=sun)
+    dtable = hashgrid_bwd(res, g.log2_table, table.shape, smp["pos"], dfeat, smp["tile_id"])
+    if adam_state is None:
+        adam_state = dict(m_t=np.zeros(table.size), v_t=np.zeros(table.size),
+                          m_w=np.zeros(mlp_params.size), v_w=np.zeros(mlp_params.size))
+    p_t = table.astype(np.float64).ravel().copy()
+    p_w = mlp_params.astype(np.float64).copy()
+    adam_step(p_t, dtable.ravel(), adam_state["m_t"], adam_state["v_t"], wl.lr, step)
+    adam_step(p_w, dW, adam_state["m_w"], adam_state["v_w"], wl.lr, step)
+    out.update(res=res, feat=feat, sigma=sigma, rgb=rgb, comp=comp, n_alive=n_alive,
+               dsigma=dsigma, drgb=drgb, dW=dW, dfeat=dfeat, dtable=dtable,
+               table_new=p_t.reshape(table.shape), mlp_new=p_w, adam=adam_state,
+               loss=comp["loss"], n_samples=int(n_alive.sum()), n_total=smp["n"])
+    if timings is not None:
+        timings.append(time.perf_counter() - t_start)
+    return out
