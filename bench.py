@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of one tile-NeRF training step on one MI355X.
+
+Metric: ray-samples/s for forward + backward + Adam, BF16-MFMA MLP form (the
+reported value) beside the FP32 form, with the dominant kernel's fraction of
+its roofline.  A "step" is one pass of the whole path over one batch of rays:
+segmented sampling -> hash encoding -> density/colour MLP -> volume rendering
++ MSE loss -> composite adjoint -> MLP adjoint (recomputed activations) ->
+hash-table scatter (FP32 atomics) -> Adam on the table and the MLP.
+
+Workload (full-size single tile): hash grid L=16, F=2, T=2^19, resolutions
+16 -> 2048; density MLP 32->64->16, colour MLP 21->64->64->4; 2^18 rays per
+batch from 8 synthetic affine satellite views over a heightfield scene; up to
+128 samples per ray in the altitude band z in [0.2, 0.8], transmittance early
+stop at 1e-4.  Samples are counted after early stop (those entering the
+adjoint).  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8.0e12, "bf16": 2.5e15, "fp32": 157.3e12}
+STAGES = ("sample", "hash_fwd", "mlp_fwd", "comp_fwd", "comp_bwd", "pack", "mlp_bwd", "hash_bwd",
+          "adam")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mlp_macs(n_dir, colour_layers, colour_out, feat=32, hidden=64, dens_out=16):
+    return (feat * hidden + hidden * dens_out + (dens_out - 1 + n_dir) * hidden
+            + (colour_layers - 1) * hidden * hidden + hidden * colour_out)
+
+
+def make_nerf(wl, precision, max_rays, device):
+    from paper_2507_01631_amd import TileNeRF, level_resolutions
+    g, m = wl.grid, wl.mlp
+    return TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
+                    log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
+                    colour_out=m.colour_out, boxes=wl.boxes, zband=wl.zband, samples=wl.samples_per_ray,
+                    early_stop=wl.early_stop, precision=precision, table=wl.table,
+                    mlp_params=wl.mlp_params, max_rays=max_rays, lr=wl.lr, device=device)
+
+
+def run_form(wl, precision, args, pool):
+    import torch
+    dev = "cuda:0"
+    R = args.rays
+    nerf = make_nerf(wl, precision, R, dev)
+    ro_all, rd_all, tg_all, sun_all = pool
+    nb = args.batches
+
+    def batch(k):
+        b = k % nb
+        s = slice(b * R, (b + 1) * R)
+        return ro_all[s], rd_all[s], tg_all[s], sun_all[s]
+
+    for k in range(args.warmup):
+        nerf.train_step(*batch(k))
+    torch.cuda.synchronize()
+    log("  %s: warmup %d steps done" % (precision, args.warmup))
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)] for _ in range(K)]
+    n_alive = torch.zeros(K, dtype=torch.int64, device=dev)
+    n_total = torch.zeros(K, dtype=torch.int64, device=dev)
+    scale = 1.0 / (3.0 * R)
+    from paper_2507_01631_amd import _lib as L
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for k in range(K):
+        ro, rd, tg, sun = batch(args.warmup + k)
+        e = ev[k]
+        nerf.loss.zero_()
+        e[0].record()
+        nerf.sample(ro, rd, R)
+        e[1].record()
+        L.snake_hashgrid_fwd(nerf.grid, nerf.table, nerf.pos, nerf.tile_id, None, nerf.cap, nerf.n_out,
+                             nerf.feat)
+        e[2].record()
+        L.snake_mlp_fwd(nerf.mlp, nerf.params, nerf.feat, nerf.view, sun, nerf.ray_id, None, nerf.cap,
+                        nerf.n_out, nerf.sigma, nerf.rgb)
+        e[3].record()
+        nerf.render(R, tg, scale)
+        e[4].record()
+        L.snake_composite_bwd(nerf.sigma, nerf.rgb, nerf.t0, nerf.t1, nerf.packed_info, R, nerf.n_alive,
+                              tg, scale, nerf.dsigma, nerf.drgb)
+        e[5].record()
+        L.snake_pack_alive(nerf.packed_info, nerf.n_alive, R, nerf.alive_idx, nerf.cap,
+                           nerf.n_alive_total, nerf.ws_sample)
+        e[6].record()
+        L.snake_mlp_bwd(nerf.mlp, nerf.params, nerf.feat, nerf.cap, nerf.view, sun, nerf.ray_id,
+                        nerf.alive_idx, nerf.cap, nerf.n_alive_total, nerf.dsigma, nerf.drgb, nerf.g_w,
+                        nerf.dfeat, nerf.ws_mlp)
+        e[7].record()
+        L.snake_hashgrid_bwd(nerf.grid, nerf.pos, nerf.tile_id, nerf.alive_idx, nerf.cap,
+                             nerf.n_alive_total, nerf.dfeat, nerf.g_t)
+        e[8].record()
+        nerf.adam()
+        e[9].record()
+        n_alive[k:k + 1].copy_(nerf.n_alive_total)
+        n_total[k:k + 1].copy_(nerf.n_out)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(end)
+    stage_ms = np.zeros(len(STAGES))
+    for k in range(K):
+        for i in range(len(STAGES)):
+            stage_ms[i] += ev[k][i].elapsed_time(ev[k][i + 1])
+    stage_ms /= K
+    na = n_alive.cpu().numpy().astype(np.float64)
+    nt = n_total.cpu().numpy().astype(np.float64)
+    loss = float(nerf.loss.item())
+    log("  %s: %d steps, %.3f ms/step (wall %.3f), alive %.3g/%.3g samples/step, loss %.4g"
+        % (precision, K, total_ms / K, 1e3 * wall / K, na.mean(), nt.mean(), loss))
+    return dict(ms_per_step=total_ms / K, wall_ms_per_step=1e3 * wall / K, samples_alive=na.mean(),
+                samples_total=nt.mean(), value=na.sum() / (total_ms * 1e-3),
+                stage_ms=dict(zip(STAGES, stage_ms.tolist())), loss=loss,
+                params=int(nerf.table.numel() + nerf.P), table_params=int(nerf.table.numel()),
+                mlp_params=int(nerf.P), L=len(nerf.res), F=nerf.F)
+
+
+def roofline(form, wl, precision, R):
+    """Algorithmic work per launch of each stage and its rate against peak."""
+    Lv, F = form["L"], form["F"]
+    nt, na = form["samples_total"], form["samples_alive"]
+    fb = 2 if precision == "bf16" else 4
+    macs = mlp_macs(wl.mlp.n_dir, wl.mlp.colour_layers, wl.mlp.colour_out)
+    work = {
+        "sample": ("hbm", R * (48 + 8 + 12) + nt * (4 + 4 + 12 + 4)),
+        "hash_fwd": ("hbm", nt * (12 + Lv * 8 * F * 4 + Lv * F * fb)),
+        "mlp_fwd": ("mfma", nt * 2 * macs),
+        "comp_fwd": ("hbm", nt * (4 + 12 + 4 + 4) + R * (8 + 12 + 12 + 4 + 4 + 4)),
+        "comp_bwd": ("hbm", nt * (4 + 12 + 4 + 4 + 4 + 12) + R * (8 + 12 + 4)),
+        "pack": ("hbm", R * (8 + 4) + na * 4),
+        "mlp_bwd": ("mfma", na * 3 * 2 * macs),
+        "hash_bwd": ("hbm", na * (4 + 12 + Lv * F * 4 + Lv * 8 * F * 4 * 2)),
+        "adam": ("hbm", form["params"] * 28),
+    }
+    mpeak = PEAK["bf16"] if precision == "bf16" else PEAK["fp32"]
+    out = {}
+    for k, (bound, amount) in work.items():
+        t = form["stage_ms"][k] * 1e-3
+        peak = PEAK["hbm"] if bound == "hbm" else mpeak
+        ach = amount / t if t > 0 else 0.0
+        out[k] = dict(bound=bound, per_launch=amount, ms=form["stage_ms"][k], achieved=ach, peak=peak,
+                      frac=ach / peak)
+    return out
+
+
+def cpu_baseline(args):
+    import oracle
+    import synth
+    wl = synth.full_tile(seed=0, n_rays=args.cpu_rays)
+    oracle.lib()
+    t = time.perf_counter()
+    out = oracle.train_step(wl)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": out["n_samples"] / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
+            "sample": "one full step (sampler, encoding, MLP, rendering, adjoints, Adam) of the "
+                      "full-tile workload on %d rays (%d samples after early stop), FP64 C oracle, "
+                      "%.1f s" % (args.cpu_rays, out["n_samples"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--rays", type=int, default=1 << 18)
+    ap.add_argument("--batches", type=int, default=2, help="distinct ray batches cycled through")
+    ap.add_argument("--precision", choices=["bf16", "fp32", "both"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=1 << 14)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs the single-GPU tile step only; --gpus %d is not supported "
+              "(see the sharding note in the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2507_01631_amd import _lib
+    _lib.lib()
+    t = time.perf_counter()
+    wl = synth.full_tile(seed=0, n_rays=args.rays * args.batches)
+    log("workload generated in %.1f s (%d rays)" % (time.perf_counter() - t, wl.n_rays))
+    dev = "cuda:0"
+    pool = (torch.as_tensor(wl.rays_o).to(dev), torch.as_tensor(wl.rays_d).to(dev),
+            torch.as_tensor(wl.target).to(dev), torch.as_tensor(wl.sun).to(dev))
+    forms = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
+    res = {}
+    for p in forms:
+        res[p] = run_form(wl, p, args, pool)
+    head = forms[0]
+    f = res[head]
+    rl = roofline(f, wl, head, args.rays)
+    dom = max(rl, key=lambda k: rl[k]["ms"])
+    d = rl[dom]
+    line = {
+        "metric": "NeRF train ray-samples/s fwd+bwd, BF16-MFMA vs FP32; % HBM/MFMA roofline",
+        "value": f["value"], "unit": "ray-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
+        "config": {"workload": "full_tile: L=16 F=2 T=2^19 res 16-2048, MLP 32-64-16 / 21-64-64-4, "
+                               "%d rays/batch, <=128 samples/ray, z band [0.2,0.8], early stop 1e-4"
+                               % args.rays,
+                   "rays_per_step": args.rays, "samples_alive_per_step": f["samples_alive"],
+                   "samples_total_per_step": f["samples_total"], "precision": head},
+        "roofline": {"kernel": dom, "bound": "hbm" if d["bound"] == "hbm" else "mfma",
+                     "achieved": d["achieved"] / (1e9 if d["bound"] == "hbm" else 1e12),
+                     "peak": d["peak"] / (1e9 if d["bound"] == "hbm" else 1e12),
+                     "unit": "GB/s" if d["bound"] == "hbm" else "TFLOP/s", "frac": d["frac"],
+                     "traffic": None},
+        "stages": {k: {"ms": round(v["ms"], 4), "frac": round(v["frac"], 4), "bound": v["bound"]}
+                   for k, v in rl.items()},
+    }
+    for p in forms[1:]:
+        g = res[p]
+        line["%s_form" % p] = {"value": g["value"], "ms_per_step": g["ms_per_step"],
+                               "samples_alive_per_step": g["samples_alive"],
+                               "stages_ms": {k: round(v, 4) for k, v in g["stage_ms"].items()}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,271 @@
+/*
+ * libsnake -- one training step of a tile NeRF on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Tile and Slide: A New Framework for Scaling NeRF from Local to
+ * Global 3D Earth Observation" (Snake-NeRF, arXiv 2507.01631).  A large scene
+ * is cut into non-overlapping NeRF tiles (Sec. 4.2); each NeRF is a
+ * multiresolution hash encoding feeding a local density network whose
+ * embedding feeds a colour network (Sec. 4.1); rays are cut at tile
+ * boundaries and sampled per segment (Sec. 4.5); colours come from the
+ * unmodified volume-rendering quadrature and a colour-consistency loss
+ * (Sec. 2.2, 4.4); optimisation follows the I-NGP strategy (Sec. 4.6).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *     row-major, aligned to their element size (16 B for float4-read arrays
+ *     where stated).  Scalars and descriptor structs are host values.
+ *   - The library allocates nothing in these calls; scratch memory is the
+ *     caller's `workspace`, sized by the matching *_workspace_bytes query.
+ *   - Every call is asynchronous on the HIP stream passed last (0 = the null
+ *     stream) and returns a snake_status.  Argument errors are detected on the
+ *     host before any launch and leave outputs untouched; the message is
+ *     available from snake_last_error() (thread-local).
+ *   - Sample counts may live on the device: where a call takes `n` (host, an
+ *     upper bound used to size the launch) and `n_dev` (device int64, may be
+ *     NULL), the effective count is min(n, *n_dev).  No call synchronises the
+ *     host, so a step can be captured in a HIP graph.
+ *   - Gradient outputs ACCUMULATE (+=); the caller zeroes them.
+ *   - Sample-indexed inputs may be read through an optional index list
+ *     `sample_idx` (device int32, NULL = identity): entry j of the call reads
+ *     input sample sample_idx[j] and writes its per-sample outputs at j.
+ *
+ * Data layouts
+ *   rays        rays_o, rays_d  [R][3] double, world frame (e.g. UTM metres)
+ *   NeRF tiles  boxes [K][6] double: lo_x lo_y lo_z hi_x hi_y hi_z
+ *   samples     packed per ray, t-ordered: packed_info [R][2] int32 (start,
+ *               count); t0, t1 [N] float (world ray parameter); pos [N][3]
+ *               float in the tile's [0,1]^3 frame; ray_id [N] int32;
+ *               tile_id [N] uint8
+ *   table       [K][L][T][F] float (T = 2^log2_table entries per level)
+ *   features    level-major [L][N][F] (float, or bf16 when requested), so
+ *               that every level reads and writes coalesced; the level
+ *               stride is the call's host bound `n` unless stated
+ *   MLP weights one float vector, row-major [out][in] matrices packed in the
+ *               order of snake_mlp_param_count()
+ */
+#ifndef SNAKE_H
+#define SNAKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNAKE_ABI_VERSION 1
+
+typedef struct ihipStream_t *snake_stream_t;   /* == hipStream_t */
+
+typedef enum {
+    SNAKE_OK = 0,
+    SNAKE_ERR_INVALID_ARG = -1,   /* a size, count or descriptor field is out of range */
+    SNAKE_ERR_NULL = -2,          /* a required pointer is NULL */
+    SNAKE_ERR_ALIGN = -3,         /* a pointer is not aligned as documented */
+    SNAKE_ERR_UNSUPPORTED = -4,   /* valid but not implemented (e.g. F not in {1,2,4}) */
+    SNAKE_ERR_HIP = -5,           /* a HIP runtime call failed (launch error) */
+    SNAKE_ERR_WORKSPACE = -6,     /* workspace NULL or smaller than required */
+    SNAKE_ERR_DEVICE = -7         /* snake_check_device_error found a device-side error */
+} snake_status;
+
+/* Device-side error bits, reported by snake_check_device_error(). */
+#define SNAKE_DEVERR_CAPACITY 1u  /* sampler: packed samples exceed `cap` */
+
+typedef enum { SNAKE_F32 = 0, SNAKE_BF16 = 1 } snake_dtype;
+
+/* Library version (SNAKE_ABI_VERSION). */
+int snake_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *snake_last_error(void);
+
+/* Synchronises `stream`, then reads and clears the device error word of the
+ * current device.  Returns SNAKE_OK, or SNAKE_ERR_DEVICE with the error bits
+ * in *bits (may be NULL). */
+int snake_check_device_error(snake_stream_t stream, uint32_t *bits);
+
+/* ------------------------------------------------------------------------ */
+/* Segmented sampler (Sec. 4.5 with the distribution kernel of Sec. 4.6 and  */
+/* the UTM-to-local mapping of Sec. 4.1-4.2)                                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * For each ray, intersect it in FP64 with each of the K NeRF-tile boxes
+ * (optionally clipped in z to the altitude band zband = [z_lo, z_hi], host
+ * pointer or NULL), sort the hit segments by entry distance, and give the
+ * ray's budget S_r = samples_per_ray ? samples_per_ray[r] : S samples to its
+ * segments: one each when S_r >= #segments, the rest in proportion to
+ * segment length by cumulative rounding (rint(E * cum/total)), so that
+ * the counts sum to S_r.  max_count (device, NULL = none) truncates ray r to
+ * its first max_count[r] samples (early stop); the kept samples are bit for
+ * bit the prefix of the untruncated ones.
+ *
+ * A segment [t_near, t_far] with n samples gives the intervals
+ * [t_j, t_{j+1}]: tn = fl32(t_near), tf = fl32(t_far),
+ * step = fl32(fl32(tf - tn)/n), t_j = fl32(tn + fl32(j*step)), t_n = tf.
+ * Each interval is evaluated at its midpoint m = fl32(0.5 fl32(t_j+t_{j+1}))
+ * mapped to the tile's frame: pos_a = clamp(fl32(o'_a + fl32(m d'_a)), 0, 1)
+ * with o'_a = fl32((o_a-lo_a)/(hi_a-lo_a)), d'_a = fl32(d_a/(hi_a-lo_a)).
+ * A slab hit needs t_far > t_near (t_near clamped at 0); an axis-parallel
+ * ray is inside a slab when lo <= o < hi.  Segments of neighbouring tiles
+ * meet bit-exactly on their shared face.  view[R][3] = fl32(d/|d|).
+ *
+ * Outputs: packed_info [R][2]; t0, t1, pos, ray_id, tile_id (tile_id may be
+ * NULL when K == 1) for up to `cap` samples; *n_out (device int64) = the
+ * packed total.  If the total exceeds cap, samples past cap are not written
+ * and SNAKE_DEVERR_CAPACITY is raised on the device.
+ * boxes [K][6] and zband [2] are HOST pointers, copied at call time.
+ * Workspace: snake_sample_workspace_bytes(R).  Limits: 1 <= K <= 16.
+ */
+size_t snake_sample_workspace_bytes(int32_t R);
+int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R,
+                           const double *boxes, int32_t K, const double *zband,
+                           const int32_t *samples_per_ray, int32_t S,
+                           const int32_t *max_count,
+                           int32_t *packed_info, float *t0, float *t1, float *pos,
+                           int32_t *ray_id, uint8_t *tile_id, float *view,
+                           int64_t cap, int64_t *n_out,
+                           void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
+/*
+ * Index list of the samples kept by early stop: for each ray r, the first
+ * n_alive[r] of its packed samples, in order.  idx_out [cap] int32 receives
+ * their packed indices and *n_out (device int64) their total.  Workspace:
+ * snake_sample_workspace_bytes(R).
+ */
+int snake_pack_alive(const int32_t *packed_info, const int32_t *n_alive, int32_t R,
+                     int32_t *idx_out, int64_t cap, int64_t *n_out,
+                     void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Multiresolution hash encoding (Sec. 4.1; the NGP representation)          */
+/* ------------------------------------------------------------------------ */
+
+#define SNAKE_MAX_LEVELS 32
+#define SNAKE_GRID_ALWAYS_HASH 1u      /* hash every level, even when dense fits */
+
+typedef struct {
+    int32_t n_levels;                  /* L, 1..32 */
+    int32_t n_features;                /* F, 1, 2 or 4 */
+    int32_t log2_table;                /* log2 T, 4..24 */
+    int32_t feat_dtype;                /* snake_dtype of the feature array */
+    uint32_t flags;                    /* SNAKE_GRID_* */
+    int32_t resolution[SNAKE_MAX_LEVELS];  /* N_l >= 1 per level */
+} snake_grid_desc;
+
+/*
+ * Level l of resolution N: p = fl32(x * N) per axis, cell c = min(floor p, N-1),
+ * w = p - c; the 8 corners c + b (b in {0,1}^3, bit 0 = x) are stored at
+ *   dense:  i + j (N+1) + k (N+1)^2                       if (N+1)^3 <= T
+ *   hashed: (i*1 XOR j*2654435761 XOR k*805459861) mod 2^32 AND (T-1)
+ * and feat[l][s][f] = sum_b w_b table[tile][l][idx_b][f] with
+ * w_b = prod_a (b_a ? w_a : 1 - w_a).
+ * pos [.][3] float, tile_id (NULL = tile 0 for all), feat [L][n][F] written.
+ * idx_dbg (NULL or [n][L][8] uint32) receives the corner slots.
+ */
+int snake_hashgrid_fwd(const snake_grid_desc *g, const float *table,
+                       const float *pos, const uint8_t *tile_id, const int32_t *sample_idx,
+                       int64_t n, const int64_t *n_dev, void *feat, uint32_t *idx_dbg,
+                       snake_stream_t stream);
+
+/* Adjoint: dtable[tile][l][idx_b][f] += w_b * dfeat[l][s][f] (float atomics;
+ * the order of additions, hence the last bits, is not deterministic).
+ * dfeat [L][n][F] float.  dtable [K][L][T][F] float. */
+int snake_hashgrid_bwd(const snake_grid_desc *g, const float *pos, const uint8_t *tile_id,
+                       const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
+                       const float *dfeat, float *dtable, snake_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Density and colour networks (Sec. 4.1)                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n_levels;        /* L of the encoding feeding the density net */
+    int32_t n_features;      /* F of the encoding; L*F <= 32, the density input is
+                                zero-padded to 32 */
+    int32_t n_dir;           /* 3: view direction; 6: view + sun direction */
+    int32_t colour_layers;   /* hidden layers of the colour net: 1 or 2 */
+    int32_t colour_out;      /* 3: rgb = sigmoid(o); 4: rgb = sigmoid(o_0..2) sigmoid(o_3) */
+    int32_t precision;       /* SNAKE_F32 or SNAKE_BF16 (MFMA with FP32 accumulation) */
+    int32_t feat_dtype;      /* snake_dtype of the feature array */
+} snake_mlp_desc;
+
+/* Fixed widths: density 32 -> 64 -> 16 (ReLU hidden, sigma = exp(o_0),
+ * embedding o_1..o_15), colour [embedding, view, (sun)] -> 64 (-> 64) -> 3|4,
+ * no biases.  Packed weight order: density L1 [64][32], density L2 [16][64],
+ * colour L1 [64][15+n_dir], colour L2 [64][64] (if 2 layers), colour out
+ * [colour_out][64]. */
+int64_t snake_mlp_param_count(const snake_mlp_desc *m);
+
+/* Forward.  feat [L][n][F] (level-major; sample j's row is j), view/sun
+ * [R][3] float per ray (sun may be NULL when n_dir == 3), ray_id per input
+ * sample (read through sample_idx).  Writes sigma [n], rgb [n][3].  BF16
+ * precision rounds inputs, weights and hidden activations to bf16 (RNE) and
+ * accumulates in FP32. */
+int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat,
+                  const float *view, const float *sun, const int32_t *ray_id,
+                  const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
+                  float *sigma, float *rgb, snake_stream_t stream);
+
+/* Adjoint, recomputing the activations from feat.  feat, ray_id, dsigma
+ * and drgb are read through sample_idx (feat level-major with level stride
+ * feat_ld >= every index read); dfeat [L][n][F] float is written compact at
+ * j.  dW [P] += the sum over samples, reduced in a fixed order (deterministic
+ * for a given n).  Workspace: snake_mlp_bwd_workspace_bytes(m). */
+size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m);
+int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat,
+                  int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
+                  const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
+                  const float *dsigma, const float *drgb, float *dW, float *dfeat,
+                  void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Volume rendering and colour-consistency loss (Sec. 2.2, 4.4, 4.5)         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Per ray: delta_i = t1_i - t0_i, T_i = exp(-sum_{j<i} sigma_j delta_j) (a
+ * prefix product of exp(-sigma_j delta_j), taken as a prefix sum of optical
+ * depth across the wavefront), alpha_i = 1 - exp(-sigma_i delta_i),
+ * w_i = T_i alpha_i; rgb_out = sum w_i c_i, opacity = sum w_i,
+ * depth = sum w_i (t0_i + t1_i)/2; background 0.  early_stop_T > 0 keeps only
+ * the samples with T_i >= early_stop_T (a prefix); n_alive [R] (may be NULL)
+ * receives the kept count.  With target [R][3] given, *loss (device float)
+ * += loss_scale * sum_r sum_ch (rgb_out - target)^2.  opacity, depth, loss may
+ * be NULL.
+ */
+int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
+                        const int32_t *packed_info, int32_t R, float early_stop_T,
+                        const float *target, float loss_scale,
+                        float *rgb_out, float *opacity, float *depth, int32_t *n_alive,
+                        float *loss, snake_stream_t stream);
+
+/*
+ * Adjoint of the loss above with g = 2 loss_scale (C - target):
+ *   drgb_i = w_i g,  dsigma_i = delta_i sum_ch g_ch (T_{i+1} c_i,ch - (C_ch - A_i,ch)),
+ * A_i = sum_{j<=i} w_j c_j, for i < n_alive[r] (all samples if n_alive is NULL);
+ * the other samples of the ray get 0.  dsigma [N], drgb [N][3] written.
+ */
+int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
+                        const int32_t *packed_info, int32_t R, const int32_t *n_alive,
+                        const float *target, float loss_scale,
+                        float *dsigma, float *drgb, snake_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Adam (the I-NGP optimisation strategy, Sec. 4.6)                          */
+/* ------------------------------------------------------------------------ */
+
+#define SNAKE_ADAM_ZERO_GRAD 1u    /* write 0 to g after reading it */
+
+/* g' = g + l2 p; m = b1 m + (1-b1) g'; v = b2 v + (1-b2) g'^2;
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), step >= 1.
+ * p, g, m, v [n] float, 16-byte aligned. */
+int snake_adam_step(float *p, float *g, float *m, float *v, int64_t n,
+                    float lr, float b1, float b2, float eps, int32_t step, float l2,
+                    uint32_t flags, snake_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAKE_H */

@@ -1,0 +1,761 @@
+// Density and colour networks of a tile NeRF (Sec. 4.1) on CDNA4 matrix cores.
+//
+// Shapes are fixed by the architecture: density 32 -> 64 -> 16 (ReLU hidden,
+// sigma = exp(o_0), embedding o_1..o_15), colour [o_1..o_15, view, (sun)] ->
+// 64 (-> 64) -> 3|4, no biases.
+//
+// Every layer is a 16-sample tile multiplied on MFMA: weights are the A
+// operand (output units x inputs), activations the B operand (inputs x 16
+// samples), so a layer's output (lane (i, q) holds rows 4q..4q+3 of sample i)
+// is directly the next layer's B operand once the weight fragments in LDS
+// carry the matching K permutation.  FP32 form: v_mfma_f32_16x16x4_f32.
+// BF16 form: v_mfma_f32_16x16x32_bf16 (K=16 layers: 16x16x16) with FP32
+// accumulation; inputs, weights and hidden activations rounded RNE to bf16.
+//
+// The adjoint recomputes activations from the features (no activation
+// storage), runs the transposed chain, and accumulates weight gradients with
+// MFMA over samples (K = samples) after a per-wave LDS transpose.  Per-block
+// partial sums are reduced in a fixed order by a second kernel.
+#include "common.h"
+
+namespace snake {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;   // 4 wavefronts
+constexpr int kStageStride = 20;  // floats per staged row (16 samples + pad)
+constexpr int kStageRows = 128;
+constexpr int kMaxBwdBlocks = 512;
+
+enum Prec { P_F32 = 0, P_BF16 = 1 };
+enum Mat { M_D1 = 0, M_D2, M_C1, M_C2, M_CO };
+
+struct MlpArgs {
+    int L, F, n_feat;       // encoding levels, features per level, L*F
+    int n_dir, CL, CO;      // directions (3|6), colour hidden layers (1|2), colour outputs (3|4)
+    int cin_real;           // 15 + n_dir
+    int64_t off[5];         // offsets of D1, D2, C1, C2, CO in the packed weights
+    int64_t P;              // packed parameter count
+};
+
+// Padded weight value: D1 [64][32], D2 [16][64], C1 [64][32] whose column p
+// is o_p (p < 16, column 0 = sigma logit is 0) or direction p-16, C2 [64][64],
+// CO [16][64] (rows >= CO are 0).
+__device__ __forceinline__ float wval(const float *w, const MlpArgs &a, int mat, int r, int c)
+{
+    switch (mat) {
+    case M_D1:
+        return w[a.off[0] + r * 32 + c];
+    case M_D2:
+        return w[a.off[1] + r * 64 + c];
+    case M_C1:
+        if (c >= 1 && c < 16) return w[a.off[2] + r * a.cin_real + (c - 1)];
+        if (c >= 16 && c < 16 + a.n_dir) return w[a.off[2] + r * a.cin_real + 15 + (c - 16)];
+        return 0.0f;
+    case M_C2:
+        return w[a.off[3] + r * 64 + c];
+    default:
+        return r < a.CO ? w[a.off[4] + r * 64 + c] : 0.0f;
+    }
+}
+
+template <int PREC>
+struct FragT {
+    typedef float T;
+};
+template <>
+struct FragT<P_BF16> {
+    typedef __bf16 T;
+};
+
+// Fill the A-operand fragments of an MO x MI layer (W or W^T of `mat`).
+template <int PREC, int MO, int MI>
+__device__ void build_frag(typename FragT<PREC>::T *dst, const float *w, const MlpArgs &a, int mat,
+                           bool transposed)
+{
+    for (int e = threadIdx.x; e < MO * MI; e += blockDim.x) {
+        int row, col;
+        if (PREC == P_F32) {
+            const int r = e & 3, lane = (e >> 2) & 63, blk = e >> 8;
+            const int to = blk / (MI / 16), ti = blk % (MI / 16);
+            row = 16 * to + (lane & 15);
+            col = 16 * ti + 4 * (lane >> 4) + r;
+        } else if (MI % 32 == 0) {
+            const int k = e & 7, lane = (e >> 3) & 63, blk = e >> 9;
+            const int to = blk / (MI / 32), u = blk % (MI / 32), q = lane >> 4;
+            row = 16 * to + (lane & 15);
+            col = 32 * u + (k < 4 ? 4 * q + k : 16 + 4 * q + (k - 4));
+        } else {
+            const int k = e & 3, lane = (e >> 2) & 63, to = e >> 8;
+            row = 16 * to + (lane & 15);
+            col = 4 * (lane >> 4) + k;
+        }
+        const float v = transposed ? wval(w, a, mat, col, row) : wval(w, a, mat, row, col);
+        dst[e] = (typename FragT<PREC>::T)v;
+    }
+}
+
+// y[MO/16][4] = W (MO x MI) . x[MI/16][4] for one 16-sample tile.
+template <int PREC, int MO, int MI>
+__device__ __forceinline__ void apply(const typename FragT<PREC>::T *frag, const float (&x)[MI / 16][4],
+                                      float (&y)[MO / 16][4])
+{
+    const int lane = lane_id();
+    if constexpr (PREC == P_F32) {
+        const f4 *fr = reinterpret_cast<const f4 *>(frag);
+#pragma unroll
+        for (int to = 0; to < MO / 16; ++to) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ti = 0; ti < MI / 16; ++ti) {
+                const f4 av = fr[(to * (MI / 16) + ti) * 64 + lane];
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], x[ti][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], x[ti][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], x[ti][2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], x[ti][3], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[to][r] = acc[r];
+        }
+    } else if constexpr (MI % 32 == 0) {
+        const bf8 *fr = reinterpret_cast<const bf8 *>(frag);
+        bf8 b[MI / 32];
+#pragma unroll
+        for (int u = 0; u < MI / 32; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                b[u][r] = (__bf16)x[2 * u][r];
+                b[u][4 + r] = (__bf16)x[2 * u + 1][r];
+            }
+#pragma unroll
+        for (int to = 0; to < MO / 16; ++to) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < MI / 32; ++u)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[(to * (MI / 32) + u) * 64 + lane], b[u], acc, 0,
+                                                             0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[to][r] = acc[r];
+        }
+    } else {
+        static_assert(MI == 16, "K=16 layers only");
+        const s4 *fr = reinterpret_cast<const s4 *>(frag);
+        bf4 bb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bb[r] = (__bf16)x[0][r];
+        const s4 b = __builtin_bit_cast(s4, bb);
+#pragma unroll
+        for (int to = 0; to < MO / 16; ++to) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fr[to * 64 + lane], b, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[to][r] = acc[r];
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void relu(float (&v)[T][4])
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[t][r] = fmaxf(v[t][r], 0.0f);
+}
+
+template <int T>
+__device__ __forceinline__ void relu_mask(float (&d)[T][4], const float (&act)[T][4])
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[t][r] = act[t][r] > 0.0f ? d[t][r] : 0.0f;
+}
+
+__device__ __forceinline__ float load_f(const float *p) { return *p; }
+__device__ __forceinline__ float load_f(const __hip_bfloat16 *p) { return __bfloat162float(*p); }
+
+// Density input rows 0..31 (row p = level p/F, feature p%F; rows >= L*F are 0).
+template <typename FT>
+__device__ __forceinline__ void load_features(const FT *feat, int64_t ld, int64_t s, bool valid,
+                                              const MlpArgs &a, float (&x)[2][4])
+{
+    const int q = lane_id() >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * t + 4 * q + r;
+            float v = 0.0f;
+            if (valid && p < a.n_feat) {
+                const int lvl = p / a.F, f = p - lvl * a.F;
+                v = load_f(feat + ((int64_t)lvl * ld + s) * a.F + f);
+            }
+            x[t][r] = v;
+        }
+}
+
+// Colour input rows 16..31: view xyz, sun xyz (n_dir == 6), then zeros.
+__device__ __forceinline__ void load_dirs(const float *view, const float *sun, int64_t ray, bool valid,
+                                          const MlpArgs &a, float (&c)[4])
+{
+    const int q = lane_id() >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 4 * q + r;
+        float v = 0.0f;
+        if (valid) {
+            if (k < 3)
+                v = view[3 * ray + k];
+            else if (k < a.n_dir)
+                v = sun[3 * ray + (k - 3)];
+        }
+        c[r] = v;
+    }
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+template <int PREC, int CL>
+struct Layout {
+    typedef typename FragT<PREC>::T T;
+    // forward fragments
+    static constexpr int D1 = 0;
+    static constexpr int D2 = D1 + 64 * 32;
+    static constexpr int C1 = D2 + 16 * 64;
+    static constexpr int C2 = C1 + 64 * 32;
+    static constexpr int CO = C2 + (CL == 2 ? 64 * 64 : 0);
+    static constexpr int FWD = CO + 16 * 64;
+    // adjoint (transposed) fragments
+    static constexpr int COT = FWD;
+    static constexpr int C2T = COT + 64 * 16;
+    static constexpr int C1T = C2T + (CL == 2 ? 64 * 64 : 0);
+    static constexpr int D2T = C1T + 16 * 64;
+    static constexpr int D1T = D2T + 64 * 16;
+    static constexpr int ALL = D1T + 32 * 64;
+};
+
+template <int PREC, int CL>
+__device__ void build_forward(typename FragT<PREC>::T *lds, const float *w, const MlpArgs &a)
+{
+    typedef Layout<PREC, CL> Lt;
+    build_frag<PREC, 64, 32>(lds + Lt::D1, w, a, M_D1, false);
+    build_frag<PREC, 16, 64>(lds + Lt::D2, w, a, M_D2, false);
+    build_frag<PREC, 64, 32>(lds + Lt::C1, w, a, M_C1, false);
+    if (CL == 2) build_frag<PREC, 64, 64>(lds + Lt::C2, w, a, M_C2, false);
+    build_frag<PREC, 16, 64>(lds + Lt::CO, w, a, M_CO, false);
+}
+
+// Forward of one 16-sample tile; keeps every activation.
+template <int PREC, int CL>
+struct Acts {
+    float x[2][4], h1[4][4], o[1][4], cin[2][4], g1[4][4], g2[4][4], out[1][4];
+};
+
+template <int PREC, int CL>
+__device__ __forceinline__ void forward_tile(const typename FragT<PREC>::T *lds, Acts<PREC, CL> &A)
+{
+    typedef Layout<PREC, CL> Lt;
+    apply<PREC, 64, 32>(lds + Lt::D1, A.x, A.h1);
+    relu(A.h1);
+    apply<PREC, 16, 64>(lds + Lt::D2, A.h1, A.o);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) A.cin[0][r] = A.o[0][r];
+    apply<PREC, 64, 32>(lds + Lt::C1, A.cin, A.g1);
+    relu(A.g1);
+    if constexpr (CL == 2) {
+        apply<PREC, 64, 64>(lds + Lt::C2, A.g1, A.g2);
+        relu(A.g2);
+        apply<PREC, 16, 64>(lds + Lt::CO, A.g2, A.out);
+    } else {
+        apply<PREC, 16, 64>(lds + Lt::CO, A.g1, A.out);
+    }
+}
+
+template <int PREC, int CL, typename FT>
+__global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float *__restrict__ w,
+                                                         const FT *__restrict__ feat,
+                                                         const float *__restrict__ view,
+                                                         const float *__restrict__ sun,
+                                                         const int32_t *__restrict__ ray_id,
+                                                         const int32_t *__restrict__ sidx, int64_t n,
+                                                         const int64_t *__restrict__ n_dev,
+                                                         float *__restrict__ sigma, float *__restrict__ rgb)
+{
+    typedef Layout<PREC, CL> Lt;
+    __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::FWD];
+    build_forward<PREC, CL>(lds, w, a);
+    __syncthreads();
+    const int64_t ne = effective_n(n, n_dev);
+    const int64_t tiles = (ne + 15) / 16;
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); t < tiles; t += nw) {
+        const int64_t s = t * 16 + i;
+        const bool valid = s < ne;
+        const int64_t si = valid ? (sidx ? sidx[s] : s) : 0;
+        Acts<PREC, CL> A;
+        load_features(feat, n, s, valid, a, A.x);
+        const int64_t ray = valid ? ray_id[si] : 0;
+        load_dirs(view, sun, ray, valid, a, A.cin[1]);
+        forward_tile<PREC, CL>(lds, A);
+        if (q == 0 && valid) {
+            sigma[s] = expf(A.o[0][0]);
+            if (a.CO == 3) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]);
+            } else {
+                const float vis = sigmoidf(A.out[0][3]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]) * vis;
+            }
+        }
+    }
+}
+
+// ---- adjoint ----------------------------------------------------------------
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stage rows row0 + (0..16T-1) of a D-layout tile set as [row][sample].
+template <int T>
+__device__ __forceinline__ void stage(float *st, int row0, const float (&v)[T][4])
+{
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) st[(row0 + 16 * t + 4 * q + r) * kStageStride + i] = v[t][r];
+}
+
+// acc[to][ti] += dy[16to.. ][samples] . x[16ti.. ][samples]^T over the 16 staged samples.
+template <int PREC, int TO, int TI>
+__device__ __forceinline__ void dw_accumulate(const float *st, int dy0, int x0, f4 (&acc)[TO][TI])
+{
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4;
+    f4 av[TO], bv[TI];
+#pragma unroll
+    for (int to = 0; to < TO; ++to)
+        av[to] = *reinterpret_cast<const f4 *>(st + (dy0 + 16 * to + i) * kStageStride + 4 * q);
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+        bv[ti] = *reinterpret_cast<const f4 *>(st + (x0 + 16 * ti + i) * kStageStride + 4 * q);
+    if constexpr (PREC == P_F32) {
+#pragma unroll
+        for (int to = 0; to < TO; ++to)
+#pragma unroll
+            for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    acc[to][ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[to][k], bv[ti][k], acc[to][ti], 0, 0, 0);
+    } else {
+        s4 ab[TO], bb[TI];
+#pragma unroll
+        for (int to = 0; to < TO; ++to) {
+            bf4 t4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t4[k] = (__bf16)av[to][k];
+            ab[to] = __builtin_bit_cast(s4, t4);
+        }
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti) {
+            bf4 t4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t4[k] = (__bf16)bv[ti][k];
+            bb[ti] = __builtin_bit_cast(s4, t4);
+        }
+#pragma unroll
+        for (int to = 0; to < TO; ++to)
+#pragma unroll
+            for (int ti = 0; ti < TI; ++ti)
+                acc[to][ti] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab[to], bb[ti], acc[to][ti], 0, 0, 0);
+    }
+}
+
+template <int TO, int TI>
+__device__ __forceinline__ void zero(f4 (&acc)[TO][TI])
+{
+#pragma unroll
+    for (int a = 0; a < TO; ++a)
+#pragma unroll
+        for (int b = 0; b < TI; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Add a dW tile set into the padded block buffer R (row-major, `cols` wide).
+template <int TO, int TI>
+__device__ __forceinline__ void flush(float *R, int base, int cols, const f4 (&acc)[TO][TI], bool first)
+{
+    const int lane = lane_id(), j = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int to = 0; to < TO; ++to)
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float *p = R + base + (16 * to + 4 * q + r) * cols + 16 * ti + j;
+                *p = first ? acc[to][ti][r] : *p + acc[to][ti][r];
+            }
+}
+
+template <typename FT>
+__device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s, bool valid, const MlpArgs &a,
+                                            const float (&dx)[2][4])
+{
+    const int q = lane_id() >> 4;
+    if (!valid) return;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * t + 4 * q + r;
+            if (p < a.n_feat) {
+                const int lvl = p / a.F, f = p - lvl * a.F;
+                dfeat[((int64_t)lvl * ld + s) * a.F + f] = dx[t][r];
+            }
+        }
+}
+
+template <int PREC, int CL, typename FT>
+__global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
+    MlpArgs a, const float *__restrict__ w, const FT *__restrict__ feat, int64_t feat_ld,
+    const float *__restrict__ view, const float *__restrict__ sun, const int32_t *__restrict__ ray_id,
+    const int32_t *__restrict__ sidx, int64_t n, const int64_t *__restrict__ n_dev,
+    const float *__restrict__ dsigma, const float *__restrict__ drgb, float *__restrict__ dfeat,
+    float *__restrict__ partial)
+{
+    typedef Layout<PREC, CL> Lt;
+    __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::ALL];
+    __shared__ __attribute__((aligned(16))) float stage_buf[4 * kStageRows * kStageStride];
+    build_forward<PREC, CL>(lds, w, a);
+    build_frag<PREC, 64, 16>(lds + Lt::COT, w, a, M_CO, true);
+    if (CL == 2) build_frag<PREC, 64, 64>(lds + Lt::C2T, w, a, M_C2, true);
+    build_frag<PREC, 16, 64>(lds + Lt::C1T, w, a, M_C1, true);
+    build_frag<PREC, 64, 16>(lds + Lt::D2T, w, a, M_D2, true);
+    build_frag<PREC, 32, 64>(lds + Lt::D1T, w, a, M_D1, true);
+    __syncthreads();
+
+    const int64_t ne = effective_n(n, n_dev);
+    const int64_t tiles = (ne + 15) / 16;
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+    float *st = stage_buf + wv * kStageRows * kStageStride;
+
+    f4 acc_d1[4][2], acc_d2[1][4], acc_c1[4][2], acc_c2[4][4], acc_co[1][4];
+    zero(acc_d1);
+    zero(acc_d2);
+    zero(acc_c1);
+    zero(acc_c2);
+    zero(acc_co);
+
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + wv; t < tiles; t += nw) {
+        const int64_t s = t * 16 + i;
+        const bool valid = s < ne;
+        const int64_t si = valid ? (sidx ? sidx[s] : s) : 0;
+        Acts<PREC, CL> A;
+        load_features(feat, feat_ld, si, valid, a, A.x);
+        const int64_t ray = valid ? ray_id[si] : 0;
+        load_dirs(view, sun, ray, valid, a, A.cin[1]);
+        forward_tile<PREC, CL>(lds, A);
+
+        // output activation adjoint (rows 0..3 live in lane group 0)
+        float dout[1][4] = {{0.f, 0.f, 0.f, 0.f}};
+        float dsig = 0.0f;
+        if (q == 0 && valid) {
+            dsig = dsigma[si];
+            const float d0 = drgb[3 * si], d1 = drgb[3 * si + 1], d2 = drgb[3 * si + 2];
+            const float dr[3] = {d0, d1, d2};
+            if (a.CO == 3) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float y = sigmoidf(A.out[0][c]);
+                    dout[0][c] = dr[c] * y * (1.0f - y);
+                }
+            } else {
+                const float vis = sigmoidf(A.out[0][3]);
+                float dvis = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float alb = sigmoidf(A.out[0][c]);
+                    dout[0][c] = dr[c] * vis * alb * (1.0f - alb);
+                    dvis += dr[c] * alb;
+                }
+                dout[0][3] = dvis * vis * (1.0f - vis);
+            }
+        }
+        float dg2[4][4], dg1[4][4], dob[1][4], dh1[4][4], dx[2][4];
+        if constexpr (CL == 2) {
+            apply<PREC, 64, 16>(lds + Lt::COT, dout, dg2);
+            relu_mask(dg2, A.g2);
+            apply<PREC, 64, 64>(lds + Lt::C2T, dg2, dg1);
+        } else {
+            apply<PREC, 64, 16>(lds + Lt::COT, dout, dg1);
+        }
+        relu_mask(dg1, A.g1);
+        apply<PREC, 16, 64>(lds + Lt::C1T, dg1, dob);
+        if (q == 0) dob[0][0] = dsig * expf(A.o[0][0]);   // sigma = exp(o_0)
+        apply<PREC, 64, 16>(lds + Lt::D2T, dob, dh1);
+        relu_mask(dh1, A.h1);
+        apply<PREC, 32, 64>(lds + Lt::D1T, dh1, dx);
+        store_dfeat<FT>(dfeat, n, s, valid, a, dx);
+
+        // weight gradients: stage (dy, x) pairs as [row][sample], MFMA over samples
+        stage<1>(st, 0, dout);
+        stage<4>(st, 16, CL == 2 ? A.g2 : A.g1);
+        wave_sync();
+        dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_co);
+        wave_sync();
+        if constexpr (CL == 2) {
+            stage<4>(st, 0, dg2);
+            stage<4>(st, 64, A.g1);
+            wave_sync();
+            dw_accumulate<PREC, 4, 4>(st, 0, 64, acc_c2);
+            wave_sync();
+        }
+        stage<4>(st, 0, dg1);
+        stage<2>(st, 64, A.cin);
+        wave_sync();
+        dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_c1);
+        wave_sync();
+        stage<1>(st, 0, dob);
+        stage<4>(st, 16, A.h1);
+        wave_sync();
+        dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_d2);
+        wave_sync();
+        stage<4>(st, 0, dh1);
+        stage<2>(st, 64, A.x);
+        wave_sync();
+        dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_d1);
+        wave_sync();
+    }
+
+    // block reduction in a fixed wave order into the padded buffer R
+    // (D1 [64][32] | D2 [16][64] | C1 [64][32] | C2 [64][64] | CO [16][64])
+    constexpr int RD1 = 0, RD2 = 2048, RC1 = 3072, RC2 = 5120, RCO = 5120 + (CL == 2 ? 4096 : 0);
+    float *R = stage_buf;
+    static_assert(RCO + 1024 <= 4 * kStageRows * kStageStride, "reduction buffer");
+    __syncthreads();
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (wv == w) {
+            flush(R, RD1, 32, acc_d1, w == 0);
+            flush(R, RD2, 64, acc_d2, w == 0);
+            flush(R, RC1, 32, acc_c1, w == 0);
+            if (CL == 2) flush(R, RC2, 64, acc_c2, w == 0);
+            flush(R, RCO, 64, acc_co, w == 0);
+        }
+        __syncthreads();
+    }
+    // unpadded packed order into this block's partial row
+    float *out = partial + (int64_t)blockIdx.x * a.P;
+    for (int64_t p = threadIdx.x; p < a.P; p += kBlock) {
+        float v;
+        if (p < a.off[1]) {
+            v = R[RD1 + p];
+        } else if (p < a.off[2]) {
+            v = R[RD2 + (p - a.off[1])];
+        } else if (p < a.off[2] + 64 * a.cin_real) {
+            const int e = (int)(p - a.off[2]), h = e / a.cin_real, c = e - h * a.cin_real;
+            const int col = c < 15 ? c + 1 : 16 + (c - 15);
+            v = R[RC1 + h * 32 + col];
+        } else if (CL == 2 && p < a.off[4]) {
+            v = R[RC2 + (p - a.off[3])];
+        } else {
+            v = R[RCO + (p - a.off[4])];
+        }
+        out[p] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float *__restrict__ partial, int nb,
+                                                              int64_t P, float *__restrict__ dW)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * P + p];
+        dW[p] += s;
+    }
+}
+
+int make_args(const snake_mlp_desc *m, MlpArgs &a, const char *fn)
+{
+    SNAKE_REQUIRE(m != nullptr, SNAKE_ERR_NULL, "%s: MLP descriptor is NULL", fn);
+    SNAKE_REQUIRE(m->n_levels >= 1 && (m->n_features == 1 || m->n_features == 2 || m->n_features == 4),
+                  SNAKE_ERR_INVALID_ARG, "%s: bad encoding shape L=%d F=%d", fn, m->n_levels, m->n_features);
+    SNAKE_REQUIRE(m->n_levels * m->n_features <= 32, SNAKE_ERR_INVALID_ARG, "%s: L*F = %d > 32", fn,
+                  m->n_levels * m->n_features);
+    SNAKE_REQUIRE(m->n_dir == 3 || m->n_dir == 6, SNAKE_ERR_INVALID_ARG, "%s: n_dir = %d not 3 or 6", fn,
+                  m->n_dir);
+    SNAKE_REQUIRE(m->colour_layers == 1 || m->colour_layers == 2, SNAKE_ERR_UNSUPPORTED,
+                  "%s: colour_layers = %d not 1 or 2", fn, m->colour_layers);
+    SNAKE_REQUIRE(m->colour_out == 3 || m->colour_out == 4, SNAKE_ERR_INVALID_ARG,
+                  "%s: colour_out = %d not 3 or 4", fn, m->colour_out);
+    SNAKE_REQUIRE(m->precision == SNAKE_F32 || m->precision == SNAKE_BF16, SNAKE_ERR_INVALID_ARG,
+                  "%s: bad precision %d", fn, m->precision);
+    SNAKE_REQUIRE(m->feat_dtype == SNAKE_F32 || m->feat_dtype == SNAKE_BF16, SNAKE_ERR_INVALID_ARG,
+                  "%s: bad feat_dtype %d", fn, m->feat_dtype);
+    a.L = m->n_levels;
+    a.F = m->n_features;
+    a.n_feat = a.L * a.F;
+    a.n_dir = m->n_dir;
+    a.CL = m->colour_layers;
+    a.CO = m->colour_out;
+    a.cin_real = 15 + a.n_dir;
+    int64_t o = 0;
+    a.off[0] = o;
+    o += 64 * 32;
+    a.off[1] = o;
+    o += 16 * 64;
+    a.off[2] = o;
+    o += 64 * a.cin_real;
+    a.off[3] = o;
+    if (a.CL == 2) o += 64 * 64;
+    a.off[4] = o;
+    o += a.CO * 64;
+    a.P = o;
+    return SNAKE_OK;
+}
+
+template <int PREC, int CL, typename FT>
+void launch_fwd(const MlpArgs &a, const float *w, const void *feat, const float *view, const float *sun,
+                const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev, float *sigma,
+                float *rgb, hipStream_t st)
+{
+    const unsigned grid = grid_for((n + 15) / 16 * 64, kBlock, 4);
+    mlp_fwd_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun, ray_id,
+                                                          sidx, n, n_dev, sigma, rgb);
+}
+
+template <int PREC, int CL, typename FT>
+void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat_ld, const float *view,
+                const float *sun, const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev,
+                const float *dsigma, const float *drgb, float *dW, float *dfeat, float *partial, hipStream_t st)
+{
+    unsigned grid = grid_for((n + 15) / 16 * 64, kBlock, PREC == P_BF16 ? 2 : 1);
+    if (grid > (unsigned)kMaxBwdBlocks) grid = kMaxBwdBlocks;
+    mlp_bwd_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view, sun,
+                                                          ray_id, sidx, n, n_dev, dsigma, drgb, dfeat, partial);
+    reduce_partials_kernel<<<(unsigned)((a.P + 255) / 256), 256, 0, st>>>(partial, (int)grid, a.P, dW);
+}
+
+}  // namespace
+}  // namespace snake
+
+using namespace snake;
+
+extern "C" {
+
+int64_t snake_mlp_param_count(const snake_mlp_desc *m)
+{
+    MlpArgs a;
+    if (make_args(m, a, __func__)) return -1;
+    return a.P;
+}
+
+size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m)
+{
+    MlpArgs a;
+    if (make_args(m, a, __func__)) return 0;
+    return (size_t)kMaxBwdBlocks * (size_t)a.P * sizeof(float);
+}
+
+int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat, const float *view,
+                  const float *sun, const int32_t *ray_id, const int32_t *sample_idx, int64_t n,
+                  const int64_t *n_dev, float *sigma, float *rgb, snake_stream_t stream)
+{
+    MlpArgs a;
+    int rc = make_args(m, a, __func__);
+    if (rc) return rc;
+    SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_mlp_fwd: n < 0");
+    if (n == 0) return SNAKE_OK;
+    SNAKE_NOT_NULL(weights);
+    SNAKE_NOT_NULL(feat);
+    SNAKE_NOT_NULL(view);
+    SNAKE_NOT_NULL(ray_id);
+    SNAKE_NOT_NULL(sigma);
+    SNAKE_NOT_NULL(rgb);
+    SNAKE_REQUIRE(a.n_dir == 3 || sun != nullptr, SNAKE_ERR_NULL, "snake_mlp_fwd: sun is NULL with n_dir = 6");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool bf = m->precision == SNAKE_BF16, fb = m->feat_dtype == SNAKE_BF16;
+#define SNAKE_MLP_FWD(P, C)                                                                                  \
+    if (fb)                                                                                                  \
+        launch_fwd<P, C, __hip_bfloat16>(a, weights, feat, view, sun, ray_id, sample_idx, n, n_dev, sigma, rgb, \
+                                         st);                                                                \
+    else                                                                                                     \
+        launch_fwd<P, C, float>(a, weights, feat, view, sun, ray_id, sample_idx, n, n_dev, sigma, rgb, st)
+    if (bf) {
+        if (a.CL == 2) {
+            SNAKE_MLP_FWD(P_BF16, 2);
+        } else {
+            SNAKE_MLP_FWD(P_BF16, 1);
+        }
+    } else {
+        if (a.CL == 2) {
+            SNAKE_MLP_FWD(P_F32, 2);
+        } else {
+            SNAKE_MLP_FWD(P_F32, 1);
+        }
+    }
+#undef SNAKE_MLP_FWD
+    return launch_status(__func__);
+}
+
+int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat, int64_t feat_ld,
+                  const float *view, const float *sun, const int32_t *ray_id, const int32_t *sample_idx, int64_t n,
+                  const int64_t *n_dev, const float *dsigma, const float *drgb, float *dW, float *dfeat,
+                  void *workspace, size_t workspace_bytes, snake_stream_t stream)
+{
+    MlpArgs a;
+    int rc = make_args(m, a, __func__);
+    if (rc) return rc;
+    SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_mlp_bwd: n < 0");
+    if (n == 0) return SNAKE_OK;
+    SNAKE_REQUIRE(sample_idx != nullptr || feat_ld >= n, SNAKE_ERR_INVALID_ARG,
+                  "snake_mlp_bwd: feat_ld = %lld < n = %lld", (long long)feat_ld, (long long)n);
+    SNAKE_NOT_NULL(weights);
+    SNAKE_NOT_NULL(feat);
+    SNAKE_NOT_NULL(view);
+    SNAKE_NOT_NULL(ray_id);
+    SNAKE_NOT_NULL(dsigma);
+    SNAKE_NOT_NULL(drgb);
+    SNAKE_NOT_NULL(dW);
+    SNAKE_NOT_NULL(dfeat);
+    SNAKE_REQUIRE(a.n_dir == 3 || sun != nullptr, SNAKE_ERR_NULL, "snake_mlp_bwd: sun is NULL with n_dir = 6");
+    const size_t need = (size_t)kMaxBwdBlocks * (size_t)a.P * sizeof(float);
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= need, SNAKE_ERR_WORKSPACE,
+                  "snake_mlp_bwd: workspace needs %zu bytes", need);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    float *partial = static_cast<float *>(workspace);
+    const bool bf = m->precision == SNAKE_BF16, fb = m->feat_dtype == SNAKE_BF16;
+#define SNAKE_MLP_BWD(P, C)                                                                                     \
+    if (fb)                                                                                                     \
+        launch_bwd<P, C, __hip_bfloat16>(a, weights, feat, feat_ld, view, sun, ray_id, sample_idx, n, n_dev,      \
+                                         dsigma, drgb, dW, dfeat, partial, st);                                 \
+    else                                                                                                        \
+        launch_bwd<P, C, float>(a, weights, feat, feat_ld, view, sun, ray_id, sample_idx, n, n_dev, dsigma, drgb, \
+                                dW, dfeat, partial, st)
+    if (bf) {
+        if (a.CL == 2) {
+            SNAKE_MLP_BWD(P_BF16, 2);
+        } else {
+            SNAKE_MLP_BWD(P_BF16, 1);
+        }
+    } else {
+        if (a.CL == 2) {
+            SNAKE_MLP_BWD(P_F32, 2);
+        } else {
+            SNAKE_MLP_BWD(P_F32, 1);
+        }
+    }
+#undef SNAKE_MLP_BWD
+    return launch_status(__func__);
+}
+
+}  // extern "C"

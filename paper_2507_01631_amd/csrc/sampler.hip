@@ -1,0 +1,465 @@
+// Segmented sampler: per-NeRF-tile near/far, per-segment uniform intervals,
+// count -> exclusive scan -> fill packing (Sec. 4.5, Sec. 4.6; tile-local
+// [0,1]^3 frame of Sec. 4.1-4.2).
+//
+// Bit-exactness: every FP64 and FP32 operation below is a single IEEE
+// operation at a stated rounding point, so FMA contraction is off for the
+// whole file.
+#pragma clang fp contract(off)
+
+#include <math.h>
+
+#include "common.h"
+
+namespace snake {
+namespace {
+
+constexpr int kMaxTiles = 16;
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;  // counts per scan block
+
+struct Boxes {
+    double b[kMaxTiles][6];
+    int K;
+    int use_band;
+    double z_lo, z_hi;
+};
+
+struct Seg {
+    double tn, tf;
+    int tile;
+    int n;
+};
+
+// FP64 slab test; hit iff t_far > t_near after clamping t_near at 0.  An
+// axis-parallel component is inside when lo <= o < hi.
+__device__ __forceinline__ bool slab(const double o[3], const double d[3], const double lo[3],
+                                     const double hi[3], double &tn, double &tf)
+{
+    double t_near = -INFINITY, t_far = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (o[a] < lo[a] || o[a] >= hi[a]) return false;
+            continue;
+        }
+        double u = (lo[a] - o[a]) / d[a];
+        double v = (hi[a] - o[a]) / d[a];
+        double mn = u < v ? u : v;
+        double mx = u < v ? v : u;
+        t_near = mn > t_near ? mn : t_near;
+        t_far = mx < t_far ? mx : t_far;
+    }
+    t_near = t_near < 0.0 ? 0.0 : t_near;
+    if (!(t_far > t_near)) return false;
+    tn = t_near;
+    tf = t_far;
+    return true;
+}
+
+// Hit segments of one ray in entry order with their sample counts (sum S_r
+// when S_r > 0).  Returns the number of segments.
+template <int KMAX>
+__device__ int ray_segments(const double o[3], const double d[3], const Boxes &bx, int S_r,
+                            Seg *seg)
+{
+    int ns = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < bx.K) {
+            double lo[3] = {bx.b[k][0], bx.b[k][1], bx.b[k][2]};
+            double hi[3] = {bx.b[k][3], bx.b[k][4], bx.b[k][5]};
+            if (bx.use_band) {
+                lo[2] = bx.z_lo > lo[2] ? bx.z_lo : lo[2];
+                hi[2] = bx.z_hi < hi[2] ? bx.z_hi : hi[2];
+            }
+            double tn, tf;
+            if (slab(o, d, lo, hi, tn, tf)) {
+                // insert keeping (tn, tile) order
+                int j = ns;
+                while (j > 0 && seg[j - 1].tn > tn) {
+                    seg[j] = seg[j - 1];
+                    --j;
+                }
+                seg[j].tn = tn;
+                seg[j].tf = tf;
+                seg[j].tile = k;
+                seg[j].n = 0;
+                ++ns;
+            }
+        }
+    }
+    if (ns == 0 || S_r <= 0) return ns;
+    const int base = S_r >= ns ? 1 : 0;
+    const int extra = S_r - base * ns;
+    double total = 0.0;
+    for (int i = 0; i < ns; ++i) total += seg[i].tf - seg[i].tn;
+    double cum = 0.0;
+    int prev = 0;
+    for (int i = 0; i < ns; ++i) {
+        cum += seg[i].tf - seg[i].tn;
+        int b = (i == ns - 1) ? extra : (int)rint((double)extra * cum / total);
+        seg[i].n = base + b - prev;
+        prev = b;
+    }
+    return ns;
+}
+
+__device__ __forceinline__ void load_ray(const double *ro, const double *rd, int64_t r, double o[3],
+                                         double d[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[a] = ro[3 * r + a];
+        d[a] = rd[3 * r + a];
+    }
+}
+
+// ---- count ----------------------------------------------------------------
+template <int KMAX>
+__global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ ro,
+                                                    const double *__restrict__ rd, int R, Boxes bx,
+                                                    const int32_t *__restrict__ spr, int S,
+                                                    const int32_t *__restrict__ max_count,
+                                                    int32_t *__restrict__ counts,
+                                                    float *__restrict__ view)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        double o[3], d[3];
+        load_ray(ro, rd, r, o, d);
+        Seg seg[KMAX];
+        int S_r = spr ? spr[r] : S;
+        int ns = ray_segments<KMAX>(o, d, bx, S_r, seg);
+        int c = 0;
+        for (int i = 0; i < ns; ++i) c += seg[i].n;
+        if (max_count) {
+            int mc = max_count[r];
+            mc = mc < 0 ? 0 : mc;
+            c = mc < c ? mc : c;
+        }
+        counts[r] = c;
+        if (view) {
+            double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) view[3 * (int64_t)r + a] = (float)(d[a] / len);
+        }
+    }
+}
+
+// ---- exclusive scan of int32 counts ---------------------------------------
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *total, int64_t *sh)
+{
+    // 256 threads = 4 waves; sh holds 4 wave totals
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        int64_t u = __shfl_up(inc, dd, 64);
+        if (l >= dd) inc += u;
+    }
+    if (l == 63) sh[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kScanBlock / 64; ++i) {
+        if (i < w) before += sh[i];
+        all += sh[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_partial_kernel(const int32_t *__restrict__ counts,
+                                                                  int R, int64_t *__restrict__ bsum)
+{
+    __shared__ int64_t sh[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < kScanItems; ++e)
+        if (base + e < R) s += counts[base + e];
+    int64_t tot;
+    block_exclusive_scan(s, &tot, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_top_kernel(int64_t *__restrict__ bsum, int nb,
+                                                              int64_t cap, int64_t *__restrict__ n_out,
+                                                              unsigned int *__restrict__ err)
+{
+    __shared__ int64_t sh[4];
+    int64_t carry = 0;
+    for (int base = 0; base < nb; base += kScanBlock) {
+        int i = base + threadIdx.x;
+        int64_t v = i < nb ? bsum[i] : 0;
+        int64_t tot;
+        int64_t ex = block_exclusive_scan(v, &tot, sh);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (n_out) *n_out = carry;
+        if (carry > cap && err) atomicOr(err, (unsigned)SNAKE_DEVERR_CAPACITY);
+    }
+}
+
+// start[r * stride] = exclusive prefix; count_dst[r * stride] = count (if given)
+__global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const int32_t *__restrict__ counts, int R,
+                                                                const int64_t *__restrict__ bsum,
+                                                                int32_t *__restrict__ start, int stride,
+                                                                int32_t *__restrict__ count_dst)
+{
+    __shared__ int64_t sh[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int32_t c[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < kScanItems; ++e) {
+        c[e] = (base + e < R) ? counts[base + e] : 0;
+        s += c[e];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(s, &tot, sh) + bsum[blockIdx.x];
+#pragma unroll
+    for (int e = 0; e < kScanItems; ++e) {
+        if (base + e < R) {
+            start[(base + e) * stride] = (int32_t)ex;
+            if (count_dst) count_dst[(base + e) * stride] = c[e];
+        }
+        ex += c[e];
+    }
+}
+
+// ---- fill: one wavefront per ray, one lane per sample -----------------------
+template <int KMAX>
+__global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro,
+                                                   const double *__restrict__ rd, int R, Boxes bx,
+                                                   const int32_t *__restrict__ spr, int S,
+                                                   const int32_t *__restrict__ info, int64_t cap,
+                                                   float *__restrict__ t0, float *__restrict__ t1,
+                                                   float *__restrict__ pos, int32_t *__restrict__ ray_id,
+                                                   uint8_t *__restrict__ tile_id)
+{
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < R; r += waves) {
+        const int64_t start = info[2 * (int64_t)r];
+        const int count = info[2 * (int64_t)r + 1];
+        if (count == 0) continue;
+        double o[3], d[3];
+        load_ray(ro, rd, r, o, d);
+        Seg seg[KMAX];
+        int S_r = spr ? spr[r] : S;
+        int ns = ray_segments<KMAX>(o, d, bx, S_r, seg);
+        for (int j = lane; j < count; j += 64) {
+            // segment of packed sample j
+            int s = 0, before = 0;
+            while (s < ns - 1 && j >= before + seg[s].n) {
+                before += seg[s].n;
+                ++s;
+            }
+            const int k = j - before, n = seg[s].n;
+            const double *b = bx.b[seg[s].tile];
+            float tn = (float)seg[s].tn, tf = (float)seg[s].tf;
+            float step = (tf - tn) / (float)n;
+            float ta = tn + (float)k * step;
+            float tb = (k + 1 == n) ? tf : tn + (float)(k + 1) * step;
+            float m = 0.5f * (ta + tb);
+            const int64_t out = start + j;
+            if (out >= cap) continue;
+            t0[out] = ta;
+            t1[out] = tb;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double ext = b[3 + a] - b[a];
+                float ol = (float)((o[a] - b[a]) / ext);
+                float dl = (float)(d[a] / ext);
+                float x = ol + m * dl;
+                x = x < 0.0f ? 0.0f : x;
+                x = x > 1.0f ? 1.0f : x;
+                pos[3 * out + a] = x;
+            }
+            ray_id[out] = r;
+            if (tile_id) tile_id[out] = (uint8_t)seg[s].tile;
+        }
+    }
+}
+
+// ---- early-stop index list --------------------------------------------------
+__global__ __launch_bounds__(256) void alive_count_kernel(const int32_t *__restrict__ info,
+                                                          const int32_t *__restrict__ n_alive, int R,
+                                                          int32_t *__restrict__ counts)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        int c = info[2 * (int64_t)r + 1];
+        int a = n_alive[r];
+        a = a < 0 ? 0 : a;
+        counts[r] = a < c ? a : c;
+    }
+}
+
+__global__ __launch_bounds__(256) void alive_fill_kernel(const int32_t *__restrict__ info,
+                                                         const int32_t *__restrict__ counts,
+                                                         const int32_t *__restrict__ offs, int R,
+                                                         int64_t cap, int32_t *__restrict__ idx_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < R; r += waves) {
+        const int32_t start = info[2 * (int64_t)r];
+        const int c = counts[r];
+        const int64_t o = offs[r];
+        for (int j = lane; j < c; j += 64)
+            if (o + j < cap) idx_out[o + j] = start + j;
+    }
+}
+
+__global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
+
+// workspace: counts[R] | offs[R] | bsum[nb]
+struct ScanWs {
+    int32_t *counts, *offs;
+    int64_t *bsum;
+    int nb;
+};
+
+size_t scan_ws_bytes(int32_t R)
+{
+    size_t r = (size_t)(R > 0 ? R : 1);
+    size_t nb = (r + kScanTile - 1) / kScanTile;
+    return 2 * ((r * 4 + 255) / 256 * 256) + nb * 8 + 256;
+}
+
+ScanWs carve(void *ws, int32_t R)
+{
+    size_t r = (size_t)(R > 0 ? R : 1);
+    size_t a = (r * 4 + 255) / 256 * 256;
+    char *p = static_cast<char *>(ws);
+    ScanWs s;
+    s.counts = reinterpret_cast<int32_t *>(p);
+    s.offs = reinterpret_cast<int32_t *>(p + a);
+    s.bsum = reinterpret_cast<int64_t *>(p + 2 * a);
+    s.nb = (int)((r + kScanTile - 1) / kScanTile);
+    return s;
+}
+
+void launch_scan(const ScanWs &w, int R, int32_t *start, int stride, int32_t *count_dst, int64_t cap,
+                 int64_t *n_out, hipStream_t st)
+{
+    unsigned int *err = device_error_word();
+    scan_partial_kernel<<<w.nb, kScanBlock, 0, st>>>(w.counts, R, w.bsum);
+    scan_top_kernel<<<1, kScanBlock, 0, st>>>(w.bsum, w.nb, cap, n_out, err);
+    scan_apply_kernel<<<w.nb, kScanBlock, 0, st>>>(w.counts, R, w.bsum, start, stride, count_dst);
+}
+
+}  // namespace
+}  // namespace snake
+
+using namespace snake;
+
+extern "C" {
+
+size_t snake_sample_workspace_bytes(int32_t R) { return scan_ws_bytes(R); }
+
+int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R, const double *boxes,
+                           int32_t K, const double *zband, const int32_t *samples_per_ray, int32_t S,
+                           const int32_t *max_count, int32_t *packed_info, float *t0, float *t1,
+                           float *pos, int32_t *ray_id, uint8_t *tile_id, float *view, int64_t cap,
+                           int64_t *n_out, void *workspace, size_t workspace_bytes,
+                           snake_stream_t stream)
+{
+    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "snake_sample_segmented: R = %d < 0", R);
+    SNAKE_REQUIRE(K >= 1 && K <= kMaxTiles, SNAKE_ERR_INVALID_ARG,
+                  "snake_sample_segmented: K = %d not in [1, %d]", K, kMaxTiles);
+    SNAKE_REQUIRE(K == 1 || tile_id != nullptr, SNAKE_ERR_NULL,
+                  "snake_sample_segmented: tile_id is NULL with K = %d > 1", K);
+    SNAKE_REQUIRE(samples_per_ray != nullptr || S >= 0, SNAKE_ERR_INVALID_ARG,
+                  "snake_sample_segmented: S = %d < 0", S);
+    SNAKE_REQUIRE(cap >= 0 && cap <= INT32_MAX, SNAKE_ERR_INVALID_ARG,
+                  "snake_sample_segmented: cap = %lld not in [0, 2^31)", (long long)cap);
+    SNAKE_NOT_NULL(boxes);
+    SNAKE_NOT_NULL(n_out);
+    if (R > 0) {
+        SNAKE_NOT_NULL(rays_o);
+        SNAKE_NOT_NULL(rays_d);
+        SNAKE_NOT_NULL(packed_info);
+    }
+    if (cap > 0) {
+        SNAKE_NOT_NULL(t0);
+        SNAKE_NOT_NULL(t1);
+        SNAKE_NOT_NULL(pos);
+        SNAKE_NOT_NULL(ray_id);
+    }
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= scan_ws_bytes(R), SNAKE_ERR_WORKSPACE,
+                  "snake_sample_segmented: workspace needs %zu bytes", scan_ws_bytes(R));
+    SNAKE_ALIGNED(workspace, 256);
+    Boxes bx{};
+    bx.K = K;
+    for (int k = 0; k < K; ++k) {
+        for (int a = 0; a < 6; ++a) bx.b[k][a] = boxes[6 * k + a];
+        for (int a = 0; a < 3; ++a)
+            SNAKE_REQUIRE(bx.b[k][3 + a] > bx.b[k][a], SNAKE_ERR_INVALID_ARG,
+                          "snake_sample_segmented: box %d is empty on axis %d", k, a);
+    }
+    if (zband) {
+        SNAKE_REQUIRE(zband[1] > zband[0], SNAKE_ERR_INVALID_ARG,
+                      "snake_sample_segmented: empty altitude band");
+        bx.use_band = 1;
+        bx.z_lo = zband[0];
+        bx.z_hi = zband[1];
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (R == 0) {
+        set_i64_kernel<<<1, 1, 0, st>>>(n_out, 0);
+        return launch_status(__func__);
+    }
+    ScanWs w = carve(workspace, R);
+    const unsigned gc = grid_for(R, 256, 8), gf = grid_for((int64_t)R * 64, 256, 16);
+#define SNAKE_SAMPLER_LAUNCH(KM)                                                                   \
+    count_kernel<KM><<<gc, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, max_count,     \
+                                         w.counts, view);                                        \
+    launch_scan(w, R, packed_info, 2, packed_info + 1, cap, n_out, st);                          \
+    fill_kernel<KM><<<gf, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, packed_info,  \
+                                        cap, t0, t1, pos, ray_id, tile_id)
+    if (K == 1) {
+        SNAKE_SAMPLER_LAUNCH(1);
+    } else if (K <= 4) {
+        SNAKE_SAMPLER_LAUNCH(4);
+    } else {
+        SNAKE_SAMPLER_LAUNCH(kMaxTiles);
+    }
+#undef SNAKE_SAMPLER_LAUNCH
+    return launch_status(__func__);
+}
+
+int snake_pack_alive(const int32_t *packed_info, const int32_t *n_alive, int32_t R, int32_t *idx_out,
+                     int64_t cap, int64_t *n_out, void *workspace, size_t workspace_bytes,
+                     snake_stream_t stream)
+{
+    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "snake_pack_alive: R = %d < 0", R);
+    SNAKE_REQUIRE(cap >= 0 && cap <= INT32_MAX, SNAKE_ERR_INVALID_ARG, "snake_pack_alive: bad cap");
+    SNAKE_NOT_NULL(n_out);
+    if (R > 0) {
+        SNAKE_NOT_NULL(packed_info);
+        SNAKE_NOT_NULL(n_alive);
+    }
+    if (cap > 0) SNAKE_NOT_NULL(idx_out);
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= scan_ws_bytes(R), SNAKE_ERR_WORKSPACE,
+                  "snake_pack_alive: workspace needs %zu bytes", scan_ws_bytes(R));
+    SNAKE_ALIGNED(workspace, 256);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (R == 0) {
+        set_i64_kernel<<<1, 1, 0, st>>>(n_out, 0);
+        return launch_status(__func__);
+    }
+    ScanWs w = carve(workspace, R);
+    alive_count_kernel<<<grid_for(R, 256, 8), 256, 0, st>>>(packed_info, n_alive, R, w.counts);
+    launch_scan(w, R, w.offs, 1, nullptr, cap, n_out, st);
+    alive_fill_kernel<<<grid_for((int64_t)R * 64, 256, 16), 256, 0, st>>>(packed_info, w.counts, w.offs,
+                                                                         R, cap, idx_out);
+    return launch_status(__func__);
+}
+
+}  // extern "C"

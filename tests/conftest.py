@@ -13,6 +13,13 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long-running CPU test")
 
 
+def pytest_runtest_setup(item):
+    if "gpu" in item.keywords:
+        import torch
+        if not torch.cuda.is_available():
+            pytest.skip("needs a GPU")
+
+
 @pytest.fixture(scope="session")
 def orc():
     import oracle

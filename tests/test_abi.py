@@ -1,0 +1,144 @@
+"""The C-ABI library loads and exports every entry point include/snake.h
+declares; host-side argument checks reject bad calls before any launch.  CPU
+only: no call here reaches the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snake.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(snake_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_01631_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsnake.so is not built (python -m paper_2507_01631_amd.build)")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(L):
+    decl = _declared()
+    assert len(decl) >= 15
+    so = ctypes.CDLL(L.LIB_PATH)
+    for name in decl:
+        assert hasattr(so, name), name
+    assert sorted(L.EXPORTS) == decl
+
+
+def test_abi_version_and_error_string(L):
+    assert L.snake_abi_version() == 1
+    assert isinstance(L.snake_last_error(), str)
+
+
+def test_struct_layouts_match_header(L):
+    # two int32 + int32 + int32 + uint32 + 32 int32
+    assert ctypes.sizeof(L.GridDesc) == 4 * 5 + 4 * 32
+    assert ctypes.sizeof(L.MlpDesc) == 4 * 7
+
+
+def test_param_count_matches_oracle(L, orc):
+    for m in (synth.tiny_tile(n_rays=4).mlp,
+              synth.MlpConfig(feat_real=32, n_dir=6, colour_layers=2, colour_out=4)):
+        d = L.mlp_desc(8, 2, m.n_dir, m.colour_layers, m.colour_out)
+        assert L.snake_mlp_param_count(d) == orc.mlp_param_count(m)
+
+
+def test_level_resolutions_match_oracle(orc):
+    from paper_2507_01631_amd import level_resolutions
+    for Lv, lo, hi in [(8, 16, 256), (16, 16, 2048), (12, 8, 4096), (1, 32, 32)]:
+        assert list(orc.level_resolutions(Lv, lo, hi)) == level_resolutions(Lv, lo, hi)
+
+
+def test_workspace_queries(L):
+    assert L.snake_sample_workspace_bytes(4096) >= 2 * 4096 * 4
+    d = L.mlp_desc(16, 2, 6, 2, 4)
+    assert L.snake_mlp_bwd_workspace_bytes(d) >= 4 * L.snake_mlp_param_count(d)
+
+
+def _raw(L):
+    return L.lib()
+
+
+def test_host_side_argument_errors(L):
+    so = _raw(L)
+    SNAKE_ERR_INVALID_ARG, SNAKE_ERR_NULL, SNAKE_ERR_UNSUPPORTED = -1, -2, -4
+    # grid descriptor checks
+    g = L.grid_desc([16, 32], 3, 14)
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), None, None, None, None, 10, None, None, None,
+                                 None) == SNAKE_ERR_UNSUPPORTED
+    assert "n_features" in L.snake_last_error()
+    g = L.grid_desc([16, 32], 2, 30)
+    assert so.snake_hashgrid_bwd(ctypes.byref(g), None, None, None, 10, None, None, None,
+                                 None) == SNAKE_ERR_INVALID_ARG
+    g = L.grid_desc([16, 0], 2, 14)
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), None, None, None, None, 10, None, None, None,
+                                 None) == SNAKE_ERR_INVALID_ARG
+    g = L.grid_desc([16, 32], 2, 14)
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), None, None, None, None, 10, None, None, None,
+                                 None) == SNAKE_ERR_NULL
+    assert so.snake_hashgrid_fwd(None, None, None, None, None, 10, None, None, None, None) == SNAKE_ERR_NULL
+    # MLP descriptor checks
+    m = L.mlp_desc(8, 2, 5, 1, 3)
+    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, None, 16, None, None, None,
+                            None) == SNAKE_ERR_INVALID_ARG
+    m = L.mlp_desc(8, 2, 3, 3, 3)
+    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, None, 16, None, None, None,
+                            None) == SNAKE_ERR_UNSUPPORTED
+    m = L.mlp_desc(17, 2, 3, 1, 3)
+    assert so.snake_mlp_param_count(ctypes.byref(m)) == -1
+    m = L.mlp_desc(8, 2, 6, 2, 4)
+    assert so.snake_mlp_bwd(ctypes.byref(m), None, None, 0, None, None, None, None, 16, None, None,
+                            None, None, None, None, 0, None) == SNAKE_ERR_INVALID_ARG
+    # sampler checks (boxes are host memory)
+    boxes = np.array([[0, 0, 0, 1, 1, 1]], np.float64)
+    assert so.snake_sample_segmented(None, None, 4, boxes.ctypes.data, 0, None, None, 8, None, None,
+                                     None, None, None, None, None, None, 32, None, None, 0,
+                                     None) == SNAKE_ERR_INVALID_ARG
+    assert so.snake_sample_segmented(None, None, 4, boxes.ctypes.data, 1, None, None, 8, None, None,
+                                     None, None, None, None, None, None, 32, None, None, 0,
+                                     None) == SNAKE_ERR_NULL
+    bad = np.array([[0, 0, 0, 1, 0, 1]], np.float64)
+    fake = ctypes.c_void_p(256)
+    ws = ctypes.c_void_p(4096)
+    assert so.snake_sample_segmented(fake, fake, 4, bad.ctypes.data, 1, None, None, 8, None, fake, fake,
+                                     fake, fake, fake, None, None, 32, fake, ws, 1 << 20,
+                                     None) == SNAKE_ERR_INVALID_ARG
+    assert "empty" in L.snake_last_error()
+    assert so.snake_sample_segmented(fake, fake, 4, boxes.ctypes.data, 1, None, None, 8, None, fake,
+                                     fake, fake, fake, fake, None, None, 32, fake, ws, 16,
+                                     None) == -6
+    # composite / adam checks
+    assert so.snake_composite_fwd(None, None, None, None, None, 4, ctypes.c_float(1.5), None,
+                                  ctypes.c_float(0), None, None, None, None, None,
+                                  None) == SNAKE_ERR_INVALID_ARG
+    assert so.snake_adam_step(None, None, None, None, 4, ctypes.c_float(1e-2), ctypes.c_float(0.9),
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 0, ctypes.c_float(0), 0,
+                              None) == SNAKE_ERR_INVALID_ARG
+    assert so.snake_adam_step(None, None, None, None, 4, ctypes.c_float(1e-2), ctypes.c_float(0.9),
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, ctypes.c_float(0), 0,
+                              None) == SNAKE_ERR_NULL
+    al = ctypes.c_void_p(4)
+    assert so.snake_adam_step(al, al, al, al, 4, ctypes.c_float(1e-2), ctypes.c_float(0.9),
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, ctypes.c_float(0), 0,
+                              None) == -3
+    # n == 0 is a no-op
+    assert so.snake_adam_step(None, None, None, None, 0, ctypes.c_float(1e-2), ctypes.c_float(0.9),
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, ctypes.c_float(0), 0,
+                              None) == 0
+
+
+def test_binding_raises_on_error(L):
+    with pytest.raises(L.SnakeError):
+        L.snake_adam_step(None, None, None, None, 4, 1e-2, 0.9, 0.99, 1e-15, 0, stream=0)

@@ -1,0 +1,120 @@
+"""GPU parity of snake_sample_segmented / snake_pack_alive against the FP64
+oracle: sample bounds, positions, ray ids, tile ids and packing bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from _helpers import DEV, dev, host, run_sampler, sync
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_01631_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _same(g, o, keys=("t0", "t1", "pos", "ray_id")):
+    assert g["n"] == o["n"]
+    assert np.array_equal(g["packed_info"], o["packed_info"])
+    for k in keys:
+        assert np.array_equal(g[k], o[k]), k
+
+
+def _grid_boxes(nx, ny, side=1.0, z=(0.0, 1.0), x0=0.0, y0=0.0):
+    return np.array([[x0 + i * side, y0 + j * side, z[0], x0 + (i + 1) * side, y0 + (j + 1) * side, z[1]]
+                     for i in range(nx) for j in range(ny)])
+
+
+def _slanted(rng, n, lo, hi, z_top, max_deg=30.0):
+    th = np.deg2rad(rng.uniform(0.0, max_deg, size=n))
+    ph = rng.uniform(0, 2 * np.pi, size=n)
+    d = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), -np.cos(th)], 1)
+    g = np.concatenate([rng.uniform(lo, hi, size=(n, 2)), np.full((n, 1), 0.5)], 1)
+    return g - ((z_top - 0.5) / np.cos(th))[:, None] * d, d
+
+
+def test_tiny_tile_bitexact(L, orc):
+    w = synth.tiny_tile(seed=0)
+    g = run_sampler(L, w.rays_o, w.rays_d, w.boxes, 64)
+    o = orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 64)
+    _same(g, o)
+    assert np.array_equal(g["view"], o["view"])
+
+
+def test_full_tile_band_bitexact(L, orc):
+    w = synth.full_tile(seed=1, n_rays=3000, render_targets=False)
+    g = run_sampler(L, w.rays_o, w.rays_d, w.boxes, 128, zband=w.zband)
+    o = orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 128, zband=w.zband)
+    _same(g, o)
+    assert np.array_equal(g["view"], o["view"])
+    assert g["pos"][:, 2].min() >= 0.2 - 1e-6 and g["pos"][:, 2].max() <= 0.8 + 1e-6
+
+
+def test_window_ragged_multi_tile_bitexact(L, orc):
+    """2x2 window of unit tiles, ragged budgets, misses, vertical and axis rays."""
+    rng = np.random.default_rng(2)
+    boxes = _grid_boxes(2, 2)
+    o, d = _slanted(rng, 4000, -0.3, 2.3, z_top=1.6)
+    o[:8] = [[0.5, 0.5, 2], [1.0, 0.5, 2], [1.0, 1.0, 2], [3, 3, 2], [0.25, 0.75, 0.5],
+             [-1, 0.5, 0.5], [0.5, -1, 0.25], [1.5, 1.5, 1.0]]
+    d[:8] = [[0, 0, -1], [0, 0, -1], [0, 0, -1], [0, 0, -1], [0, 0, -1], [1, 0, 0], [0, 1, 0],
+             [0.3, -0.2, -0.9]]
+    spr = rng.integers(0, 129, size=4000).astype(np.int32)
+    spr[:3] = [1, 2, 3]
+    g = run_sampler(L, o, d, boxes, 0, spr=spr)
+    r = orc.sample_segmented(o, d, boxes, 0, samples_per_ray=spr)
+    _same(g, r, keys=("t0", "t1", "pos", "ray_id", "tile_id"))
+    assert np.array_equal(g["view"], r["view"])
+    # four-tile windows with an altitude band, scaled world coordinates
+    boxes2 = _grid_boxes(2, 2, side=153.6, z=(0.0, 200.0), x0=412345.0, y0=3312345.0)
+    o2 = o * np.array([153.6, 153.6, 200.0]) + np.array([412345.0, 3312345.0, 0.0])
+    d2 = d * np.array([153.6, 153.6, 200.0])
+    g = run_sampler(L, o2, d2, boxes2, 96, zband=[20.0, 180.0])
+    r = orc.sample_segmented(o2, d2, boxes2, 96, zband=[20.0, 180.0])
+    _same(g, r, keys=("t0", "t1", "pos", "ray_id", "tile_id"))
+
+
+def test_truncation_prefix_and_capacity(L, orc):
+    w = synth.tiny_tile(seed=3, n_rays=777, samples=48)
+    mc = np.random.default_rng(4).integers(-2, 60, size=777).astype(np.int32)
+    g = run_sampler(L, w.rays_o, w.rays_d, w.boxes, 48, max_count=mc)
+    o = orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 48, max_count=mc)
+    _same(g, o)
+    # too small a capacity: nothing past cap is written and the device flags it
+    L.snake_check_device_error()
+    g = run_sampler(L, w.rays_o, w.rays_d, w.boxes, 48, cap=1000)
+    assert g["n"] == 777 * 48
+    assert L.snake_check_device_error() == L.SNAKE_DEVERR_CAPACITY
+    assert L.snake_check_device_error() == 0
+
+
+def test_empty_and_all_miss(L):
+    g = run_sampler(L, np.zeros((0, 3)), np.zeros((0, 3)), synth.tiny_tile(n_rays=1).boxes, 16)
+    assert g["n"] == 0
+    o = np.tile([5.0, 5.0, 2.0], (100, 1))
+    d = np.tile([0.0, 0.0, -1.0], (100, 1))
+    g = run_sampler(L, o, d, np.array([[0, 0, 0, 1, 1, 1.0]]), 16)
+    assert g["n"] == 0 and np.all(g["packed_info"][:, 1] == 0)
+
+
+def test_pack_alive(L):
+    rng = np.random.default_rng(5)
+    R = 5000
+    cnt = rng.integers(0, 130, size=R).astype(np.int32)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.int32)
+    alive = rng.integers(-3, 140, size=R).astype(np.int32)
+    info = dev(np.stack([start, cnt], 1), torch.int32)
+    cap = int(cnt.sum())
+    idx = torch.full((cap,), -1, dtype=torch.int32, device=DEV)
+    n_out = torch.zeros(1, dtype=torch.int64, device=DEV)
+    ws = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=DEV)
+    L.snake_pack_alive(info, dev(alive, torch.int32), R, idx, cap, n_out, ws)
+    sync()
+    keep = np.clip(alive, 0, cnt)
+    expect = np.concatenate([np.arange(s, s + k) for s, k in zip(start, keep)]).astype(np.int32)
+    assert int(host(n_out)[0]) == expect.size
+    assert np.array_equal(host(idx)[:expect.size], expect)
