@@ -90,10 +90,10 @@ def run_form(wl, precision, args, pool):
         e[0].record()
         nerf.sample(ro, rd, R)
         e[1].record()
-        L.snake_hashgrid_fwd(nerf.grid, nerf.table, nerf.pos, nerf.tile_id, None, nerf.cap, nerf.n_out,
-                             nerf.feat)
+        L.snake_hashgrid_fwd(nerf.grid, nerf.K, nerf.table, nerf.pos, nerf.tile_id, None, nerf.cap,
+                             nerf.n_out, nerf.feat)
         e[2].record()
-        L.snake_mlp_fwd(nerf.mlp, nerf.params, nerf.feat, nerf.view, sun, nerf.ray_id, None, nerf.cap,
+        L.snake_mlp_fwd(nerf.mlp, nerf.params, nerf.feat, nerf.view, sun, nerf.ray_id, R, None, nerf.cap,
                         nerf.n_out, nerf.sigma, nerf.rgb)
         e[3].record()
         nerf.render(R, tg, scale)
@@ -104,12 +104,12 @@ def run_form(wl, precision, args, pool):
         L.snake_pack_alive(nerf.packed_info, nerf.n_alive, R, nerf.alive_idx, nerf.cap,
                            nerf.n_alive_total, nerf.ws_sample)
         e[6].record()
-        L.snake_mlp_bwd(nerf.mlp, nerf.params, nerf.feat, nerf.cap, nerf.view, sun, nerf.ray_id,
+        L.snake_mlp_bwd(nerf.mlp, nerf.params, nerf.feat, nerf.cap, nerf.view, sun, nerf.ray_id, R,
                         nerf.alive_idx, nerf.cap, nerf.n_alive_total, nerf.dsigma, nerf.drgb, nerf.g_w,
                         nerf.dfeat, nerf.ws_mlp)
         e[7].record()
-        L.snake_hashgrid_bwd(nerf.grid, nerf.pos, nerf.tile_id, nerf.alive_idx, nerf.cap,
-                             nerf.n_alive_total, nerf.dfeat, nerf.g_t)
+        L.snake_hashgrid_bwd(nerf.grid, nerf.K, nerf.pos, nerf.tile_id, nerf.alive_idx, nerf.cap,
+                             nerf.n_alive_total, nerf.dfeat, nerf.g_t, nerf.ws_hash)
         e[8].record()
         nerf.adam()
         e[9].record()

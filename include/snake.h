@@ -70,6 +70,8 @@ typedef enum {
 
 /* Device-side error bits, reported by snake_check_device_error(). */
 #define SNAKE_DEVERR_CAPACITY 1u  /* sampler: packed samples exceed `cap` */
+#define SNAKE_DEVERR_TILE_ID 2u   /* a tile_id >= K (the sample is dropped) */
+#define SNAKE_DEVERR_RAY_ID 4u    /* a ray_id >= R (the sample is dropped) */
 
 typedef enum { SNAKE_F32 = 0, SNAKE_BF16 = 1 } snake_dtype;
 
@@ -160,20 +162,33 @@ typedef struct {
  *   hashed: (i*1 XOR j*2654435761 XOR k*805459861) mod 2^32 AND (T-1)
  * and feat[l][s][f] = sum_b w_b table[tile][l][idx_b][f] with
  * w_b = prod_a (b_a ? w_a : 1 - w_a).
- * pos [.][3] float, tile_id (NULL = tile 0 for all), feat [L][n][F] written.
- * idx_dbg (NULL or [n][L][8] uint32) receives the corner slots.
+ * table [K][L][T][F] float (1 <= K <= 256), pos [.][3] float, tile_id (NULL =
+ * tile 0 for all; an id >= K gives zero features and SNAKE_DEVERR_TILE_ID),
+ * feat [L][n][F] written.  idx_dbg (NULL or [n][L][8] uint32) receives the
+ * corner slots.
  */
-int snake_hashgrid_fwd(const snake_grid_desc *g, const float *table,
+int snake_hashgrid_fwd(const snake_grid_desc *g, int32_t K, const float *table,
                        const float *pos, const uint8_t *tile_id, const int32_t *sample_idx,
                        int64_t n, const int64_t *n_dev, void *feat, uint32_t *idx_dbg,
                        snake_stream_t stream);
 
-/* Adjoint: dtable[tile][l][idx_b][f] += w_b * dfeat[l][s][f] (float atomics;
- * the order of additions, hence the last bits, is not deterministic).
- * dfeat [L][n][F] float.  dtable [K][L][T][F] float. */
-int snake_hashgrid_bwd(const snake_grid_desc *g, const float *pos, const uint8_t *tile_id,
+/* Adjoint: dtable[tile][l][idx_b][f] += w_b * dfeat[l][s][f] for the K tiles
+ * of dtable [K][L][T][F] float; dfeat [L][n][F] float (compact, indexed by j).
+ * With a workspace the corner contributions are binned by table slot (count,
+ * scan, scatter) and each bin is summed in LDS, then added to dtable once per
+ * touched slot; the workspace size decides how many levels share a pass
+ * (snake_hashgrid_bwd_workspace_bytes(g, K, n, levels_per_pass); one level per
+ * pass is the minimum).  With workspace == NULL every contribution is a direct
+ * FP32 atomic add.  Either way the order of additions, hence the last bits,
+ * is not deterministic.  A tile_id >= K contributes nothing and raises
+ * SNAKE_DEVERR_TILE_ID.  Limits: 1 <= K <= 256, K*T <= 2^28; the binned form
+ * needs 8 n < 2^31 and puts at most (2^31 - 1) / (8 n) levels in a pass. */
+size_t snake_hashgrid_bwd_workspace_bytes(const snake_grid_desc *g, int32_t K, int64_t n,
+                                          int32_t levels_per_pass);
+int snake_hashgrid_bwd(const snake_grid_desc *g, int32_t K, const float *pos, const uint8_t *tile_id,
                        const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
-                       const float *dfeat, float *dtable, snake_stream_t stream);
+                       const float *dfeat, float *dtable, void *workspace, size_t workspace_bytes,
+                       snake_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Density and colour networks (Sec. 4.1)                                    */
@@ -199,23 +214,25 @@ int64_t snake_mlp_param_count(const snake_mlp_desc *m);
 
 /* Forward.  feat [L][n][F] (level-major; sample j's row is j), view/sun
  * [R][3] float per ray (sun may be NULL when n_dir == 3), ray_id per input
- * sample (read through sample_idx).  Writes sigma [n], rgb [n][3].  BF16
+ * sample (read through sample_idx); a ray id outside [0, R) gives sigma = 0,
+ * rgb = 0 and raises SNAKE_DEVERR_RAY_ID.  Writes sigma [n], rgb [n][3].  BF16
  * precision rounds inputs, weights and hidden activations to bf16 (RNE) and
  * accumulates in FP32. */
 int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat,
-                  const float *view, const float *sun, const int32_t *ray_id,
+                  const float *view, const float *sun, const int32_t *ray_id, int32_t R,
                   const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
                   float *sigma, float *rgb, snake_stream_t stream);
 
 /* Adjoint, recomputing the activations from feat.  feat, ray_id, dsigma
  * and drgb are read through sample_idx (feat level-major with level stride
  * feat_ld >= every index read); dfeat [L][n][F] float is written compact at
- * j.  dW [P] += the sum over samples, reduced in a fixed order (deterministic
- * for a given n).  Workspace: snake_mlp_bwd_workspace_bytes(m). */
+ * j (zero for a sample whose ray id is outside [0, R), which is flagged with
+ * SNAKE_DEVERR_RAY_ID).  dW [P] += the sum over samples, reduced in a fixed
+ * order (deterministic for a given n).  Workspace: snake_mlp_bwd_workspace_bytes(m). */
 size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m);
 int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat,
                   int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
-                  const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
+                  int32_t R, const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
                   const float *dsigma, const float *drgb, float *dW, float *dfeat,
                   void *workspace, size_t workspace_bytes, snake_stream_t stream);
 

@@ -57,6 +57,8 @@ def lib():
         L.orc_mlp_param_count.restype = _I64
         L.orc_mlp_fwd.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P]
         L.orc_mlp_bwd.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.orc_mlp_margin.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P]
+        L.orc_mlp_fwd_bf16emu.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P]
         L.orc_composite_fwd.argtypes = [_I, _P, _P, _P, _P, _P, _D, _P, _P, _D,
                                         _P, _P, _P, _P, _P]
         L.orc_composite_bwd.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _D, _P, _P]
@@ -145,6 +147,31 @@ def mlp_fwd(m, weights, feat, view, ray_id, sun=None):
     rgb = np.zeros((n, 3))
     lib().orc_mlp_fwd(*_mlp_args(m), _ptr(weights), n, _ptr(feat), _ptr(_c(view, np.float32)),
                       _ptr(_c(sun, np.float32)), _ptr(_c(ray_id, np.int32)), _ptr(sigma), _ptr(rgb))
+    return sigma, rgb
+
+
+def mlp_margin(m, weights, feat, view, ray_id, sun=None):
+    """Per-sample distance from the nearest ReLU kink, min |z| / sum |W x|."""
+    weights = _c(weights, np.float32)
+    feat = _c(feat, np.float64)
+    n = feat.shape[0]
+    out = np.zeros(n)
+    lib().orc_mlp_margin(*_mlp_args(m), _ptr(weights), n, _ptr(feat), _ptr(_c(view, np.float32)),
+                         _ptr(_c(sun, np.float32)), _ptr(_c(ray_id, np.int32)), _ptr(out))
+    return out
+
+
+def mlp_fwd_bf16emu(m, weights, feat, view, ray_id, sun=None):
+    """Forward with BF16 rounding emulated at the operand rounding points
+    (diagnostic; the reference forward is mlp_fwd)."""
+    weights = _c(weights, np.float32)
+    feat = _c(feat, np.float64)
+    n = feat.shape[0]
+    sigma = np.zeros(n)
+    rgb = np.zeros((n, 3))
+    lib().orc_mlp_fwd_bf16emu(*_mlp_args(m), _ptr(weights), n, _ptr(feat),
+                              _ptr(_c(view, np.float32)), _ptr(_c(sun, np.float32)),
+                              _ptr(_c(ray_id, np.int32)), _ptr(sigma), _ptr(rgb))
     return sigma, rgb
 
 

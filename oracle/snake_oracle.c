@@ -406,6 +406,25 @@ static void mlp_forward_one(const orc_mlp *m, const double *w, const int64_t *of
     }
 }
 
+/* Distance of one sample from the nearest ReLU kink: the minimum over every
+ * hidden pre-activation z of |z| / sum_i |W_i x_i|.  A sample whose margin is
+ * below the working precision of an implementation may legitimately get the
+ * other ReLU decision there; tests use this to tell ambiguous samples apart. */
+static double relu_margin_layer(const double *W, int out, int in, const double *x, double *y)
+{
+    double m = INFINITY;
+    for (int o = 0; o < out; ++o) {
+        double acc = 0.0, l1 = 0.0;
+        for (int i = 0; i < in; ++i) {
+            acc += W[(int64_t)o * in + i] * x[i];
+            l1 += fabs(W[(int64_t)o * in + i] * x[i]);
+        }
+        y[o] = acc;
+        if (l1 > 0.0 && fabs(acc) / l1 < m) m = fabs(acc) / l1;
+    }
+    return m;
+}
+
 static double *weights_f64(const float *wf, int64_t P)
 {
     double *w = (double *)malloc(sizeof(double) * (size_t)P);
@@ -434,6 +453,96 @@ void orc_mlp_fwd(int feat_width, int hidden, int dens_out, int n_dir, int colour
         int64_t r = ray_id[s];
         mlp_forward_one(&m, w, off, feat + s * feat_width, view + 3 * r,
                         sun ? sun + 3 * r : NULL, &a, sigma + s, rgb + 3 * s);
+    }
+    free(w);
+}
+
+/* Per-sample ReLU margin (see relu_margin_layer) of the forward pass. */
+void orc_mlp_margin(int feat_width, int hidden, int dens_out, int n_dir, int colour_layers,
+                    int colour_out, const float *weights, int64_t n, const double *feat,
+                    const float *view, const float *sun, const int32_t *ray_id, double *margin)
+{
+    orc_mlp m = {feat_width, hidden, dens_out, n_dir, colour_layers, colour_out};
+    int64_t off[8];
+    int64_t P = mlp_offsets(&m, off);
+    double *w = weights_f64(weights, P);
+    int H = hidden, cin = dens_out - 1 + n_dir;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        orc_act a;
+        int64_t r = ray_id[s];
+        double sig, rgb[3];
+        mlp_forward_one(&m, w, off, feat + s * feat_width, view + 3 * r, sun ? sun + 3 * r : NULL,
+                        &a, &sig, rgb);
+        double y[ORC_MAXW];
+        double mg = relu_margin_layer(w + off[0], H, feat_width, a.x, y);
+        double t = relu_margin_layer(w + off[2], H, cin, a.cin, y);
+        if (t < mg) mg = t;
+        for (int c = 1; c < colour_layers; ++c) {
+            t = relu_margin_layer(w + off[2 + c], H, H, a.g[c - 1], y);
+            if (t < mg) mg = t;
+        }
+        margin[s] = mg;
+    }
+    free(w);
+}
+
+/* Forward with BF16 rounding emulated at the points where a BF16 matrix-core
+ * implementation rounds: features, weights, the embedding and directions fed
+ * to the colour net, and every post-ReLU hidden activation are rounded to the
+ * nearest bfloat16 (ties to even, via float32); sums stay exact in FP64;
+ * sigma = exp(o_0) uses the unrounded logit.  Diagnostic only. */
+static double bf16r(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) != 0x7f800000u) {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        u &= 0xffff0000u;
+    }
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+void orc_mlp_fwd_bf16emu(int feat_width, int hidden, int dens_out, int n_dir, int colour_layers,
+                         int colour_out, const float *weights, int64_t n, const double *feat,
+                         const float *view, const float *sun, const int32_t *ray_id,
+                         double *sigma, double *rgb)
+{
+    orc_mlp m = {feat_width, hidden, dens_out, n_dir, colour_layers, colour_out};
+    int64_t off[8];
+    int64_t P = mlp_offsets(&m, off);
+    double *w = weights_f64(weights, P);
+    for (int64_t i = 0; i < P; ++i) w[i] = bf16r(w[i]);
+    int H = hidden, cin = dens_out - 1 + n_dir, CL = colour_layers;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double x[ORC_MAXW] = {0}, h[ORC_MAXW] = {0}, o[ORC_MAXW] = {0}, ci[ORC_MAXW] = {0};
+        double g[ORC_MAXW] = {0}, g2[ORC_MAXW] = {0}, out[8] = {0};
+        int64_t r = ray_id[s];
+        for (int i = 0; i < feat_width; ++i) x[i] = bf16r(feat[s * feat_width + i]);
+        matvec(w + off[0], H, feat_width, x, h);
+        for (int i = 0; i < H; ++i) h[i] = bf16r(h[i] > 0.0 ? h[i] : 0.0);
+        matvec(w + off[1], dens_out, H, h, o);
+        sigma[s] = exp(o[0]);
+        for (int i = 0; i < dens_out - 1; ++i) ci[i] = bf16r(o[1 + i]);
+        for (int i = 0; i < 3; ++i) ci[dens_out - 1 + i] = bf16r(view[3 * r + i]);
+        if (n_dir == 6)
+            for (int i = 0; i < 3; ++i) ci[dens_out + 2 + i] = bf16r(sun[3 * r + i]);
+        matvec(w + off[2], H, cin, ci, g);
+        for (int i = 0; i < H; ++i) g[i] = bf16r(g[i] > 0.0 ? g[i] : 0.0);
+        for (int c = 1; c < CL; ++c) {
+            matvec(w + off[2 + c], H, H, g, g2);
+            for (int i = 0; i < H; ++i) g[i] = bf16r(g2[i] > 0.0 ? g2[i] : 0.0);
+        }
+        matvec(w + off[2 + CL], colour_out, H, g, out);
+        if (colour_out == 3) {
+            for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoid(out[c]);
+        } else {
+            double vis = sigmoid(out[3]);
+            for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoid(out[c]) * vis;
+        }
     }
     free(w);
 }

@@ -19,12 +19,14 @@ SNAKE_F32, SNAKE_BF16 = 0, 1
 SNAKE_GRID_ALWAYS_HASH = 1
 SNAKE_ADAM_ZERO_GRAD = 1
 SNAKE_DEVERR_CAPACITY = 1
+SNAKE_DEVERR_TILE_ID = 2
+SNAKE_DEVERR_RAY_ID = 4
 MAX_LEVELS = 32
 
 EXPORTS = (
     "snake_abi_version", "snake_last_error", "snake_check_device_error",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_pack_alive",
-    "snake_hashgrid_fwd", "snake_hashgrid_bwd",
+    "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd", "snake_mlp_bwd",
     "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step",
 )
@@ -78,12 +80,13 @@ _SIGS = {
     "snake_sample_segmented": ([_P, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
                                 _I64, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_pack_alive": ([_P, _P, _I32, _P, _I64, _P, _P, _SZ, _P], ctypes.c_int),
-    "snake_hashgrid_fwd": ([_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
-    "snake_hashgrid_bwd": ([_P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "snake_hashgrid_fwd": ([_P, _I32, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "snake_hashgrid_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "snake_hashgrid_bwd_workspace_bytes": ([_P, _I32, _I64, _I32], _SZ),
     "snake_mlp_param_count": ([_P], _I64),
     "snake_mlp_bwd_workspace_bytes": ([_P], _SZ),
-    "snake_mlp_fwd": ([_P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
-    "snake_mlp_bwd": ([_P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P],
+    "snake_mlp_fwd": ([_P, _P, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "snake_mlp_bwd": ([_P, _P, _P, _I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P],
                       ctypes.c_int),
     "snake_composite_fwd": ([_P, _P, _P, _P, _P, _I32, _F, _P, _F, _P, _P, _P, _P, _P, _P],
                             ctypes.c_int),
@@ -175,17 +178,25 @@ def snake_pack_alive(packed_info, n_alive, R, idx_out, cap, n_out, workspace, st
     _check("snake_pack_alive", rc)
 
 
-def snake_hashgrid_fwd(g: GridDesc, table, pos, tile_id, sample_idx, n, n_dev, feat, idx_dbg=None,
+def snake_hashgrid_fwd(g: GridDesc, K, table, pos, tile_id, sample_idx, n, n_dev, feat, idx_dbg=None,
                        stream=None):
-    rc = lib().snake_hashgrid_fwd(ctypes.byref(g), _ptr(table), _ptr(pos), _ptr(tile_id),
+    rc = lib().snake_hashgrid_fwd(ctypes.byref(g), int(K), _ptr(table), _ptr(pos), _ptr(tile_id),
                                   _ptr(sample_idx), int(n), _ptr(n_dev), _ptr(feat), _ptr(idx_dbg),
                                   _stream(stream))
     _check("snake_hashgrid_fwd", rc)
 
 
-def snake_hashgrid_bwd(g: GridDesc, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable, stream=None):
-    rc = lib().snake_hashgrid_bwd(ctypes.byref(g), _ptr(pos), _ptr(tile_id), _ptr(sample_idx), int(n),
-                                  _ptr(n_dev), _ptr(dfeat), _ptr(dtable), _stream(stream))
+def snake_hashgrid_bwd_workspace_bytes(g: GridDesc, K, n, levels_per_pass) -> int:
+    return int(lib().snake_hashgrid_bwd_workspace_bytes(ctypes.byref(g), int(K), int(n),
+                                                        int(levels_per_pass)))
+
+
+def snake_hashgrid_bwd(g: GridDesc, K, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable,
+                       workspace=None, stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    rc = lib().snake_hashgrid_bwd(ctypes.byref(g), int(K), _ptr(pos), _ptr(tile_id), _ptr(sample_idx),
+                                  int(n), _ptr(n_dev), _ptr(dfeat), _ptr(dtable), _ptr(workspace),
+                                  nbytes, _stream(stream))
     _check("snake_hashgrid_bwd", rc)
 
 
@@ -197,18 +208,18 @@ def snake_mlp_bwd_workspace_bytes(m: MlpDesc) -> int:
     return int(lib().snake_mlp_bwd_workspace_bytes(ctypes.byref(m)))
 
 
-def snake_mlp_fwd(m: MlpDesc, weights, feat, view, sun, ray_id, sample_idx, n, n_dev, sigma, rgb,
+def snake_mlp_fwd(m: MlpDesc, weights, feat, view, sun, ray_id, R, sample_idx, n, n_dev, sigma, rgb,
                   stream=None):
     rc = lib().snake_mlp_fwd(ctypes.byref(m), _ptr(weights), _ptr(feat), _ptr(view), _ptr(sun),
-                             _ptr(ray_id), _ptr(sample_idx), int(n), _ptr(n_dev), _ptr(sigma),
+                             _ptr(ray_id), int(R), _ptr(sample_idx), int(n), _ptr(n_dev), _ptr(sigma),
                              _ptr(rgb), _stream(stream))
     _check("snake_mlp_fwd", rc)
 
 
-def snake_mlp_bwd(m: MlpDesc, weights, feat, feat_ld, view, sun, ray_id, sample_idx, n, n_dev,
+def snake_mlp_bwd(m: MlpDesc, weights, feat, feat_ld, view, sun, ray_id, R, sample_idx, n, n_dev,
                   dsigma, drgb, dW, dfeat, workspace, stream=None):
     rc = lib().snake_mlp_bwd(ctypes.byref(m), _ptr(weights), _ptr(feat), int(feat_ld), _ptr(view),
-                             _ptr(sun), _ptr(ray_id), _ptr(sample_idx), int(n), _ptr(n_dev),
+                             _ptr(sun), _ptr(ray_id), int(R), _ptr(sample_idx), int(n), _ptr(n_dev),
                              _ptr(dsigma), _ptr(drgb), _ptr(dW), _ptr(dfeat), _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream))
     _check("snake_mlp_bwd", rc)

@@ -42,8 +42,12 @@ __device__ __forceinline__ SampleVals chunk_vals(const float *sigma, const float
         v.c[2] = rgb[3 * idx + 2];
     }
     incl = wave_inclusive_sum(s);
+    // exclusive prefix = the previous lane's inclusive one (no subtraction,
+    // which would cancel when s is large)
+    float excl = __shfl_up(incl, 1, 64);
+    excl = lane == 0 ? 0.0f : excl;
     v.s = s;
-    v.T = expf(-(carry + incl - s));
+    v.T = expf(-(carry + excl));
     v.w = v.T * (-expm1f(-s));
     v.mid = 0.5f * (a0 + a1);
     chunk_depth_sum = __shfl(incl, 63, 64);

@@ -14,11 +14,14 @@
 #pragma clang fp contract(off)
 
 #include "common.h"
+#include "scan.h"
 
 namespace snake {
 namespace {
 
 struct Grid {
+    int K;                // tiles in the table
+    unsigned int *err;    // device error word
     int L;
     int log2T;
     uint32_t mask;        // T - 1
@@ -100,6 +103,11 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const float *
         const int64_t si = sidx ? sidx[s] : s;
         const float x[3] = {pos[3 * si], pos[3 * si + 1], pos[3 * si + 2]};
         const int64_t tile = tile_id ? tile_id[si] : 0;
+        if (tile >= g.K) {                      // no such tile: zero features, flag it
+            for (int f = 0; f < F; ++f) store_feat(feat + ((int64_t)l * n + s) * F + f, 0.0f);
+            if (g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_TILE_ID);
+            continue;
+        }
         uint32_t idx[8];
         float wt[8];
         corners(g, l, x, idx, wt);
@@ -145,6 +153,10 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
         const int64_t si = sidx ? sidx[s] : s;
         const float x[3] = {pos[3 * si], pos[3 * si + 1], pos[3 * si + 2]};
         const int64_t tile = tile_id ? tile_id[si] : 0;
+        if (tile >= g.K) {
+            if (g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_TILE_ID);
+            continue;
+        }
         uint32_t idx[8];
         float wt[8];
         corners(g, l, x, idx, wt);
@@ -157,7 +169,254 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
     }
 }
 
-int make_grid(const snake_grid_desc *d, Grid &g, const char *fn)
+// ---- binned adjoint ----------------------------------------------------------
+//
+// Global FP32 atomics on this chip run at a fixed ~2e10 operations/s whatever
+// the footprint, far below the rate at which the samples produce corner
+// gradients (L*8*F per sample).  The binned adjoint therefore sorts the
+// corner contributions by table slot before adding them:
+//   count   per (bin, block) how many (slot, w*g) items a block's samples make
+//   scan    exclusive offsets, bin-major, so each bin's items are contiguous
+//   scatter write the items to their bin (LDS cursors per block)
+//   reduce  per chunk of items: add into a 64 KB LDS copy of the bin's slots,
+//           then flush the bin once with one global atomic per touched slot
+// A pass covers `lg` levels; bins never straddle levels.
+
+constexpr int kBinBlocks = 1024;        // blocks of the count/scatter passes
+constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
+constexpr int kAccFloats = 16384;       // LDS accumulator, 64 KB
+constexpr int64_t kReduceChunk = 1 << 19;
+
+struct BinPlan {
+    int l0, lg;            // levels [l0, l0 + lg) in this pass
+    int kt2_log2;          // per-level key space (padded K*T), log2
+    int binshift;          // slots per bin = 2^binshift
+    int nbpl;              // bins per level
+    int nb;                // bins in the pass
+    int T_log2;
+};
+
+__device__ __forceinline__ bool wave_uniform(int b, bool active, int &b0)
+{
+    const unsigned long long act = __ballot(active);
+    if (!act) return false;
+    const int first = __ffsll((long long)act) - 1;
+    b0 = __shfl(b, first, 64);
+    return __all(!active || b == b0);
+}
+
+template <int F>
+__device__ __forceinline__ bool grad_nonzero(const typename Vec<F>::T &gv)
+{
+    bool any = false;
+#pragma unroll
+    for (int f = 0; f < F; ++f) any |= Vec<F>::get(gv, f) != 0.0f;
+    return any;
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
+                                                        const uint8_t *__restrict__ tile_id,
+                                                        const int32_t *__restrict__ sidx, int64_t n,
+                                                        const int64_t *__restrict__ n_dev,
+                                                        const float *__restrict__ dfeat,
+                                                        int32_t *__restrict__ counts)
+{
+    typedef typename Vec<F>::T VT;
+    __shared__ int hist[kMaxBins];
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int64_t ne = effective_n(n, n_dev);
+    const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
+    const int lane = lane_id();
+    for (int64_t base = s0; base < s1; base += blockDim.x) {
+        const int64_t s = base + threadIdx.x;
+        const bool valid = s < s1;
+        float x[3] = {0.f, 0.f, 0.f};
+        int64_t tile = 0;
+        if (valid) {
+            const int64_t si = sidx ? sidx[s] : s;
+            x[0] = pos[3 * si];
+            x[1] = pos[3 * si + 1];
+            x[2] = pos[3 * si + 2];
+            tile = tile_id ? tile_id[si] : 0;
+        }
+        const bool tile_ok = tile < g.K;
+        if (valid && !tile_ok && g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_TILE_ID);
+        for (int lr = 0; lr < bp.lg; ++lr) {
+            const int l = bp.l0 + lr;
+            bool act = valid && tile_ok;
+            if (act) act = grad_nonzero<F>(*reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F));
+            uint32_t idx[8];
+            float wt[8];
+            corners(g, l, x, idx, wt);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
+                const int b = lr * bp.nbpl + (int)(key >> bp.binshift);
+                int b0;
+                if (wave_uniform(b, act, b0)) {
+                    if (lane == __ffsll((long long)__ballot(act)) - 1)
+                        atomicAdd(&hist[b0], __popcll(__ballot(act)));
+                } else if (act) {
+                    atomicAdd(&hist[b], 1);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) counts[(int64_t)b * gridDim.x + blockIdx.x] = hist[b];
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
+                                                          const uint8_t *__restrict__ tile_id,
+                                                          const int32_t *__restrict__ sidx, int64_t n,
+                                                          const int64_t *__restrict__ n_dev,
+                                                          const float *__restrict__ dfeat,
+                                                          const int32_t *__restrict__ offsets,
+                                                          uint32_t *__restrict__ items)
+{
+    typedef typename Vec<F>::T VT;
+    __shared__ int cursor[kMaxBins];
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x)
+        cursor[b] = offsets[(int64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int64_t ne = effective_n(n, n_dev);
+    const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
+    const int lane = lane_id();
+    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = s0; base < s1; base += blockDim.x) {
+        const int64_t s = base + threadIdx.x;
+        const bool valid = s < s1;
+        float x[3] = {0.f, 0.f, 0.f};
+        int64_t tile = 0;
+        if (valid) {
+            const int64_t si = sidx ? sidx[s] : s;
+            x[0] = pos[3 * si];
+            x[1] = pos[3 * si + 1];
+            x[2] = pos[3 * si + 2];
+            tile = tile_id ? tile_id[si] : 0;
+        }
+        const bool tile_ok = tile < g.K;
+        for (int lr = 0; lr < bp.lg; ++lr) {
+            const int l = bp.l0 + lr;
+            bool act = valid && tile_ok;
+            VT gv = {};
+            if (act) {
+                gv = *reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F);
+                act = grad_nonzero<F>(gv);
+            }
+            uint32_t idx[8];
+            float wt[8];
+            corners(g, l, x, idx, wt);
+            const uint32_t lbase = (uint32_t)lr << bp.kt2_log2;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
+                const int b = lr * bp.nbpl + (int)(key >> bp.binshift);
+                int b0, at;
+                if (wave_uniform(b, act, b0)) {
+                    const unsigned long long am = __ballot(act);
+                    const int leader = __ffsll((long long)am) - 1;
+                    int basepos = 0;
+                    if (lane == leader) basepos = atomicAdd(&cursor[b0], __popcll(am));
+                    basepos = __shfl(basepos, leader, 64);
+                    at = basepos + __popcll(am & lt_mask);
+                } else {
+                    at = act ? atomicAdd(&cursor[b], 1) : 0;
+                }
+                if (act) {
+                    uint32_t *it = items + (int64_t)at * (1 + F);
+                    it[0] = lbase + key;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) it[1 + f] = __float_as_uint(wt[q] * Vec<F>::get(gv, f));
+                }
+            }
+        }
+    }
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, const int32_t *__restrict__ offsets,
+                                                         int nblk, const int64_t *__restrict__ n_items,
+                                                         const uint32_t *__restrict__ items,
+                                                         float *__restrict__ dtable)
+{
+    __shared__ float acc[kAccFloats];
+    const int64_t total = *n_items;
+    const int slots = 1 << bp.binshift;
+    const uint32_t smask = (uint32_t)slots - 1;
+    for (int64_t c0 = (int64_t)blockIdx.x * kReduceChunk; c0 < total; c0 += (int64_t)gridDim.x * kReduceChunk) {
+        const int64_t c1 = c0 + kReduceChunk < total ? c0 + kReduceChunk : total;
+        const int bfirst = (int)(items[c0 * (1 + F)] >> bp.binshift);
+        const int blast = (int)(items[(c1 - 1) * (1 + F)] >> bp.binshift);
+        for (int b = bfirst; b <= blast; ++b) {
+            const int64_t bs = offsets[(int64_t)b * nblk];
+            const int64_t be = b + 1 < bp.nb ? (int64_t)offsets[(int64_t)(b + 1) * nblk] : total;
+            const int64_t lo = bs > c0 ? bs : c0, hi = be < c1 ? be : c1;
+            if (lo >= hi) continue;
+            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) acc[e] = 0.0f;
+            __syncthreads();
+            for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+                const uint32_t *it = items + i * (1 + F);
+                const uint32_t slot = it[0] & smask;
+#pragma unroll
+                for (int f = 0; f < F; ++f) atomicAdd(&acc[slot * F + f], __uint_as_float(it[1 + f]));
+            }
+            __syncthreads();
+            // the bin's first key: level and table position of slot 0
+            const uint32_t kbase = (uint32_t)b << bp.binshift;
+            const int lr = (int)(kbase >> bp.kt2_log2);
+            const uint32_t key0 = kbase & ((1u << bp.kt2_log2) - 1u);
+            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) {
+                const float v = acc[e];
+                if (v != 0.0f) {
+                    const uint32_t key = key0 + (uint32_t)(e / F);
+                    const int64_t tile = key >> bp.T_log2;
+                    const int64_t idx = key & ((1u << bp.T_log2) - 1u);
+                    unsafeAtomicAdd(dtable + ((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + (e % F), v);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct BinWs {
+    int32_t *counts;
+    int64_t *bsum, *n_items;
+    uint32_t *items;
+    int64_t item_cap;
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace of a pass over lg levels for n samples.
+static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F)
+{
+    const int64_t ncnt = (int64_t)nb * kBinBlocks;
+    return align256((size_t)ncnt * 4) + align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 +
+           align256((size_t)n * lg * 8 * (1 + F) * 4);
+}
+
+static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
+{
+    BinPlan bp;
+    bp.l0 = l0;
+    bp.lg = lg;
+    bp.T_log2 = log2T;
+    int kt = log2T;
+    while ((1 << (kt - log2T)) < K) ++kt;      // padded K*T
+    bp.kt2_log2 = kt;
+    const int acc_log2 = F == 1 ? 14 : F == 2 ? 13 : 12;   // 2^acc_log2 * F floats = 64 KB
+    bp.binshift = kt < acc_log2 ? kt : acc_log2;
+    bp.nbpl = 1 << (kt - bp.binshift);
+    bp.nb = lg * bp.nbpl;
+    return bp;
+}
+
+int make_grid(const snake_grid_desc *d, int K, Grid &g, const char *fn)
 {
     SNAKE_REQUIRE(d != nullptr, SNAKE_ERR_NULL, "%s: grid descriptor is NULL", fn);
     SNAKE_REQUIRE(d->n_levels >= 1 && d->n_levels <= SNAKE_MAX_LEVELS, SNAKE_ERR_INVALID_ARG,
@@ -168,6 +427,9 @@ int make_grid(const snake_grid_desc *d, Grid &g, const char *fn)
                   "%s: log2_table = %d not in [4, 24]", fn, d->log2_table);
     SNAKE_REQUIRE(d->feat_dtype == SNAKE_F32 || d->feat_dtype == SNAKE_BF16, SNAKE_ERR_INVALID_ARG,
                   "%s: bad feat_dtype %d", fn, d->feat_dtype);
+    SNAKE_REQUIRE(K >= 1 && K <= 256, SNAKE_ERR_INVALID_ARG, "%s: K = %d not in [1, 256]", fn, K);
+    g.K = K;
+    g.err = device_error_word();
     g.L = d->n_levels;
     g.log2T = d->log2_table;
     g.mask = (uint32_t)((1ull << d->log2_table) - 1);
@@ -192,12 +454,12 @@ using namespace snake;
 
 extern "C" {
 
-int snake_hashgrid_fwd(const snake_grid_desc *gd, const float *table, const float *pos,
+int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const float *table, const float *pos,
                        const uint8_t *tile_id, const int32_t *sample_idx, int64_t n,
                        const int64_t *n_dev, void *feat, uint32_t *idx_dbg, snake_stream_t stream)
 {
     Grid g;
-    int rc = make_grid(gd, g, __func__);
+    int rc = make_grid(gd, K, g, __func__);
     if (rc) return rc;
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_hashgrid_fwd: n < 0");
     if (n == 0) return SNAKE_OK;
@@ -227,14 +489,26 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, const float *table, const floa
     return launch_status(__func__);
 }
 
-int snake_hashgrid_bwd(const snake_grid_desc *gd, const float *pos, const uint8_t *tile_id,
-                       const int32_t *sample_idx, int64_t n, const int64_t *n_dev, const float *dfeat,
-                       float *dtable, snake_stream_t stream)
+size_t snake_hashgrid_bwd_workspace_bytes(const snake_grid_desc *gd, int32_t K, int64_t n,
+                                          int32_t levels_per_pass)
 {
     Grid g;
-    int rc = make_grid(gd, g, __func__);
+    if (make_grid(gd, K, g, __func__) || n < 0) return 0;
+    const int lg = levels_per_pass < 1 ? 1 : (levels_per_pass > g.L ? g.L : levels_per_pass);
+    const BinPlan bp = make_plan(g.L, gd->n_features, gd->log2_table, K, 0, lg);
+    return bin_ws_bytes(bp.nb, n, lg, gd->n_features);
+}
+
+int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, const uint8_t *tile_id,
+                       const int32_t *sample_idx, int64_t n, const int64_t *n_dev, const float *dfeat,
+                       float *dtable, void *workspace, size_t workspace_bytes, snake_stream_t stream)
+{
+    Grid g;
+    int rc = make_grid(gd, K, g, __func__);
     if (rc) return rc;
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_hashgrid_bwd: n < 0");
+    SNAKE_REQUIRE((int64_t)K << gd->log2_table <= ((int64_t)1 << 28), SNAKE_ERR_INVALID_ARG,
+                  "snake_hashgrid_bwd: K * T exceeds 2^28 slots per level");
     if (n == 0) return SNAKE_OK;
     SNAKE_NOT_NULL(pos);
     SNAKE_NOT_NULL(dfeat);
@@ -242,13 +516,65 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, const float *pos, const uint8_
     const int F = gd->n_features;
     SNAKE_ALIGNED(dfeat, 4 * F);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const unsigned grid = grid_for(n * g.L, 256, 16);
-    if (F == 1)
-        hashgrid_bwd_kernel<1><<<grid, 256, 0, st>>>(g, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable);
-    else if (F == 2)
-        hashgrid_bwd_kernel<2><<<grid, 256, 0, st>>>(g, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable);
-    else
-        hashgrid_bwd_kernel<4><<<grid, 256, 0, st>>>(g, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable);
+    if (workspace == nullptr) {
+        const unsigned grid = grid_for(n * g.L, 256, 16);
+        if (F == 1)
+            hashgrid_bwd_kernel<1><<<grid, 256, 0, st>>>(g, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable);
+        else if (F == 2)
+            hashgrid_bwd_kernel<2><<<grid, 256, 0, st>>>(g, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable);
+        else
+            hashgrid_bwd_kernel<4><<<grid, 256, 0, st>>>(g, pos, tile_id, sample_idx, n, n_dev, dfeat, dtable);
+        return launch_status(__func__);
+    }
+    SNAKE_ALIGNED(workspace, 256);
+    // largest level group whose items fit the workspace
+    int lg = 0;
+    for (int cand = g.L; cand >= 1; --cand) {
+        const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, 0, cand);
+        // item offsets are int32: a pass holds fewer than 2^31 items
+        if (bp.nb <= kMaxBins && n * cand * 8 <= (int64_t)INT32_MAX &&
+            bin_ws_bytes(bp.nb, n, cand, F) <= workspace_bytes) {
+            lg = cand;
+            break;
+        }
+    }
+    SNAKE_REQUIRE(n * 8 <= (int64_t)INT32_MAX, SNAKE_ERR_INVALID_ARG,
+                  "snake_hashgrid_bwd: n = %lld too large for the binned adjoint (n * 8 < 2^31)", (long long)n);
+    SNAKE_REQUIRE(lg >= 1, SNAKE_ERR_WORKSPACE, "snake_hashgrid_bwd: workspace needs at least %zu bytes",
+                  snake_hashgrid_bwd_workspace_bytes(gd, K, n, 1));
+    for (int l0 = 0; l0 < g.L; l0 += lg) {
+        const int lgp = l0 + lg <= g.L ? lg : g.L - l0;
+        const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, l0, lgp);
+        const int64_t ncnt = (int64_t)bp.nb * kBinBlocks;
+        char *p = static_cast<char *>(workspace);
+        BinWs w;
+        w.counts = reinterpret_cast<int32_t *>(p);
+        p += align256((size_t)ncnt * 4);
+        w.bsum = reinterpret_cast<int64_t *>(p);
+        p += align256((size_t)scan::scan_blocks(ncnt) * 8);
+        w.n_items = reinterpret_cast<int64_t *>(p);
+        p += 256;
+        w.items = reinterpret_cast<uint32_t *>(p);
+        w.item_cap = n * lgp * 8;
+        const int64_t chunks = (w.item_cap + kReduceChunk - 1) / kReduceChunk;
+        const unsigned rgrid = (unsigned)(chunks < 4096 ? (chunks > 0 ? chunks : 1) : 4096);
+#define SNAKE_BIN_PASS(FF)                                                                               \
+    bin_count_kernel<FF><<<kBinBlocks, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat,   \
+                                                     w.counts);                                           \
+    scan::launch_scan(w.counts, ncnt, w.bsum, w.counts, 1, nullptr, w.item_cap, w.n_items,              \
+                      device_error_word(), st);                                                           \
+    bin_scatter_kernel<FF><<<kBinBlocks, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, \
+                                                       w.counts, w.items);                                \
+    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, g.L, w.counts, kBinBlocks, w.n_items, w.items, dtable)
+        if (F == 1) {
+            SNAKE_BIN_PASS(1);
+        } else if (F == 2) {
+            SNAKE_BIN_PASS(2);
+        } else {
+            SNAKE_BIN_PASS(4);
+        }
+#undef SNAKE_BIN_PASS
+    }
     return launch_status(__func__);
 }
 

@@ -40,6 +40,8 @@ struct MlpArgs {
     int cin_real;           // 15 + n_dir
     int64_t off[5];         // offsets of D1, D2, C1, C2, CO in the packed weights
     int64_t P;              // packed parameter count
+    int64_t R;              // rows of view / sun (ray ids must be below)
+    unsigned int *err;      // device error word
 };
 
 // Padded weight value: D1 [64][32], D2 [16][64], C1 [64][32] whose column p
@@ -299,11 +301,17 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
         const bool valid = s < ne;
         const int64_t si = valid ? (sidx ? sidx[s] : s) : 0;
         Acts<PREC, CL> A;
-        load_features(feat, n, s, valid, a, A.x);
-        const int64_t ray = valid ? ray_id[si] : 0;
-        load_dirs(view, sun, ray, valid, a, A.cin[1]);
+        int64_t ray = valid ? ray_id[si] : 0;
+        const bool ok = valid && ray >= 0 && ray < a.R;     // a bad ray id drops the sample
+        if (valid && !ok && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
+        ray = ok ? ray : 0;
+        load_features(feat, n, s, ok, a, A.x);
+        load_dirs(view, sun, ray, ok, a, A.cin[1]);
         forward_tile<PREC, CL>(lds, A);
-        if (q == 0 && valid) {
+        if (q == 0 && valid && !ok) {
+            sigma[s] = 0.0f;
+            rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
+        } else if (q == 0 && valid) {
             sigma[s] = expf(A.o[0][0]);
             if (a.CO == 3) {
 #pragma unroll
@@ -458,11 +466,14 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
     const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + wv; t < tiles; t += nw) {
         const int64_t s = t * 16 + i;
-        const bool valid = s < ne;
-        const int64_t si = valid ? (sidx ? sidx[s] : s) : 0;
+        const bool in_range = s < ne;
+        const int64_t si = in_range ? (sidx ? sidx[s] : s) : 0;
+        int64_t ray = in_range ? ray_id[si] : 0;
+        const bool valid = in_range && ray >= 0 && ray < a.R;   // a bad ray id drops the sample
+        if (in_range && !valid && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
+        ray = valid ? ray : 0;
         Acts<PREC, CL> A;
         load_features(feat, feat_ld, si, valid, a, A.x);
-        const int64_t ray = valid ? ray_id[si] : 0;
         load_dirs(view, sun, ray, valid, a, A.cin[1]);
         forward_tile<PREC, CL>(lds, A);
 
@@ -505,7 +516,7 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
         apply<PREC, 64, 16>(lds + Lt::D2T, dob, dh1);
         relu_mask(dh1, A.h1);
         apply<PREC, 32, 64>(lds + Lt::D1T, dh1, dx);
-        store_dfeat<FT>(dfeat, n, s, valid, a, dx);
+        store_dfeat<FT>(dfeat, n, s, in_range, a, dx);       // dropped samples store zeros
 
         // weight gradients: stage (dy, x) pairs as [row][sample], MFMA over samples
         stage<1>(st, 0, dout);
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float *__res
     }
 }
 
-int make_args(const snake_mlp_desc *m, MlpArgs &a, const char *fn)
+int make_args(const snake_mlp_desc *m, int64_t R, MlpArgs &a, const char *fn)
 {
     SNAKE_REQUIRE(m != nullptr, SNAKE_ERR_NULL, "%s: MLP descriptor is NULL", fn);
     SNAKE_REQUIRE(m->n_levels >= 1 && (m->n_features == 1 || m->n_features == 2 || m->n_features == 4),
@@ -601,6 +612,9 @@ int make_args(const snake_mlp_desc *m, MlpArgs &a, const char *fn)
                   "%s: bad precision %d", fn, m->precision);
     SNAKE_REQUIRE(m->feat_dtype == SNAKE_F32 || m->feat_dtype == SNAKE_BF16, SNAKE_ERR_INVALID_ARG,
                   "%s: bad feat_dtype %d", fn, m->feat_dtype);
+    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "%s: R < 0", fn);
+    a.R = R;
+    a.err = nullptr;
     a.L = m->n_levels;
     a.F = m->n_features;
     a.n_feat = a.L * a.F;
@@ -655,23 +669,23 @@ extern "C" {
 int64_t snake_mlp_param_count(const snake_mlp_desc *m)
 {
     MlpArgs a;
-    if (make_args(m, a, __func__)) return -1;
+    if (make_args(m, 0, a, __func__)) return -1;
     return a.P;
 }
 
 size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m)
 {
     MlpArgs a;
-    if (make_args(m, a, __func__)) return 0;
+    if (make_args(m, 0, a, __func__)) return 0;
     return (size_t)kMaxBwdBlocks * (size_t)a.P * sizeof(float);
 }
 
 int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat, const float *view,
-                  const float *sun, const int32_t *ray_id, const int32_t *sample_idx, int64_t n,
+                  const float *sun, const int32_t *ray_id, int32_t R, const int32_t *sample_idx, int64_t n,
                   const int64_t *n_dev, float *sigma, float *rgb, snake_stream_t stream)
 {
     MlpArgs a;
-    int rc = make_args(m, a, __func__);
+    int rc = make_args(m, R, a, __func__);
     if (rc) return rc;
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_mlp_fwd: n < 0");
     if (n == 0) return SNAKE_OK;
@@ -683,6 +697,7 @@ int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *fea
     SNAKE_NOT_NULL(rgb);
     SNAKE_REQUIRE(a.n_dir == 3 || sun != nullptr, SNAKE_ERR_NULL, "snake_mlp_fwd: sun is NULL with n_dir = 6");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    a.err = device_error_word();
     const bool bf = m->precision == SNAKE_BF16, fb = m->feat_dtype == SNAKE_BF16;
 #define SNAKE_MLP_FWD(P, C)                                                                                  \
     if (fb)                                                                                                  \
@@ -708,12 +723,13 @@ int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *fea
 }
 
 int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat, int64_t feat_ld,
-                  const float *view, const float *sun, const int32_t *ray_id, const int32_t *sample_idx, int64_t n,
-                  const int64_t *n_dev, const float *dsigma, const float *drgb, float *dW, float *dfeat,
-                  void *workspace, size_t workspace_bytes, snake_stream_t stream)
+                  const float *view, const float *sun, const int32_t *ray_id, int32_t R,
+                  const int32_t *sample_idx, int64_t n, const int64_t *n_dev, const float *dsigma,
+                  const float *drgb, float *dW, float *dfeat, void *workspace, size_t workspace_bytes,
+                  snake_stream_t stream)
 {
     MlpArgs a;
-    int rc = make_args(m, a, __func__);
+    int rc = make_args(m, R, a, __func__);
     if (rc) return rc;
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_mlp_bwd: n < 0");
     if (n == 0) return SNAKE_OK;
@@ -733,6 +749,7 @@ int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *fea
                   "snake_mlp_bwd: workspace needs %zu bytes", need);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     float *partial = static_cast<float *>(workspace);
+    a.err = device_error_word();
     const bool bf = m->precision == SNAKE_BF16, fb = m->feat_dtype == SNAKE_BF16;
 #define SNAKE_MLP_BWD(P, C)                                                                                     \
     if (fb)                                                                                                     \

@@ -10,14 +10,12 @@
 #include <math.h>
 
 #include "common.h"
+#include "scan.h"
 
 namespace snake {
 namespace {
 
 constexpr int kMaxTiles = 16;
-constexpr int kScanBlock = 256;
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kScanBlock * kScanItems;  // counts per scan block
 
 struct Boxes {
     double b[kMaxTiles][6];
@@ -147,91 +145,6 @@ __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ r
     }
 }
 
-// ---- exclusive scan of int32 counts ---------------------------------------
-__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *total, int64_t *sh)
-{
-    // 256 threads = 4 waves; sh holds 4 wave totals
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t inc = v;
-#pragma unroll
-    for (int dd = 1; dd < 64; dd <<= 1) {
-        int64_t u = __shfl_up(inc, dd, 64);
-        if (l >= dd) inc += u;
-    }
-    if (l == 63) sh[w] = inc;
-    __syncthreads();
-    int64_t before = 0, all = 0;
-#pragma unroll
-    for (int i = 0; i < kScanBlock / 64; ++i) {
-        if (i < w) before += sh[i];
-        all += sh[i];
-    }
-    __syncthreads();
-    *total = all;
-    return before + inc - v;
-}
-
-__global__ __launch_bounds__(kScanBlock) void scan_partial_kernel(const int32_t *__restrict__ counts,
-                                                                  int R, int64_t *__restrict__ bsum)
-{
-    __shared__ int64_t sh[4];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int64_t s = 0;
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e)
-        if (base + e < R) s += counts[base + e];
-    int64_t tot;
-    block_exclusive_scan(s, &tot, sh);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(kScanBlock) void scan_top_kernel(int64_t *__restrict__ bsum, int nb,
-                                                              int64_t cap, int64_t *__restrict__ n_out,
-                                                              unsigned int *__restrict__ err)
-{
-    __shared__ int64_t sh[4];
-    int64_t carry = 0;
-    for (int base = 0; base < nb; base += kScanBlock) {
-        int i = base + threadIdx.x;
-        int64_t v = i < nb ? bsum[i] : 0;
-        int64_t tot;
-        int64_t ex = block_exclusive_scan(v, &tot, sh);
-        if (i < nb) bsum[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        if (n_out) *n_out = carry;
-        if (carry > cap && err) atomicOr(err, (unsigned)SNAKE_DEVERR_CAPACITY);
-    }
-}
-
-// start[r * stride] = exclusive prefix; count_dst[r * stride] = count (if given)
-__global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const int32_t *__restrict__ counts, int R,
-                                                                const int64_t *__restrict__ bsum,
-                                                                int32_t *__restrict__ start, int stride,
-                                                                int32_t *__restrict__ count_dst)
-{
-    __shared__ int64_t sh[4];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int32_t c[kScanItems];
-    int64_t s = 0;
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        c[e] = (base + e < R) ? counts[base + e] : 0;
-        s += c[e];
-    }
-    int64_t tot;
-    int64_t ex = block_exclusive_scan(s, &tot, sh) + bsum[blockIdx.x];
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        if (base + e < R) {
-            start[(base + e) * stride] = (int32_t)ex;
-            if (count_dst) count_dst[(base + e) * stride] = c[e];
-        }
-        ex += c[e];
-    }
-}
-
 // ---- fill: one wavefront per ray, one lane per sample -----------------------
 template <int KMAX>
 __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro,
@@ -328,7 +241,7 @@ struct ScanWs {
 size_t scan_ws_bytes(int32_t R)
 {
     size_t r = (size_t)(R > 0 ? R : 1);
-    size_t nb = (r + kScanTile - 1) / kScanTile;
+    size_t nb = (size_t)scan::scan_blocks((int64_t)r);
     return 2 * ((r * 4 + 255) / 256 * 256) + nb * 8 + 256;
 }
 
@@ -341,17 +254,14 @@ ScanWs carve(void *ws, int32_t R)
     s.counts = reinterpret_cast<int32_t *>(p);
     s.offs = reinterpret_cast<int32_t *>(p + a);
     s.bsum = reinterpret_cast<int64_t *>(p + 2 * a);
-    s.nb = (int)((r + kScanTile - 1) / kScanTile);
+    s.nb = scan::scan_blocks((int64_t)r);
     return s;
 }
 
 void launch_scan(const ScanWs &w, int R, int32_t *start, int stride, int32_t *count_dst, int64_t cap,
                  int64_t *n_out, hipStream_t st)
 {
-    unsigned int *err = device_error_word();
-    scan_partial_kernel<<<w.nb, kScanBlock, 0, st>>>(w.counts, R, w.bsum);
-    scan_top_kernel<<<1, kScanBlock, 0, st>>>(w.bsum, w.nb, cap, n_out, err);
-    scan_apply_kernel<<<w.nb, kScanBlock, 0, st>>>(w.counts, R, w.bsum, start, stride, count_dst);
+    scan::launch_scan(w.counts, R, w.bsum, start, stride, count_dst, cap, n_out, device_error_word(), st);
 }
 
 }  // namespace

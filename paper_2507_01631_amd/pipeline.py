@@ -48,7 +48,7 @@ class TileNeRF:
     def __init__(self, *, res, n_features, log2_table, n_dir, colour_layers, colour_out,
                  boxes, zband=None, samples=64, early_stop=0.0, precision="fp32",
                  table=None, mlp_params=None, max_rays=4096, lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-15, device="cuda"):
+                 eps=1e-15, hash_bwd="binned", hash_ws_gib=16.0, device="cuda"):
         self.device = torch.device(device)
         self.res = [int(r) for r in res]
         self.F = int(n_features)
@@ -80,8 +80,13 @@ class TileNeRF:
         self.v_w = torch.zeros_like(self.params)
         self.g_w = torch.zeros_like(self.params)
         self.lr, (self.b1, self.b2), self.eps = float(lr), betas, float(eps)
+        # "binned": sort corner gradients by table slot and sum them in LDS;
+        # "atomic": one FP32 atomic add per corner contribution
+        assert hash_bwd in ("binned", "atomic")
+        self.hash_bwd, self.hash_ws_gib = hash_bwd, float(hash_ws_gib)
         self.step_count = 0
         self.R = 0
+        self.R_cur = 0
         self.alloc(max_rays)
 
     # -- buffers -----------------------------------------------------------
@@ -118,19 +123,33 @@ class TileNeRF:
         self.ws_sample = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=dev)
         self.ws_mlp = torch.empty(L.snake_mlp_bwd_workspace_bytes(self.mlp), dtype=torch.uint8,
                                   device=dev)
+        self.ws_hash = None
+        if self.hash_bwd == "binned":
+            # as many levels per pass as fit in the budget (at least one)
+            budget = int(self.hash_ws_gib * (1 << 30))
+            nlev = len(self.res)
+            lg = 1
+            for c in range(nlev, 0, -1):
+                if cap * c * 8 <= 2**31 - 1 and \
+                        L.snake_hashgrid_bwd_workspace_bytes(self.grid, self.K, cap, c) <= budget:
+                    lg = c
+                    break
+            nbytes = L.snake_hashgrid_bwd_workspace_bytes(self.grid, self.K, cap, lg)
+            self.ws_hash = torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
     # -- stages ------------------------------------------------------------
     def sample(self, rays_o, rays_d, R, samples_per_ray=None, stream=None):
+        self.R_cur = int(R)
         L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S,
                                  None, self.packed_info, self.t0, self.t1, self.pos, self.ray_id,
                                  self.tile_id, self.view, self.cap, self.n_out, self.ws_sample,
                                  stream)
 
     def field_fwd(self, sun=None, stream=None):
-        L.snake_hashgrid_fwd(self.grid, self.table, self.pos, self.tile_id, None, self.cap, self.n_out,
-                             self.feat, None, stream)
-        L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, sun, self.ray_id, None, self.cap,
-                        self.n_out, self.sigma, self.rgb, stream)
+        L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.pos, self.tile_id, None, self.cap,
+                             self.n_out, self.feat, None, stream)
+        L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, sun, self.ray_id, self.R_cur, None,
+                        self.cap, self.n_out, self.sigma, self.rgb, stream)
 
     def render(self, R, target=None, loss_scale=0.0, stream=None):
         L.snake_composite_fwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R,
@@ -148,11 +167,11 @@ class TileNeRF:
             idx, n_dev = self.alive_idx, self.n_alive_total
         else:
             idx, n_dev = None, self.n_out
-        L.snake_mlp_bwd(self.mlp, self.params, self.feat, self.cap, self.view, sun, self.ray_id, idx,
+        L.snake_mlp_bwd(self.mlp, self.params, self.feat, self.cap, self.view, sun, self.ray_id, R, idx,
                         self.cap, n_dev, self.dsigma, self.drgb, self.g_w, self.dfeat, self.ws_mlp,
                         stream)
-        L.snake_hashgrid_bwd(self.grid, self.pos, self.tile_id, idx, self.cap, n_dev, self.dfeat,
-                             self.g_t, stream)
+        L.snake_hashgrid_bwd(self.grid, self.K, self.pos, self.tile_id, idx, self.cap, n_dev, self.dfeat,
+                             self.g_t, self.ws_hash, stream)
         return n_dev
 
     def adam(self, stream=None):

@@ -76,30 +76,35 @@ def test_host_side_argument_errors(L):
     SNAKE_ERR_INVALID_ARG, SNAKE_ERR_NULL, SNAKE_ERR_UNSUPPORTED = -1, -2, -4
     # grid descriptor checks
     g = L.grid_desc([16, 32], 3, 14)
-    assert so.snake_hashgrid_fwd(ctypes.byref(g), None, None, None, None, 10, None, None, None,
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), 1, None, None, None, None, 10, None, None, None,
                                  None) == SNAKE_ERR_UNSUPPORTED
     assert "n_features" in L.snake_last_error()
     g = L.grid_desc([16, 32], 2, 30)
-    assert so.snake_hashgrid_bwd(ctypes.byref(g), None, None, None, 10, None, None, None,
-                                 None) == SNAKE_ERR_INVALID_ARG
-    g = L.grid_desc([16, 0], 2, 14)
-    assert so.snake_hashgrid_fwd(ctypes.byref(g), None, None, None, None, 10, None, None, None,
+    assert so.snake_hashgrid_bwd(ctypes.byref(g), 1, None, None, None, 10, None, None, None, None, 0,
                                  None) == SNAKE_ERR_INVALID_ARG
     g = L.grid_desc([16, 32], 2, 14)
-    assert so.snake_hashgrid_fwd(ctypes.byref(g), None, None, None, None, 10, None, None, None,
+    assert so.snake_hashgrid_bwd(ctypes.byref(g), 0, None, None, None, 10, None, None, None, None, 0,
+                                 None) == SNAKE_ERR_INVALID_ARG
+    g = L.grid_desc([16, 0], 2, 14)
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), 1, None, None, None, None, 10, None, None, None,
+                                 None) == SNAKE_ERR_INVALID_ARG
+    g = L.grid_desc([16, 32], 2, 14)
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), 1, None, None, None, None, 10, None, None, None,
                                  None) == SNAKE_ERR_NULL
-    assert so.snake_hashgrid_fwd(None, None, None, None, None, 10, None, None, None, None) == SNAKE_ERR_NULL
+    assert so.snake_hashgrid_fwd(ctypes.byref(g), 300, None, None, None, None, 10, None, None, None,
+                                 None) == SNAKE_ERR_INVALID_ARG
+    assert so.snake_hashgrid_fwd(None, 1, None, None, None, None, 10, None, None, None, None) == SNAKE_ERR_NULL
     # MLP descriptor checks
     m = L.mlp_desc(8, 2, 5, 1, 3)
-    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, None, 16, None, None, None,
+    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, 1, None, 16, None, None, None,
                             None) == SNAKE_ERR_INVALID_ARG
     m = L.mlp_desc(8, 2, 3, 3, 3)
-    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, None, 16, None, None, None,
+    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, 1, None, 16, None, None, None,
                             None) == SNAKE_ERR_UNSUPPORTED
     m = L.mlp_desc(17, 2, 3, 1, 3)
     assert so.snake_mlp_param_count(ctypes.byref(m)) == -1
     m = L.mlp_desc(8, 2, 6, 2, 4)
-    assert so.snake_mlp_bwd(ctypes.byref(m), None, None, 0, None, None, None, None, 16, None, None,
+    assert so.snake_mlp_bwd(ctypes.byref(m), None, None, 0, None, None, None, 1, None, 16, None, None,
                             None, None, None, None, 0, None) == SNAKE_ERR_INVALID_ARG
     # sampler checks (boxes are host memory)
     boxes = np.array([[0, 0, 0, 1, 1, 1]], np.float64)

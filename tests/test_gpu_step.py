@@ -40,30 +40,74 @@ def gpu_step(w, precision="fp32"):
     out = dict(n=int(host(nerf.n_out)[0]), n_bwd=int(host(n_dev)[0]), loss=float(host(nerf.loss)[0]),
                rgb_out=host(nerf.rgb_out), opacity=host(nerf.opacity), depth=host(nerf.depth),
                n_alive=host(nerf.n_alive), dtable=host(nerf.g_t), dW=host(nerf.g_w))
-    n = out["n"]
+    n, nb = out["n"], out["n_bwd"]
     out["sigma"], out["rgb"] = host(nerf.sigma)[:n], host(nerf.rgb)[:n]
+    out["dsigma"], out["drgb"] = host(nerf.dsigma)[:n], host(nerf.drgb)[:n]
+    # dfeat is compact over the samples kept by early stop: scatter back to [n][32]
+    idx = host(nerf.alive_idx)[:nb] if w.early_stop > 0 else np.arange(nb)
+    df = np.zeros((n, 32))
+    df[idx, :len(nerf.res) * nerf.F] = host(nerf.dfeat)[:, :nb, :].transpose(1, 0, 2).reshape(nb, -1)
+    out["dfeat"] = df
     nerf.adam()
     sync()
     out["table_new"], out["mlp_new"] = host(nerf.table), host(nerf.params)
     return out
 
 
-def check_step(g, o, prec):
-    vt, gt = (1e-2, 3e-2) if prec == "bf16" else (1e-5, 1e-4)
+def _rel(a, b):
+    a, b = np.ravel(a).astype(np.float64), np.ravel(b).astype(np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)), \
+        float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def check_step(g, o, prec, w, orc):
+    """FP32: values within 1e-5, gradients within 1e-4 (relative L2 over each
+    tensor; elementwise against max|ref| on every sample whose ReLU decisions
+    are not within rounding of a kink, and on every table entry such samples do
+    not touch).  BF16: values within 1e-2, gradients within 1e-1 relative L2."""
     assert g["n"] == o["n_total"]
-    assert_values(g["sigma"], o["sigma"], vt, vt * 1e-2, "sigma")
-    assert_values(g["rgb"], o["rgb"], vt, vt * 1e-2, "rgb")
-    assert_values(g["rgb_out"], o["comp"]["rgb"], vt, 1e-7, "rgb_out")
-    assert_values(g["loss"], o["loss"], vt, 0.0, "loss")
-    assert_grad(g["dtable"], o["dtable"], gt, "dtable")
-    assert_grad(g["dW"], o["dW"], gt, "dW")
+    for k, ref in (("dsigma", o["dsigma"]), ("drgb", o["drgb"]), ("dfeat", o["dfeat"]),
+                   ("dtable", o["dtable"]), ("dW", o["dW"])):
+        print("%-7s rel L2 %.3g  rel max %.3g" % ((k,) + _rel(g[k], ref)))
+    if prec == "bf16":
+        assert_values(np.log(g["sigma"]), np.log(o["sigma"]), 0.0, 5e-2, "log sigma")
+        assert_values(g["rgb"], o["rgb"], 0.0, 1e-2, "rgb")
+        assert_values(g["rgb_out"], o["comp"]["rgb"], 0.0, 1e-2, "rgb_out")
+        assert_values(g["loss"], o["loss"], 1e-2, 0.0, "loss")
+        for k in ("dsigma", "drgb", "dtable", "dW"):
+            assert _rel(g[k], o[k])[0] < 1e-1, k
+        return
+    assert_values(g["sigma"], o["sigma"], 1e-5, 1e-7, "sigma")
+    assert_values(g["rgb"], o["rgb"], 1e-5, 1e-7, "rgb")
+    assert_values(g["rgb_out"], o["comp"]["rgb"], 1e-5, 1e-7, "rgb_out")
+    assert_values(g["loss"], o["loss"], 1e-5, 0.0, "loss")
+    assert_grad(g["dsigma"], o["dsigma"], 1e-4, "dsigma")
+    assert_grad(g["drgb"], o["drgb"], 1e-4, "drgb")
+    assert_grad(g["dW"], o["dW"], 1e-4, "dW")
+    # ReLU decisions within FP32 rounding of a kink may go either way
+    smp = o["sample"]
+    margin = orc.mlp_margin(w.mlp, w.mlp_params, o["feat"], smp["view"], smp["ray_id"], sun=w.sun)
+    amb = margin < 1e-5
+    print("kink-ambiguous samples: %d of %d" % (amb.sum(), amb.size))
+    assert amb.mean() < 2e-2
+    ok = ~amb
+    assert _rel(g["dfeat"], o["dfeat"])[0] <= 1e-4
+    assert_grad(g["dfeat"][ok], o["dfeat"][ok], 1e-4, "dfeat (unambiguous samples)")
+    assert _rel(g["dtable"], o["dtable"])[0] <= 1e-4
+    mask = np.ones(o["dtable"].shape, dtype=bool)
+    if amb.any():
+        _, idx = orc.hashgrid_fwd(o["res"], w.grid.log2_table, w.table, smp["pos"][amb],
+                                  smp["tile_id"][amb], 32, return_index=True)
+        tid = smp["tile_id"][amb].astype(np.int64)
+        for lvl in range(idx.shape[1]):
+            mask[tid[:, None], lvl, idx[:, lvl, :].astype(np.int64)] = False
+    assert_grad(g["dtable"][mask], o["dtable"][mask], 1e-4, "dtable (entries of unambiguous samples)")
     # Adam's first step is lr * sign(g): compare where the sign is not in doubt
-    cut = 1e-1 if prec == "bf16" else 1e-3
     gref = o["dtable"].ravel()
-    sel = np.abs(gref) > cut * np.abs(gref).max()
+    sel = (np.abs(gref) > 1e-3 * np.abs(gref).max()) & mask.ravel()
     assert_values(g["table_new"].ravel()[sel], o["table_new"].ravel()[sel], 1e-4, 1e-6, "table after Adam")
     gw = o["dW"]
-    sel = np.abs(gw) > cut * np.abs(gw).max()
+    sel = np.abs(gw) > 1e-3 * np.abs(gw).max()
     assert_values(g["mlp_new"][sel], o["mlp_new"][sel], 1e-4, 1e-6, "MLP after Adam")
 
 
@@ -72,7 +116,7 @@ def test_tiny_tile_step(orc, prec):
     w = synth.tiny_tile(seed=0)
     g = gpu_step(w, prec)
     o = orc.train_step(w)
-    check_step(g, o, prec)
+    check_step(g, o, prec, w, orc)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -83,14 +127,15 @@ def test_full_tile_step_reduced_rays(orc, prec):
     w = synth.full_tile(seed=0, n_rays=1024)
     rng = np.random.default_rng(8)
     w.table = rng.uniform(-1, 1, size=w.table.shape).astype(np.float32)
-    w.mlp_params[64 * 32:64 * 32 + 64] *= np.float32(6.0)     # density-logit row
+    row = slice(64 * 32, 64 * 32 + 64)                         # density-logit row
+    w.mlp_params[row] = np.abs(w.mlp_params[row]) * np.float32(4.0)
     g = gpu_step(w, prec)
     assert np.sum(g["n_alive"]) < 0.9 * g["n"]               # early stop is active
     o = orc.train_step(w, alive=g["n_alive"])
     if prec == "fp32":
         ref_alive = orc.train_step(w)["n_alive"]
         assert np.mean(g["n_alive"] != ref_alive) < 0.01
-    check_step(g, o, prec)
+    check_step(g, o, prec, w, orc)
 
 
 def test_autograd_function_matches_oracle_and_fd(orc):

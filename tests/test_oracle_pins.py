@@ -594,3 +594,67 @@ def test_train_step_thread_count_independent(orc, monkeypatch):
     a = orc.train_step(w)
     b = orc.train_step(w)
     assert np.array_equal(a["dtable"], b["dtable"]) and np.array_equal(a["dW"], b["dW"])
+
+
+# ---------------------------------------------------------------------------
+# diagnostics: ReLU margin and BF16-rounding emulation
+# ---------------------------------------------------------------------------
+def test_mlp_margin_invariances(orc):
+    rng = np.random.default_rng(16)
+    m = synth.tiny_tile().mlp
+    w = synth.init_mlp(rng, m)
+    feat = rng.normal(size=(50, 32))
+    feat[:, 16:] = 0.0
+    view = rng.normal(size=(50, 3)).astype(np.float32)
+    rid = np.arange(50, dtype=np.int32)
+    mg = orc.mlp_margin(m, w, feat, view, rid)
+    assert np.all(mg >= 0) and np.all(mg <= 1)
+    # doubling the first density layer and halving the second is exact (powers
+    # of two): every ratio and the embedding are unchanged, so is the margin
+    w2 = w.copy()
+    w2[:64 * 32] *= np.float32(2.0)
+    w2[64 * 32:64 * 32 + 16 * 64] *= np.float32(0.5)
+    mg2 = orc.mlp_margin(m, w2, feat, view, rid)
+    np.testing.assert_allclose(mg, mg2, rtol=1e-12)
+    # a uniformly shifted input that keeps every sign changes the margin
+    assert not np.allclose(mg, orc.mlp_margin(m, w, feat + 3.0 * (feat != 0), view, rid))
+    # a pre-activation that is exactly zero gives margin 0
+    f0 = np.zeros((1, 32))
+    f0[0, 0], f0[0, 1] = 1.0, 1.0
+    w0 = w.copy()
+    w0[0], w0[1] = np.float32(0.5), np.float32(-0.5)       # unit 0: 0.5 - 0.5 = 0
+    assert orc.mlp_margin(m, w0, f0, view[:1], rid[:1])[0] == 0.0
+
+
+@pytest.mark.parametrize("which", ["tiny", "full"])
+def test_bf16_emulation_matches_torch_rounding(orc, which):
+    """The emulated BF16 forward equals a NumPy chain whose rounding points use
+    torch's float32 -> bfloat16 conversion (round to nearest even)."""
+    import torch
+    rng = np.random.default_rng(17)
+    m = synth.tiny_tile().mlp if which == "tiny" else synth.MlpConfig(
+        feat_real=32, n_dir=6, colour_layers=2, colour_out=4)
+    w = synth.init_mlp(rng, m)
+    n = 300
+    feat = rng.normal(scale=0.5, size=(n, 32))
+    view = rng.normal(size=(n, 3)).astype(np.float32)
+    sun = rng.normal(size=(n, 3)).astype(np.float32)
+    rid = np.arange(n, dtype=np.int32)
+    bf = lambda a: torch.tensor(np.asarray(a, np.float64)).float().bfloat16().double().numpy()
+    shapes = synth.mlp_param_shapes(m)
+    mats, o = [], 0
+    for (a, b) in shapes:
+        mats.append(bf(w[o:o + a * b]).reshape(a, b))
+        o += a * b
+    h = bf(np.maximum(bf(feat) @ mats[0].T, 0))
+    out = h @ mats[1].T
+    cin = [bf(out[:, 1:]), bf(view)] + ([bf(sun)] if m.n_dir == 6 else [])
+    g = bf(np.maximum(np.concatenate(cin, 1) @ mats[2].T, 0))
+    for li in range(m.colour_layers - 1):
+        g = bf(np.maximum(g @ mats[3 + li].T, 0))
+    y = g @ mats[-1].T
+    sg = lambda v: 1 / (1 + np.exp(-v))
+    rgb = sg(y[:, :3]) if m.colour_out == 3 else sg(y[:, :3]) * sg(y[:, 3:4])
+    s_e, c_e = orc.mlp_fwd_bf16emu(m, w, feat, view, rid, sun=sun if m.n_dir == 6 else None)
+    np.testing.assert_allclose(s_e, np.exp(out[:, 0]), rtol=1e-12)
+    np.testing.assert_allclose(c_e, rgb, rtol=1e-12, atol=1e-15)
