@@ -164,6 +164,52 @@ def roofline(form, wl, precision, R):
     return out
 
 
+def recompute_check(args):
+    """Small-tile shapes (L=8, F=2, T=2^14, MLP 32-64-16 / 18-64-3, FP32) at
+    2^16 rays x 64 samples: the whole step with the MLP adjoint recomputing its
+    activations against the same step with the forward storing them.  Peak
+    device memory of each run comes from torch's allocator, which owns every
+    buffer."""
+    import torch
+    import synth
+    R = args.recompute_rays
+    wl = synth.tiny_tile(seed=2, n_rays=R)
+    dev = "cuda:0"
+    ro, rd = torch.as_tensor(wl.rays_o).to(dev), torch.as_tensor(wl.rays_d).to(dev)
+    tg = torch.as_tensor(wl.target).to(dev)
+    out = {}
+    for rec in (True, False):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        from paper_2507_01631_amd import TileNeRF, level_resolutions
+        g, m = wl.grid, wl.mlp
+        nerf = TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
+                        log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
+                        colour_out=m.colour_out, boxes=wl.boxes, samples=wl.samples_per_ray,
+                        precision="fp32", table=wl.table, mlp_params=wl.mlp_params, max_rays=R,
+                        lr=wl.lr, recompute=rec, device=dev)
+        for _ in range(3):
+            nerf.train_step(ro, rd, tg)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = 10
+        a.record()
+        for _ in range(n):
+            nerf.train_step(ro, rd, tg)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / n
+        ns = int(nerf.n_out.item())
+        out["on" if rec else "off"] = {"ms_per_step": round(ms, 4), "samples_per_s": ns / (ms * 1e-3),
+                                       "peak_mem_gib": round((torch.cuda.max_memory_allocated() - base) / 2**30, 4)}
+        del nerf
+    out["config"] = "tiny_tile shapes, %d rays x %d samples, fp32" % (R, wl.samples_per_ray)
+    log("  recompute on/off: %s" % json.dumps(out))
+    return out
+
+
 def cpu_baseline(args):
     import oracle
     import synth
@@ -188,7 +234,11 @@ def main():
     ap.add_argument("--batches", type=int, default=2, help="distinct ray batches cycled through")
     ap.add_argument("--precision", choices=["bf16", "fp32", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=1 << 14)
+    ap.add_argument("--cpu-rays", type=int, default=1 << 17)
+    ap.add_argument("--recompute-rays", type=int, default=1 << 16)
+    ap.add_argument("--no-recompute-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run three 256 MiB device copies (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs the single-GPU tile step only; --gpus %d is not supported "
@@ -205,6 +255,15 @@ def main():
     dev = "cuda:0"
     pool = (torch.as_tensor(wl.rays_o).to(dev), torch.as_tensor(wl.rays_d).to(dev),
             torch.as_tensor(wl.target).to(dev), torch.as_tensor(wl.sun).to(dev))
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling hardware byte counters
+        a = torch.empty(1 << 28, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d bytes" % a.numel())
+        del a, b
     forms = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
     res = {}
     for p in forms:
@@ -237,6 +296,8 @@ def main():
         line["%s_form" % p] = {"value": g["value"], "ms_per_step": g["ms_per_step"],
                                "samples_alive_per_step": g["samples_alive"],
                                "stages_ms": {k: round(v, 4) for k, v in g["stage_ms"].items()}}
+    if not args.no_recompute_check:
+        line["recompute"] = recompute_check(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(args)

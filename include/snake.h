@@ -72,6 +72,7 @@ typedef enum {
 #define SNAKE_DEVERR_CAPACITY 1u  /* sampler: packed samples exceed `cap` */
 #define SNAKE_DEVERR_TILE_ID 2u   /* a tile_id >= K (the sample is dropped) */
 #define SNAKE_DEVERR_RAY_ID 4u    /* a ray_id >= R (the sample is dropped) */
+#define SNAKE_DEVERR_INTERNAL 8u  /* an internal consistency check failed (nothing written out of range) */
 
 typedef enum { SNAKE_F32 = 0, SNAKE_BF16 = 1 } snake_dtype;
 
@@ -138,6 +139,42 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
 int snake_pack_alive(const int32_t *packed_info, const int32_t *n_alive, int32_t R,
                      int32_t *idx_out, int64_t cap, int64_t *n_out,
                      void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
+/*
+ * Ray acceptance of the 2x2 sliding window (Sec. 4.4): while a window of
+ * NeRF tiles is loaded, only rays that cross no other tile are trained on.
+ * The window's tiles share the altitude band zband = [z_lo, z_hi] and cover
+ * the rectangle window = [x_lo, y_lo, x_hi, y_hi] (both HOST pointers,
+ * copied at call time).  Ray r is accepted when its chord through the band
+ * (t >= 0) is non-empty and bounded (d_z != 0) and both chord end points
+ * o + t d have x, y inside the closed rectangle; FP64, no FMA contraction.
+ * Outputs: accept [R] uint8 (may be NULL), idx_out [R] int32 = the accepted
+ * ray indices in increasing order, *n_out (device int64) = their count.
+ * Workspace: snake_sample_workspace_bytes(R).
+ */
+int snake_window_accept(const double *rays_o, const double *rays_d, int32_t R,
+                        const double *window, const double *zband, uint8_t *accept,
+                        int32_t *idx_out, int64_t *n_out,
+                        void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
+/*
+ * Stable partition of n samples by NeRF tile, for the window step where each
+ * loaded tile has its own networks (Sec. 4.4): perm [n] int32 lists the
+ * sample indices tile by tile (increasing within a tile), inv [n] int32 (may
+ * be NULL) is its inverse, and tile_start [K+2] int64 (device) bounds the
+ * groups: tile k is perm[tile_start[k] .. tile_start[k+1]); entries from
+ * tile_start[K] to tile_start[K+1] = *n_dev (or n) hold samples whose tile
+ * id is >= K (raising SNAKE_DEVERR_TILE_ID).  tile_id may be NULL when K == 1.
+ * Optional gathers into the new order (each may be NULL): pos_out [n][3],
+ * tile_out [n], ray_out [n].  1 <= K <= 16, n < 2^31.
+ * Workspace: snake_tile_partition_workspace_bytes(K).
+ */
+size_t snake_tile_partition_workspace_bytes(int32_t K);
+int snake_tile_partition(const uint8_t *tile_id, const float *pos, const int32_t *ray_id,
+                         int64_t n, const int64_t *n_dev, int32_t K, int32_t *perm,
+                         int32_t *inv, int64_t *tile_start, float *pos_out, uint8_t *tile_out,
+                         int32_t *ray_out, void *workspace, size_t workspace_bytes,
+                         snake_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Multiresolution hash encoding (Sec. 4.1; the NGP representation)          */
@@ -217,24 +254,32 @@ int64_t snake_mlp_param_count(const snake_mlp_desc *m);
  * sample (read through sample_idx); a ray id outside [0, R) gives sigma = 0,
  * rgb = 0 and raises SNAKE_DEVERR_RAY_ID.  Writes sigma [n], rgb [n][3].  BF16
  * precision rounds inputs, weights and hidden activations to bf16 (RNE) and
- * accumulates in FP32. */
+ * accumulates in FP32.  With F == 2, feat is aligned to one row (2 elements);
+ * a misaligned pointer returns SNAKE_ERR_ALIGN.
+ * act: NULL, or [n][snake_mlp_act_width(m)] float (16-byte aligned) that
+ * receives every sample's hidden and output activations for an adjoint
+ * that does not recompute them (samples with a bad ray id are not written). */
+int32_t snake_mlp_act_width(const snake_mlp_desc *m);
 int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat,
                   const float *view, const float *sun, const int32_t *ray_id, int32_t R,
                   const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
-                  float *sigma, float *rgb, snake_stream_t stream);
+                  float *sigma, float *rgb, float *act, snake_stream_t stream);
 
-/* Adjoint, recomputing the activations from feat.  feat, ray_id, dsigma
+/* Adjoint.  act == NULL: activations are recomputed from feat; otherwise
+ * they are read from act as stored by snake_mlp_fwd (read through
+ * sample_idx like feat), with identical results.  feat, ray_id, dsigma
  * and drgb are read through sample_idx (feat level-major with level stride
  * feat_ld >= every index read); dfeat [L][n][F] float is written compact at
  * j (zero for a sample whose ray id is outside [0, R), which is flagged with
  * SNAKE_DEVERR_RAY_ID).  dW [P] += the sum over samples, reduced in a fixed
- * order (deterministic for a given n).  Workspace: snake_mlp_bwd_workspace_bytes(m). */
+ * order (deterministic for a given n).  With F == 2, feat and dfeat are
+ * aligned to one row.  Workspace: snake_mlp_bwd_workspace_bytes(m). */
 size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m);
 int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat,
                   int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
                   int32_t R, const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
-                  const float *dsigma, const float *drgb, float *dW, float *dfeat,
-                  void *workspace, size_t workspace_bytes, snake_stream_t stream);
+                  const float *dsigma, const float *drgb, const float *act, float *dW,
+                  float *dfeat, void *workspace, size_t workspace_bytes, snake_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Volume rendering and colour-consistency loss (Sec. 2.2, 4.4, 4.5)         */

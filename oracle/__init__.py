@@ -63,6 +63,8 @@ def lib():
                                         _P, _P, _P, _P, _P]
         L.orc_composite_bwd.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _D, _P, _P]
         L.orc_adam_step.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, _I, _D]
+        L.orc_window_accept.argtypes = [_I, _P, _P, _P, _D, _D, _P]
+        L.orc_window_accept.restype = _I64
         _lib = L
     return _lib
 
@@ -219,6 +221,19 @@ def sample_segmented(rays_o, rays_d, boxes, S, zband=None, samples_per_ray=None,
         raise ValueError("oracle sampler: %d samples exceed capacity %d (rc=%d)" % (n, cap, rc))
     return dict(packed_info=info, t0=t0[:n], t1=t1[:n], pos=pos[:n], ray_id=rid[:n],
                 tile_id=tid[:n], view=view, n=n)
+
+
+def window_accept(rays_o, rays_d, window, zband):
+    """Sliding-window ray acceptance (Sec. 4.4): 1 where the ray's chord through
+    the altitude band stays inside the closed XY rectangle of the window.
+    window = (x_lo, y_lo, x_hi, y_hi)."""
+    rays_o = _c(rays_o, np.float64).reshape(-1, 3)
+    rays_d = _c(rays_d, np.float64).reshape(-1, 3)
+    win = _c(window, np.float64).reshape(4)
+    acc = np.zeros(rays_o.shape[0], dtype=np.int32)
+    lib().orc_window_accept(rays_o.shape[0], _ptr(rays_o), _ptr(rays_d), _ptr(win),
+                            float(zband[0]), float(zband[1]), _ptr(acc))
+    return acc
 
 
 # ---------------------------------------------------------------------------

@@ -18,6 +18,8 @@
  *     segments meet exactly on the shared box face), with the UTM-to-local
  *     mapping of Sec. 4.1-4.2 (tile box -> [0,1]^3) and the per-ray segment
  *     distribution of Sec. 4.6.
+ *   - orc_window_accept: which rays a loaded 2x2 window of NeRF tiles may
+ *     train on (Sec. 4.4, sliding window).
  *   - orc_hashgrid_*: the multiresolution hash encoding the paper adopts in
  *     Sec. 4.1 (the NGP representation it cites): per level a grid of
  *     resolution N_l, the 8 cell corners, dense indexing when the grid fits
@@ -227,6 +229,46 @@ int orc_sample_segmented(int R, const double *rays_o, const double *rays_d,
         }
     }
     return 0;
+}
+
+/*
+ * Ray acceptance of the 2x2 sliding window (Sec. 4.4): a ray is used while
+ * the window is loaded only if every NeRF tile it crosses is one of the
+ * window's tiles.  The tiles of a window share the altitude band
+ * [z_lo, z_hi] and together cover the rectangle win = [x_lo, x_hi] x
+ * [y_lo, y_hi], so the test is: the part of the ray (t >= 0) inside the band
+ * is non-empty and bounded, and both of its end points have x, y inside the
+ * closed rectangle (the chord is a segment and the rectangle convex, so the
+ * whole chord is then inside).  A ray parallel to the band planes is
+ * rejected (its chord is unbounded).  accept[r] = 1 or 0; returns the count.
+ */
+int64_t orc_window_accept(int R, const double *rays_o, const double *rays_d,
+                          const double win[4], double z_lo, double z_hi, int32_t *accept)
+{
+    int64_t n = 0;
+    for (int r = 0; r < R; ++r) {
+        const double *o = rays_o + 3 * r, *d = rays_d + 3 * r;
+        int ok = 0;
+        if (d[2] != 0.0) {
+            double ta = (z_lo - o[2]) / d[2];
+            double tb = (z_hi - o[2]) / d[2];
+            double t0 = ta < tb ? ta : tb;
+            double t1 = ta < tb ? tb : ta;
+            if (t0 < 0.0) t0 = 0.0;
+            if (t1 >= t0) {
+                ok = 1;
+                double ts[2] = {t0, t1};
+                for (int e = 0; e < 2; ++e) {
+                    double x = o[0] + ts[e] * d[0];
+                    double y = o[1] + ts[e] * d[1];
+                    if (!(x >= win[0] && x <= win[2] && y >= win[1] && y <= win[3])) ok = 0;
+                }
+            }
+        }
+        accept[r] = ok;
+        n += ok;
+    }
+    return n;
 }
 
 /* ------------------------------------------------------------------ */

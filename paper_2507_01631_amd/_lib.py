@@ -21,13 +21,16 @@ SNAKE_ADAM_ZERO_GRAD = 1
 SNAKE_DEVERR_CAPACITY = 1
 SNAKE_DEVERR_TILE_ID = 2
 SNAKE_DEVERR_RAY_ID = 4
+SNAKE_DEVERR_INTERNAL = 8
 MAX_LEVELS = 32
 
 EXPORTS = (
     "snake_abi_version", "snake_last_error", "snake_check_device_error",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_pack_alive",
+    "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
     "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
-    "snake_mlp_param_count", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd", "snake_mlp_bwd",
+    "snake_mlp_param_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
+    "snake_mlp_bwd",
     "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step",
 )
 
@@ -80,13 +83,17 @@ _SIGS = {
     "snake_sample_segmented": ([_P, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
                                 _I64, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_pack_alive": ([_P, _P, _I32, _P, _I64, _P, _P, _SZ, _P], ctypes.c_int),
+    "snake_window_accept": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "snake_tile_partition_workspace_bytes": ([_I32], _SZ),
+    "snake_tile_partition": ([_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_hashgrid_fwd": ([_P, _I32, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "snake_hashgrid_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_hashgrid_bwd_workspace_bytes": ([_P, _I32, _I64, _I32], _SZ),
     "snake_mlp_param_count": ([_P], _I64),
     "snake_mlp_bwd_workspace_bytes": ([_P], _SZ),
-    "snake_mlp_fwd": ([_P, _P, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
-    "snake_mlp_bwd": ([_P, _P, _P, _I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P],
+    "snake_mlp_act_width": ([_P], _I32),
+    "snake_mlp_fwd": ([_P, _P, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
+    "snake_mlp_bwd": ([_P, _P, _P, _I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _P],
                       ctypes.c_int),
     "snake_composite_fwd": ([_P, _P, _P, _P, _P, _I32, _F, _P, _F, _P, _P, _P, _P, _P, _P],
                             ctypes.c_int),
@@ -178,6 +185,28 @@ def snake_pack_alive(packed_info, n_alive, R, idx_out, cap, n_out, workspace, st
     _check("snake_pack_alive", rc)
 
 
+def snake_window_accept(rays_o, rays_d, R, window, zband, accept, idx_out, n_out, workspace, stream=None):
+    win = _host_f64(window).reshape(4)
+    zb = _host_f64(zband).reshape(2)
+    rc = lib().snake_window_accept(_ptr(rays_o), _ptr(rays_d), int(R), win.ctypes.data, zb.ctypes.data,
+                                   _ptr(accept), _ptr(idx_out), _ptr(n_out), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream(stream))
+    _check("snake_window_accept", rc)
+
+
+def snake_tile_partition_workspace_bytes(K) -> int:
+    return int(lib().snake_tile_partition_workspace_bytes(int(K)))
+
+
+def snake_tile_partition(tile_id, pos, ray_id, n, n_dev, K, perm, inv, tile_start, pos_out, tile_out,
+                         ray_out, workspace, stream=None):
+    rc = lib().snake_tile_partition(_ptr(tile_id), _ptr(pos), _ptr(ray_id), int(n), _ptr(n_dev), int(K),
+                                    _ptr(perm), _ptr(inv), _ptr(tile_start), _ptr(pos_out), _ptr(tile_out),
+                                    _ptr(ray_out), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                    _stream(stream))
+    _check("snake_tile_partition", rc)
+
+
 def snake_hashgrid_fwd(g: GridDesc, K, table, pos, tile_id, sample_idx, n, n_dev, feat, idx_dbg=None,
                        stream=None):
     rc = lib().snake_hashgrid_fwd(ctypes.byref(g), int(K), _ptr(table), _ptr(pos), _ptr(tile_id),
@@ -204,23 +233,27 @@ def snake_mlp_param_count(m: MlpDesc) -> int:
     return int(lib().snake_mlp_param_count(ctypes.byref(m)))
 
 
+def snake_mlp_act_width(m: MlpDesc) -> int:
+    return int(lib().snake_mlp_act_width(ctypes.byref(m)))
+
+
 def snake_mlp_bwd_workspace_bytes(m: MlpDesc) -> int:
     return int(lib().snake_mlp_bwd_workspace_bytes(ctypes.byref(m)))
 
 
 def snake_mlp_fwd(m: MlpDesc, weights, feat, view, sun, ray_id, R, sample_idx, n, n_dev, sigma, rgb,
-                  stream=None):
+                  act=None, stream=None):
     rc = lib().snake_mlp_fwd(ctypes.byref(m), _ptr(weights), _ptr(feat), _ptr(view), _ptr(sun),
                              _ptr(ray_id), int(R), _ptr(sample_idx), int(n), _ptr(n_dev), _ptr(sigma),
-                             _ptr(rgb), _stream(stream))
+                             _ptr(rgb), _ptr(act), _stream(stream))
     _check("snake_mlp_fwd", rc)
 
 
 def snake_mlp_bwd(m: MlpDesc, weights, feat, feat_ld, view, sun, ray_id, R, sample_idx, n, n_dev,
-                  dsigma, drgb, dW, dfeat, workspace, stream=None):
+                  dsigma, drgb, dW, dfeat, workspace, act=None, stream=None):
     rc = lib().snake_mlp_bwd(ctypes.byref(m), _ptr(weights), _ptr(feat), int(feat_ld), _ptr(view),
                              _ptr(sun), _ptr(ray_id), int(R), _ptr(sample_idx), int(n), _ptr(n_dev),
-                             _ptr(dsigma), _ptr(drgb), _ptr(dW), _ptr(dfeat), _ptr(workspace),
+                             _ptr(dsigma), _ptr(drgb), _ptr(act), _ptr(dW), _ptr(dfeat), _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream))
     _check("snake_mlp_bwd", rc)
 

@@ -113,8 +113,28 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const float *
         corners(g, l, x, idx, wt);
         const VT *lev = reinterpret_cast<const VT *>(table + ((tile * g.L + l) << g.log2T) * F);
         VT v[8];
+        if constexpr (F == 2) {
+            // corners q and q^1 differ only in x; when their slots are an
+            // aligned pair (2m, 2m+1) -- half of all pairs, dense or hashed --
+            // one 16-byte load fetches both: one cache-line request, not two
+            const float4 *lev4 = reinterpret_cast<const float4 *>(lev);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = lev[idx[q]];
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t a = idx[2 * p], b = idx[2 * p + 1];
+                if ((a ^ b) == 1u) {
+                    const float4 w4 = lev4[a >> 1];
+                    const float2 lo = make_float2(w4.x, w4.y), hi = make_float2(w4.z, w4.w);
+                    v[2 * p] = (a & 1u) ? hi : lo;
+                    v[2 * p + 1] = (a & 1u) ? lo : hi;
+                } else {
+                    v[2 * p] = lev[a];
+                    v[2 * p + 1] = lev[b];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = lev[idx[q]];
+        }
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             float acc = 0.0f;
@@ -181,11 +201,20 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 //   reduce  per chunk of items: add into a 64 KB LDS copy of the bin's slots,
 //           then flush the bin once with one global atomic per touched slot
 // A pass covers `lg` levels; bins never straddle levels.
+//
+// LDS float atomics are slow on this chip (about 2e11/s) while LDS integer
+// atomics are about 20x faster, so a bin is summed in fixed point: every
+// contribution v becomes the int32 rint(v 2^E), E chosen from the bin's
+// largest |v| so that |q| < 2^30, added into 64-bit slot sums.  Integer sums
+// do not depend on the order of addition.  Consecutive samples of a ray that
+// share a corner are first merged across the wavefront, which shortens the
+// item list on the coarse levels.
 
 constexpr int kBinBlocks = 1024;        // blocks of the count/scatter passes
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
-constexpr int kAccFloats = 16384;       // LDS accumulator, 64 KB
-constexpr int64_t kReduceChunk = 1 << 19;
+constexpr int kAccWords = 8192;         // LDS accumulator: 8192 int64 = 64 KB
+constexpr int64_t kReduceChunk = 1 << 21;
+constexpr int kRU = 8;                  // items in flight per thread in the reduce
 
 struct BinPlan {
     int l0, lg;            // levels [l0, l0 + lg) in this pass
@@ -214,17 +243,54 @@ __device__ __forceinline__ bool grad_nonzero(const typename Vec<F>::T &gv)
     return any;
 }
 
+// Consecutive lanes (consecutive samples of a ray) often hit the same slot on
+// coarse levels.  Sum each run of equal keys across the wavefront (segmented
+// inclusive scan) so only the run's last lane emits an item.  Returns whether
+// this lane emits; v holds the run total there.  Count and scatter call it
+// identically, so they see the same items.
+template <int F>
+__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, float (&v)[F])
+{
+    const int lane = lane_id();
+    const uint32_t pk = __shfl_up(key, 1, 64);
+    const bool pa = __shfl_up(act ? 1 : 0, 1, 64) != 0;
+    const bool head = act && (lane == 0 || !pa || pk != key);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long acts = __ballot(act);
+    if (heads == acts) return act;                 // no run longer than one lane
+    const uint32_t nk = __shfl_down(key, 1, 64);
+    const bool na = __shfl_down(act ? 1 : 0, 1, 64) != 0;
+    const bool tail = act && (lane == 63 || !na || nk != key);
+    // start of this lane's run: highest head at or below this lane
+    const unsigned long long le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const unsigned long long hb = heads & le;
+    const int rs = hb ? 63 - __clzll((long long)hb) : lane;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const float u = __shfl_up(v[f], d, 64);
+            if (lane - d >= rs) v[f] += u;
+        }
+    }
+    return tail;
+}
+
 template <int F>
 __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
                                                         const uint8_t *__restrict__ tile_id,
                                                         const int32_t *__restrict__ sidx, int64_t n,
                                                         const int64_t *__restrict__ n_dev,
                                                         const float *__restrict__ dfeat,
-                                                        int32_t *__restrict__ counts)
+                                                        int32_t *__restrict__ counts,
+                                                        uint32_t *__restrict__ binmax)
 {
     typedef typename Vec<F>::T VT;
     __shared__ int hist[kMaxBins];
-    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) hist[b] = 0;
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) {
+        hist[b] = 0;
+        if (blockIdx.x == 0) binmax[b] = 0u;
+    }
     __syncthreads();
     const int64_t ne = effective_n(n, n_dev);
     const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
@@ -253,12 +319,18 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
+                float v[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) v[f] = 0.0f;
+                const bool emit = merge_runs<F>(key, act, v);
                 const int b = lr * bp.nbpl + (int)(key >> bp.binshift);
                 int b0;
-                if (wave_uniform(b, act, b0)) {
-                    if (lane == __ffsll((long long)__ballot(act)) - 1)
-                        atomicAdd(&hist[b0], __popcll(__ballot(act)));
-                } else if (act) {
+                // the vote must run on every lane: inside the leader's branch
+                // EXEC holds one lane and the popcount would be 1
+                const unsigned long long am = __ballot(emit);
+                if (wave_uniform(b, emit, b0)) {
+                    if (lane == __ffsll((long long)am) - 1) atomicAdd(&hist[b0], __popcll(am));
+                } else if (emit) {
                     atomicAdd(&hist[b], 1);
                 }
             }
@@ -268,6 +340,53 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) counts[(int64_t)b * gridDim.x + blockIdx.x] = hist[b];
 }
 
+// Exclusive prefix sum of cnt[0..m) into off[0..m) by the 256 threads of a
+// block; returns the total.  wtot is 4 ints of LDS.  Ends synchronised.
+__device__ __forceinline__ int block_exclusive_scan(const int *cnt, int *off, int m, int *wtot)
+{
+    const int per = (m + 255) >> 8;
+    const int b0 = threadIdx.x * per;
+    int sum = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < m) sum += cnt[b0 + k];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    int inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+    }
+    if (lane == 63) wtot[wv] = inc;
+    __syncthreads();
+    int run = inc - sum, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int t = wtot[w];
+        run += w < wv ? t : 0;
+        total += t;
+    }
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < m) {
+            off[b0 + k] = run;
+            run += cnt[b0 + k];
+        }
+    __syncthreads();
+    return total;
+}
+
+constexpr int kScatterBatch = 256 * 8;  // items of one (256-sample chunk, level)
+constexpr size_t kScatterLds = 64 * 1024;
+
+// Dynamic LDS of the scatter pass, in ints.
+static size_t scatter_lds_bytes(int nb, int nbpl, int F)
+{
+    return sizeof(int) * ((size_t)3 * nb + (size_t)3 * nbpl + 8 + (size_t)kScatterBatch * (1 + F));
+}
+
+// Each (256-sample chunk, level) batch of items is counting-sorted by bin in
+// LDS first, then written out bin by bin, so consecutive lanes store
+// consecutive item slots of one bin instead of each lane hitting its own
+// random cache line.
 template <int F>
 __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
                                                           const uint8_t *__restrict__ tile_id,
@@ -275,12 +394,28 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                                                           const int64_t *__restrict__ n_dev,
                                                           const float *__restrict__ dfeat,
                                                           const int32_t *__restrict__ offsets,
-                                                          uint32_t *__restrict__ items)
+                                                          const int32_t *__restrict__ counts,
+                                                          uint32_t *__restrict__ items,
+                                                          uint32_t *__restrict__ binmax)
 {
     typedef typename Vec<F>::T VT;
-    __shared__ int cursor[kMaxBins];
-    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x)
-        cursor[b] = offsets[(int64_t)b * gridDim.x + blockIdx.x];
+    extern __shared__ int sm[];
+    int *cursor = sm;                                   // [nb] next free item of this block's range
+    int *cend = cursor + bp.nb;                         // [nb] end of this block's range
+    uint32_t *bmax = reinterpret_cast<uint32_t *>(cend + bp.nb);   // [nb] largest |v| as float bits
+    int *hcnt = reinterpret_cast<int *>(bmax + bp.nb);  // [nbpl] items of the batch per bin
+    int *hoff = hcnt + bp.nbpl;                         // [nbpl] their start in the staging area
+    int *gbase = hoff + bp.nbpl;                        // [nbpl] their first global slot (-1: dropped)
+    int *wtot = gbase + bp.nbpl;                        // [8]
+    uint32_t *skey = reinterpret_cast<uint32_t *>(wtot + 8);        // [batch]
+    float *sval = reinterpret_cast<float *>(skey + kScatterBatch);  // [batch][F]
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) {
+        const int64_t i = (int64_t)b * gridDim.x + blockIdx.x;
+        cursor[b] = offsets[i];
+        cend[b] = offsets[i] + counts[i];
+        bmax[b] = 0u;
+    }
+    for (int b = threadIdx.x; b < bp.nbpl; b += blockDim.x) hcnt[b] = 0;
     __syncthreads();
     const int64_t ne = effective_n(n, n_dev);
     const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
@@ -310,59 +445,138 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             uint32_t idx[8];
             float wt[8];
             corners(g, l, x, idx, wt);
-            const uint32_t lbase = (uint32_t)lr << bp.kt2_log2;
+            // 1. rank every emitted item within its bin for this batch
+            uint32_t key[8];
+            int rank[8];
+            float v[8][F];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
-                const int b = lr * bp.nbpl + (int)(key >> bp.binshift);
-                int b0, at;
-                if (wave_uniform(b, act, b0)) {
-                    const unsigned long long am = __ballot(act);
-                    const int leader = __ffsll((long long)am) - 1;
-                    int basepos = 0;
-                    if (lane == leader) basepos = atomicAdd(&cursor[b0], __popcll(am));
-                    basepos = __shfl(basepos, leader, 64);
-                    at = basepos + __popcll(am & lt_mask);
-                } else {
-                    at = act ? atomicAdd(&cursor[b], 1) : 0;
-                }
-                if (act) {
-                    uint32_t *it = items + (int64_t)at * (1 + F);
-                    it[0] = lbase + key;
+                key[q] = ((uint32_t)tile << bp.T_log2) + idx[q];
 #pragma unroll
-                    for (int f = 0; f < F; ++f) it[1 + f] = __float_as_uint(wt[q] * Vec<F>::get(gv, f));
+                for (int f = 0; f < F; ++f) v[q][f] = wt[q] * Vec<F>::get(gv, f);
+                const bool emit = merge_runs<F>(key[q], act, v[q]);
+                const int bl = (int)(key[q] >> bp.binshift);
+                int b0;
+                if (wave_uniform(bl, emit, b0)) {
+                    const unsigned long long am = __ballot(emit);
+                    const int leader = __ffsll((long long)am) - 1;
+                    int r0 = 0;
+                    if (lane == leader) r0 = atomicAdd(&hcnt[b0], __popcll(am));
+                    r0 = __shfl(r0, leader, 64);
+                    rank[q] = emit ? r0 + __popcll(am & lt_mask) : -1;
+                } else {
+                    rank[q] = emit ? atomicAdd(&hcnt[bl], 1) : -1;
                 }
             }
+            __syncthreads();
+            // 2. staging offsets, and this block's global slots for each bin
+            const int total = block_exclusive_scan(hcnt, hoff, bp.nbpl, wtot);
+            for (int bl = threadIdx.x; bl < bp.nbpl; bl += blockDim.x) {
+                const int c = hcnt[bl];
+                hcnt[bl] = 0;
+                if (c == 0) continue;
+                const int b = lr * bp.nbpl + bl;
+                const int at = cursor[b];
+                cursor[b] = at + c;
+                if (at + c > cend[b]) {            // count and scatter disagree: never write past the range
+                    if (g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_INTERNAL);
+                    gbase[bl] = -1;
+                } else {
+                    gbase[bl] = at;
+                }
+            }
+            // 3. counting-sort the batch into the staging area
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (rank[q] >= 0) {
+                    const int at = hoff[key[q] >> bp.binshift] + rank[q];
+                    skey[at] = key[q];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) sval[at * F + f] = v[q][f];
+                }
+            __syncthreads();
+            // 4. write out: consecutive threads, consecutive slots of a bin
+            const uint32_t lbase = (uint32_t)lr << bp.kt2_log2;
+            for (int j = threadIdx.x; j < total; j += blockDim.x) {
+                const uint32_t k = skey[j];
+                const int bl = (int)(k >> bp.binshift);
+                const int gb = gbase[bl];
+                if (gb < 0) continue;
+                uint32_t *it = items + (int64_t)(gb + (j - hoff[bl])) * (1 + F);
+                it[0] = lbase + k;
+                float m = 0.0f;
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const float u = sval[j * F + f];
+                    it[1 + f] = __float_as_uint(u);
+                    m = fmaxf(m, fabsf(u));
+                }
+                atomicMax(&bmax[lr * bp.nbpl + bl], __float_as_uint(m));   // non-negative floats order as uints
+            }
+            __syncthreads();
         }
     }
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x)
+        if (bmax[b]) atomicMax(&binmax[b], bmax[b]);
+}
+
+// Fixed-point exponent of a bin: every item is rounded to an int32 with
+// |q| < 2^30 (max|v| < 2^e, so v 2^(30-e) < 2^30); slot sums are int64 and
+// cannot overflow for fewer than 2^33 items per slot.
+__device__ __forceinline__ int bin_exponent(uint32_t maxbits)
+{
+    if (maxbits == 0u) return 0;
+    int e;
+    frexpf(__uint_as_float(maxbits), &e);                 // max < 2^e
+    return 30 - e;
 }
 
 template <int F>
 __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, const int32_t *__restrict__ offsets,
                                                          int nblk, const int64_t *__restrict__ n_items,
                                                          const uint32_t *__restrict__ items,
+                                                         const uint32_t *__restrict__ binmax,
                                                          float *__restrict__ dtable)
 {
-    __shared__ float acc[kAccFloats];
+    __shared__ unsigned long long acc[kAccWords];
     const int64_t total = *n_items;
     const int slots = 1 << bp.binshift;
     const uint32_t smask = (uint32_t)slots - 1;
     for (int64_t c0 = (int64_t)blockIdx.x * kReduceChunk; c0 < total; c0 += (int64_t)gridDim.x * kReduceChunk) {
         const int64_t c1 = c0 + kReduceChunk < total ? c0 + kReduceChunk : total;
-        const int bfirst = (int)(items[c0 * (1 + F)] >> bp.binshift);
-        const int blast = (int)(items[(c1 - 1) * (1 + F)] >> bp.binshift);
+        int bfirst = (int)(items[c0 * (1 + F)] >> bp.binshift);
+        int blast = (int)(items[(c1 - 1) * (1 + F)] >> bp.binshift);
+        bfirst = bfirst < 0 ? 0 : (bfirst >= bp.nb ? bp.nb - 1 : bfirst);
+        blast = blast < bfirst ? bfirst : (blast >= bp.nb ? bp.nb - 1 : blast);
         for (int b = bfirst; b <= blast; ++b) {
             const int64_t bs = offsets[(int64_t)b * nblk];
             const int64_t be = b + 1 < bp.nb ? (int64_t)offsets[(int64_t)(b + 1) * nblk] : total;
             const int64_t lo = bs > c0 ? bs : c0, hi = be < c1 ? be : c1;
             if (lo >= hi) continue;
-            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) acc[e] = 0.0f;
+            const int E = bin_exponent(binmax[b]);
+            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) acc[e] = 0ull;
             __syncthreads();
-            for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-                const uint32_t *it = items + i * (1 + F);
-                const uint32_t slot = it[0] & smask;
+            // kRU items per thread per round keep enough loads in flight
+            for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kRU * blockDim.x) {
+                uint32_t w[kRU][1 + F];
 #pragma unroll
-                for (int f = 0; f < F; ++f) atomicAdd(&acc[slot * F + f], __uint_as_float(it[1 + f]));
+                for (int u = 0; u < kRU; ++u) {
+                    const int64_t i = i0 + (int64_t)u * blockDim.x;
+                    if (i < hi) {
+#pragma unroll
+                        for (int k = 0; k <= F; ++k) w[u][k] = items[i * (1 + F) + k];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kRU; ++u) {
+                    if (i0 + (int64_t)u * blockDim.x < hi) {
+#pragma unroll
+                        for (int f = 0; f < F; ++f) {
+                            const int qv = (int)rintf(ldexpf(__uint_as_float(w[u][1 + f]), E));
+                            atomicAdd(&acc[(w[u][0] & smask) * F + f], (unsigned long long)(long long)qv);
+                        }
+                    }
+                }
             }
             __syncthreads();
             // the bin's first key: level and table position of slot 0
@@ -370,12 +584,13 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, cons
             const int lr = (int)(kbase >> bp.kt2_log2);
             const uint32_t key0 = kbase & ((1u << bp.kt2_log2) - 1u);
             for (int e = threadIdx.x; e < slots * F; e += blockDim.x) {
-                const float v = acc[e];
-                if (v != 0.0f) {
+                const long long sv = (long long)acc[e];
+                if (sv != 0) {
                     const uint32_t key = key0 + (uint32_t)(e / F);
                     const int64_t tile = key >> bp.T_log2;
                     const int64_t idx = key & ((1u << bp.T_log2) - 1u);
-                    unsafeAtomicAdd(dtable + ((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + (e % F), v);
+                    unsafeAtomicAdd(dtable + ((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + (e % F),
+                                    (float)ldexp((double)sv, -E));
                 }
             }
             __syncthreads();
@@ -384,8 +599,9 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, cons
 }
 
 struct BinWs {
-    int32_t *counts;
+    int32_t *counts, *offsets;
     int64_t *bsum, *n_items;
+    uint32_t *binmax;
     uint32_t *items;
     int64_t item_cap;
 };
@@ -396,8 +612,8 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F)
 {
     const int64_t ncnt = (int64_t)nb * kBinBlocks;
-    return align256((size_t)ncnt * 4) + align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 +
-           align256((size_t)n * lg * 8 * (1 + F) * 4);
+    return 2 * align256((size_t)ncnt * 4) + align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 +
+           align256((size_t)nb * 4) + align256((size_t)n * lg * 8 * (1 + F) * 4);
 }
 
 static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
@@ -409,7 +625,7 @@ static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
     int kt = log2T;
     while ((1 << (kt - log2T)) < K) ++kt;      // padded K*T
     bp.kt2_log2 = kt;
-    const int acc_log2 = F == 1 ? 14 : F == 2 ? 13 : 12;   // 2^acc_log2 * F floats = 64 KB
+    const int acc_log2 = F == 1 ? 13 : F == 2 ? 12 : 11;   // 2^acc_log2 * F int64 = 64 KB
     bp.binshift = kt < acc_log2 ? kt : acc_log2;
     bp.nbpl = 1 << (kt - bp.binshift);
     bp.nb = lg * bp.nbpl;
@@ -527,19 +743,25 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         return launch_status(__func__);
     }
     SNAKE_ALIGNED(workspace, 256);
+    SNAKE_REQUIRE(n * 8 <= (int64_t)INT32_MAX, SNAKE_ERR_INVALID_ARG,
+                  "snake_hashgrid_bwd: n = %lld too large for the binned adjoint (n * 8 < 2^31)", (long long)n);
+    {
+        const BinPlan b1 = make_plan(g.L, F, gd->log2_table, K, 0, 1);
+        SNAKE_REQUIRE(b1.nb <= kMaxBins && scatter_lds_bytes(b1.nb, b1.nbpl, F) <= kScatterLds, SNAKE_ERR_UNSUPPORTED,
+                      "snake_hashgrid_bwd: K * T = %lld slots per level is too many for the binned adjoint "
+                      "(pass workspace = NULL for the atomic form)", (long long)K << gd->log2_table);
+    }
     // largest level group whose items fit the workspace
     int lg = 0;
     for (int cand = g.L; cand >= 1; --cand) {
         const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, 0, cand);
         // item offsets are int32: a pass holds fewer than 2^31 items
-        if (bp.nb <= kMaxBins && n * cand * 8 <= (int64_t)INT32_MAX &&
-            bin_ws_bytes(bp.nb, n, cand, F) <= workspace_bytes) {
+        if (bp.nb <= kMaxBins && scatter_lds_bytes(bp.nb, bp.nbpl, F) <= kScatterLds &&
+            n * cand * 8 <= (int64_t)INT32_MAX && bin_ws_bytes(bp.nb, n, cand, F) <= workspace_bytes) {
             lg = cand;
             break;
         }
     }
-    SNAKE_REQUIRE(n * 8 <= (int64_t)INT32_MAX, SNAKE_ERR_INVALID_ARG,
-                  "snake_hashgrid_bwd: n = %lld too large for the binned adjoint (n * 8 < 2^31)", (long long)n);
     SNAKE_REQUIRE(lg >= 1, SNAKE_ERR_WORKSPACE, "snake_hashgrid_bwd: workspace needs at least %zu bytes",
                   snake_hashgrid_bwd_workspace_bytes(gd, K, n, 1));
     for (int l0 = 0; l0 < g.L; l0 += lg) {
@@ -550,22 +772,27 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         BinWs w;
         w.counts = reinterpret_cast<int32_t *>(p);
         p += align256((size_t)ncnt * 4);
+        w.offsets = reinterpret_cast<int32_t *>(p);
+        p += align256((size_t)ncnt * 4);
         w.bsum = reinterpret_cast<int64_t *>(p);
         p += align256((size_t)scan::scan_blocks(ncnt) * 8);
         w.n_items = reinterpret_cast<int64_t *>(p);
         p += 256;
+        w.binmax = reinterpret_cast<uint32_t *>(p);
+        p += align256((size_t)bp.nb * 4);
         w.items = reinterpret_cast<uint32_t *>(p);
         w.item_cap = n * lgp * 8;
         const int64_t chunks = (w.item_cap + kReduceChunk - 1) / kReduceChunk;
         const unsigned rgrid = (unsigned)(chunks < 4096 ? (chunks > 0 ? chunks : 1) : 4096);
 #define SNAKE_BIN_PASS(FF)                                                                               \
     bin_count_kernel<FF><<<kBinBlocks, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat,   \
-                                                     w.counts);                                           \
-    scan::launch_scan(w.counts, ncnt, w.bsum, w.counts, 1, nullptr, w.item_cap, w.n_items,              \
+                                                     w.counts, w.binmax);                                 \
+    scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items,             \
                       device_error_word(), st);                                                           \
-    bin_scatter_kernel<FF><<<kBinBlocks, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, \
-                                                       w.counts, w.items);                                \
-    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, g.L, w.counts, kBinBlocks, w.n_items, w.items, dtable)
+    bin_scatter_kernel<FF><<<kBinBlocks, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(              \
+        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.items, w.binmax);        \
+    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, g.L, w.offsets, kBinBlocks, w.n_items, w.items,     \
+                                                 w.binmax, dtable)
         if (F == 1) {
             SNAKE_BIN_PASS(1);
         } else if (F == 2) {

@@ -12,8 +12,8 @@
 // BF16 form: v_mfma_f32_16x16x32_bf16 (K=16 layers: 16x16x16) with FP32
 // accumulation; inputs, weights and hidden activations rounded RNE to bf16.
 //
-// The adjoint recomputes activations from the features (no activation
-// storage), runs the transposed chain, and accumulates weight gradients with
+// The adjoint recomputes activations from the features (or reads them back
+// when the forward stored them), runs the transposed chain, and accumulates weight gradients with
 // MFMA over samples (K = samples) after a per-wave LDS transpose.  Per-block
 // partial sums are reduced in a fixed order by a second kernel.
 #include "common.h"
@@ -181,12 +181,32 @@ __device__ __forceinline__ void relu_mask(float (&d)[T][4], const float (&act)[T
 __device__ __forceinline__ float load_f(const float *p) { return *p; }
 __device__ __forceinline__ float load_f(const __hip_bfloat16 *p) { return __bfloat162float(*p); }
 
+__device__ __forceinline__ float2 load_pair(const float *p) { return *reinterpret_cast<const float2 *>(p); }
+__device__ __forceinline__ float2 load_pair(const __hip_bfloat16 *p)
+{
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
 // Density input rows 0..31 (row p = level p/F, feature p%F; rows >= L*F are 0).
 template <typename FT>
 __device__ __forceinline__ void load_features(const FT *feat, int64_t ld, int64_t s, bool valid,
                                               const MlpArgs &a, float (&x)[2][4])
 {
     const int q = lane_id() >> 4;
+    if (a.F == 2) {             // rows 2m, 2m+1 are the two features of level m: one load
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = 16 * t + 4 * q + 2 * h;
+                float2 v = make_float2(0.0f, 0.0f);
+                if (valid && p < a.n_feat) v = load_pair(feat + ((int64_t)(p >> 1) * ld + s) * 2);
+                x[t][2 * h] = v.x;
+                x[t][2 * h + 1] = v.y;
+            }
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -278,7 +298,69 @@ __device__ __forceinline__ void forward_tile(const typename FragT<PREC>::T *lds,
     }
 }
 
-template <int PREC, int CL, typename FT>
+// Stored activations of one sample: h1 [64] | o [16] | g1 [64] | g2 [64] (two
+// colour layers only) | out [16]; element 16t + 4q + r of an array is row
+// 4q + r of its tile t, so each lane moves 16-byte pieces.
+template <int CL>
+struct ActLayout {
+    static constexpr int H1 = 0, O = 64, G1 = 80, G2 = 144;
+    static constexpr int OUT = CL == 2 ? 208 : 144;
+    static constexpr int W = OUT + 16;
+};
+
+template <int T>
+__device__ __forceinline__ void act_put(float *row, int base, const float (&v)[T][4])
+{
+    const int q = lane_id() >> 4;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+        *reinterpret_cast<f4 *>(row + base + 16 * t + 4 * q) = f4{v[t][0], v[t][1], v[t][2], v[t][3]};
+}
+
+template <int T>
+__device__ __forceinline__ void act_get(const float *row, int base, float (&v)[T][4])
+{
+    const int q = lane_id() >> 4;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const f4 u = *reinterpret_cast<const f4 *>(row + base + 16 * t + 4 * q);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[t][r] = u[r];
+    }
+}
+
+template <int PREC, int CL>
+__device__ __forceinline__ void store_acts(float *row, const Acts<PREC, CL> &A)
+{
+    typedef ActLayout<CL> AL;
+    act_put(row, AL::H1, A.h1);
+    act_put(row, AL::O, A.o);
+    act_put(row, AL::G1, A.g1);
+    if constexpr (CL == 2) act_put(row, AL::G2, A.g2);
+    act_put(row, AL::OUT, A.out);
+}
+
+template <int PREC, int CL>
+__device__ __forceinline__ void load_acts(const float *row, Acts<PREC, CL> &A)
+{
+    typedef ActLayout<CL> AL;
+    act_get(row, AL::H1, A.h1);
+    act_get(row, AL::O, A.o);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) A.cin[0][r] = A.o[0][r];
+    act_get(row, AL::G1, A.g1);
+    if constexpr (CL == 2) act_get(row, AL::G2, A.g2);
+    act_get(row, AL::OUT, A.out);
+}
+
+// Per-lane inputs of one 16-sample tile of the adjoint.
+struct BwdIn {
+    int64_t s, si;
+    bool in_range, valid;
+    float x[2][4], dirs[4], dsig, dr[3];
+};
+
+template <int PREC, int CL, typename FT, bool STORE>
 __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float *__restrict__ w,
                                                          const FT *__restrict__ feat,
                                                          const float *__restrict__ view,
@@ -286,7 +368,8 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
                                                          const int32_t *__restrict__ ray_id,
                                                          const int32_t *__restrict__ sidx, int64_t n,
                                                          const int64_t *__restrict__ n_dev,
-                                                         float *__restrict__ sigma, float *__restrict__ rgb)
+                                                         float *__restrict__ sigma, float *__restrict__ rgb,
+                                                         float *__restrict__ act)
 {
     typedef Layout<PREC, CL> Lt;
     __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::FWD];
@@ -308,6 +391,9 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
         load_features(feat, n, s, ok, a, A.x);
         load_dirs(view, sun, ray, ok, a, A.cin[1]);
         forward_tile<PREC, CL>(lds, A);
+        if constexpr (STORE) {
+            if (ok) store_acts<PREC, CL>(act + s * ActLayout<CL>::W, A);
+        }
         if (q == 0 && valid && !ok) {
             sigma[s] = 0.0f;
             rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
@@ -420,6 +506,18 @@ __device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s,
 {
     const int q = lane_id() >> 4;
     if (!valid) return;
+    if (a.F == 2) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = 16 * t + 4 * q + 2 * h;
+                if (p < a.n_feat)
+                    *reinterpret_cast<float2 *>(dfeat + ((int64_t)(p >> 1) * ld + s) * 2) =
+                        make_float2(dx[t][2 * h], dx[t][2 * h + 1]);
+            }
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -432,13 +530,13 @@ __device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s,
         }
 }
 
-template <int PREC, int CL, typename FT>
+template <int PREC, int CL, typename FT, bool LOAD>
 __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
     MlpArgs a, const float *__restrict__ w, const FT *__restrict__ feat, int64_t feat_ld,
     const float *__restrict__ view, const float *__restrict__ sun, const int32_t *__restrict__ ray_id,
     const int32_t *__restrict__ sidx, int64_t n, const int64_t *__restrict__ n_dev,
-    const float *__restrict__ dsigma, const float *__restrict__ drgb, float *__restrict__ dfeat,
-    float *__restrict__ partial)
+    const float *__restrict__ dsigma, const float *__restrict__ drgb, const float *__restrict__ act,
+    float *__restrict__ dfeat, float *__restrict__ partial)
 {
     typedef Layout<PREC, CL> Lt;
     __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::ALL];
@@ -464,26 +562,59 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
     zero(acc_co);
 
     const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + wv; t < tiles; t += nw) {
-        const int64_t s = t * 16 + i;
-        const bool in_range = s < ne;
-        const int64_t si = in_range ? (sidx ? sidx[s] : s) : 0;
-        int64_t ray = in_range ? ray_id[si] : 0;
-        const bool valid = in_range && ray >= 0 && ray < a.R;   // a bad ray id drops the sample
-        if (in_range && !valid && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
-        ray = valid ? ray : 0;
+    // inputs of the next tile are loaded while the current one is computed
+    auto load = [&](int64_t t, BwdIn &in) {
+        in.s = t * 16 + i;
+        in.in_range = in.s < ne;
+        in.si = in.in_range ? (sidx ? sidx[in.s] : in.s) : 0;
+        int64_t ray = in.in_range ? ray_id[in.si] : 0;
+        in.valid = in.in_range && ray >= 0 && ray < a.R;    // a bad ray id drops the sample
+        if (in.in_range && !in.valid && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
+        ray = in.valid ? ray : 0;
+        load_features(feat, feat_ld, in.si, in.valid, a, in.x);
+        load_dirs(view, sun, ray, in.valid, a, in.dirs);
+        in.dsig = in.dr[0] = in.dr[1] = in.dr[2] = 0.0f;
+        if (q == 0 && in.valid) {
+            in.dsig = dsigma[in.si];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) in.dr[c] = drgb[3 * in.si + c];
+        }
+    };
+    int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+    BwdIn cur;
+    if (t < tiles) load(t, cur);
+    for (; t < tiles; t += nw) {
+        BwdIn nxt;
+        if (t + nw < tiles) load(t + nw, nxt);
+        const int64_t s = cur.s;
+        const bool in_range = cur.in_range, valid = cur.valid;
         Acts<PREC, CL> A;
-        load_features(feat, feat_ld, si, valid, a, A.x);
-        load_dirs(view, sun, ray, valid, a, A.cin[1]);
-        forward_tile<PREC, CL>(lds, A);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A.x[u][r] = cur.x[u][r];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A.cin[1][r] = cur.dirs[r];
+        if constexpr (LOAD) {
+            if (valid) {
+                load_acts<PREC, CL>(act + cur.si * ActLayout<CL>::W, A);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    A.o[0][r] = A.cin[0][r] = A.out[0][r] = 0.0f;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) A.h1[t][r] = A.g1[t][r] = A.g2[t][r] = 0.0f;
+                }
+            }
+        } else {
+            forward_tile<PREC, CL>(lds, A);
+        }
 
         // output activation adjoint (rows 0..3 live in lane group 0)
         float dout[1][4] = {{0.f, 0.f, 0.f, 0.f}};
-        float dsig = 0.0f;
+        const float dsig = cur.dsig;
         if (q == 0 && valid) {
-            dsig = dsigma[si];
-            const float d0 = drgb[3 * si], d1 = drgb[3 * si + 1], d2 = drgb[3 * si + 2];
-            const float dr[3] = {d0, d1, d2};
+            const float *dr = cur.dr;
             if (a.CO == 3) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -546,6 +677,7 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
         wave_sync();
         dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_d1);
         wave_sync();
+        cur = nxt;
     }
 
     // block reduction in a fixed wave order into the padded buffer R
@@ -640,22 +772,33 @@ int make_args(const snake_mlp_desc *m, int64_t R, MlpArgs &a, const char *fn)
 template <int PREC, int CL, typename FT>
 void launch_fwd(const MlpArgs &a, const float *w, const void *feat, const float *view, const float *sun,
                 const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev, float *sigma,
-                float *rgb, hipStream_t st)
+                float *rgb, float *act, hipStream_t st)
 {
     const unsigned grid = grid_for((n + 15) / 16 * 64, kBlock, 4);
-    mlp_fwd_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun, ray_id,
-                                                          sidx, n, n_dev, sigma, rgb);
+    if (act)
+        mlp_fwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun,
+                                                                    ray_id, sidx, n, n_dev, sigma, rgb, act);
+    else
+        mlp_fwd_kernel<PREC, CL, FT, false><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun,
+                                                                     ray_id, sidx, n, n_dev, sigma, rgb, act);
 }
 
 template <int PREC, int CL, typename FT>
 void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat_ld, const float *view,
                 const float *sun, const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev,
-                const float *dsigma, const float *drgb, float *dW, float *dfeat, float *partial, hipStream_t st)
+                const float *dsigma, const float *drgb, const float *act, float *dW, float *dfeat, float *partial,
+                hipStream_t st)
 {
     unsigned grid = grid_for((n + 15) / 16 * 64, kBlock, PREC == P_BF16 ? 2 : 1);
     if (grid > (unsigned)kMaxBwdBlocks) grid = kMaxBwdBlocks;
-    mlp_bwd_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view, sun,
-                                                          ray_id, sidx, n, n_dev, dsigma, drgb, dfeat, partial);
+    if (act)
+        mlp_bwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view,
+                                                                    sun, ray_id, sidx, n, n_dev, dsigma, drgb, act,
+                                                                    dfeat, partial);
+    else
+        mlp_bwd_kernel<PREC, CL, FT, false><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld,
+                                                                     view, sun, ray_id, sidx, n, n_dev, dsigma, drgb,
+                                                                     act, dfeat, partial);
     reduce_partials_kernel<<<(unsigned)((a.P + 255) / 256), 256, 0, st>>>(partial, (int)grid, a.P, dW);
 }
 
@@ -673,6 +816,13 @@ int64_t snake_mlp_param_count(const snake_mlp_desc *m)
     return a.P;
 }
 
+int32_t snake_mlp_act_width(const snake_mlp_desc *m)
+{
+    MlpArgs a;
+    if (make_args(m, 0, a, __func__)) return -1;
+    return a.CL == 2 ? ActLayout<2>::W : ActLayout<1>::W;
+}
+
 size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m)
 {
     MlpArgs a;
@@ -682,7 +832,7 @@ size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m)
 
 int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat, const float *view,
                   const float *sun, const int32_t *ray_id, int32_t R, const int32_t *sample_idx, int64_t n,
-                  const int64_t *n_dev, float *sigma, float *rgb, snake_stream_t stream)
+                  const int64_t *n_dev, float *sigma, float *rgb, float *act, snake_stream_t stream)
 {
     MlpArgs a;
     int rc = make_args(m, R, a, __func__);
@@ -696,15 +846,17 @@ int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *fea
     SNAKE_NOT_NULL(sigma);
     SNAKE_NOT_NULL(rgb);
     SNAKE_REQUIRE(a.n_dir == 3 || sun != nullptr, SNAKE_ERR_NULL, "snake_mlp_fwd: sun is NULL with n_dir = 6");
+    if (a.F == 2) SNAKE_ALIGNED(feat, m->feat_dtype == SNAKE_BF16 ? 4 : 8);
+    SNAKE_ALIGNED(act, 16);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     a.err = device_error_word();
     const bool bf = m->precision == SNAKE_BF16, fb = m->feat_dtype == SNAKE_BF16;
 #define SNAKE_MLP_FWD(P, C)                                                                                  \
     if (fb)                                                                                                  \
         launch_fwd<P, C, __hip_bfloat16>(a, weights, feat, view, sun, ray_id, sample_idx, n, n_dev, sigma, rgb, \
-                                         st);                                                                \
+                                         act, st);                                                           \
     else                                                                                                     \
-        launch_fwd<P, C, float>(a, weights, feat, view, sun, ray_id, sample_idx, n, n_dev, sigma, rgb, st)
+        launch_fwd<P, C, float>(a, weights, feat, view, sun, ray_id, sample_idx, n, n_dev, sigma, rgb, act, st)
     if (bf) {
         if (a.CL == 2) {
             SNAKE_MLP_FWD(P_BF16, 2);
@@ -725,8 +877,8 @@ int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *fea
 int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat, int64_t feat_ld,
                   const float *view, const float *sun, const int32_t *ray_id, int32_t R,
                   const int32_t *sample_idx, int64_t n, const int64_t *n_dev, const float *dsigma,
-                  const float *drgb, float *dW, float *dfeat, void *workspace, size_t workspace_bytes,
-                  snake_stream_t stream)
+                  const float *drgb, const float *act, float *dW, float *dfeat, void *workspace,
+                  size_t workspace_bytes, snake_stream_t stream)
 {
     MlpArgs a;
     int rc = make_args(m, R, a, __func__);
@@ -744,6 +896,11 @@ int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *fea
     SNAKE_NOT_NULL(dW);
     SNAKE_NOT_NULL(dfeat);
     SNAKE_REQUIRE(a.n_dir == 3 || sun != nullptr, SNAKE_ERR_NULL, "snake_mlp_bwd: sun is NULL with n_dir = 6");
+    if (a.F == 2) {
+        SNAKE_ALIGNED(feat, m->feat_dtype == SNAKE_BF16 ? 4 : 8);
+        SNAKE_ALIGNED(dfeat, 8);
+    }
+    SNAKE_ALIGNED(act, 16);
     const size_t need = (size_t)kMaxBwdBlocks * (size_t)a.P * sizeof(float);
     SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= need, SNAKE_ERR_WORKSPACE,
                   "snake_mlp_bwd: workspace needs %zu bytes", need);
@@ -754,10 +911,10 @@ int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *fea
 #define SNAKE_MLP_BWD(P, C)                                                                                     \
     if (fb)                                                                                                     \
         launch_bwd<P, C, __hip_bfloat16>(a, weights, feat, feat_ld, view, sun, ray_id, sample_idx, n, n_dev,      \
-                                         dsigma, drgb, dW, dfeat, partial, st);                                 \
+                                         dsigma, drgb, act, dW, dfeat, partial, st);                            \
     else                                                                                                        \
         launch_bwd<P, C, float>(a, weights, feat, feat_ld, view, sun, ray_id, sample_idx, n, n_dev, dsigma, drgb, \
-                                dW, dfeat, partial, st)
+                                act, dW, dfeat, partial, st)
     if (bf) {
         if (a.CL == 2) {
             SNAKE_MLP_BWD(P_BF16, 2);

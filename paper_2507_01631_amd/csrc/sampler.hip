@@ -229,6 +229,56 @@ __global__ __launch_bounds__(256) void alive_fill_kernel(const int32_t *__restri
     }
 }
 
+// Sliding-window acceptance (Sec. 4.4): the ray's chord through the band
+// [z_lo, z_hi] (t >= 0) must be non-empty, bounded, and have both end points
+// inside the closed rectangle win.  FP64, no contraction (file-wide), so the
+// decision is the written arithmetic bit for bit.
+struct Window {
+    double x_lo, y_lo, x_hi, y_hi, z_lo, z_hi;
+};
+
+__device__ __forceinline__ int window_accepts(const double *o, const double *d, const Window &w)
+{
+    if (d[2] == 0.0) return 0;
+    const double ta = (w.z_lo - o[2]) / d[2];
+    const double tb = (w.z_hi - o[2]) / d[2];
+    double t0 = ta < tb ? ta : tb;
+    const double t1 = ta < tb ? tb : ta;
+    if (t0 < 0.0) t0 = 0.0;
+    if (!(t1 >= t0)) return 0;
+    int ok = 1;
+    const double ts[2] = {t0, t1};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const double x = o[0] + ts[e] * d[0];
+        const double y = o[1] + ts[e] * d[1];
+        if (!(x >= w.x_lo && x <= w.x_hi && y >= w.y_lo && y <= w.y_hi)) ok = 0;
+    }
+    return ok;
+}
+
+__global__ __launch_bounds__(256) void accept_count_kernel(const double *__restrict__ rays_o,
+                                                           const double *__restrict__ rays_d, int R, Window w,
+                                                           int32_t *__restrict__ counts,
+                                                           uint8_t *__restrict__ accept)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const double o[3] = {rays_o[3 * (int64_t)r], rays_o[3 * (int64_t)r + 1], rays_o[3 * (int64_t)r + 2]};
+        const double d[3] = {rays_d[3 * (int64_t)r], rays_d[3 * (int64_t)r + 1], rays_d[3 * (int64_t)r + 2]};
+        const int a = window_accepts(o, d, w);
+        counts[r] = a;
+        if (accept) accept[r] = (uint8_t)a;
+    }
+}
+
+__global__ __launch_bounds__(256) void accept_fill_kernel(const int32_t *__restrict__ counts,
+                                                          const int32_t *__restrict__ offs, int R,
+                                                          int32_t *__restrict__ idx_out)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x)
+        if (counts[r]) idx_out[offs[r]] = r;
+}
+
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 
 // workspace: counts[R] | offs[R] | bsum[nb]
@@ -369,6 +419,37 @@ int snake_pack_alive(const int32_t *packed_info, const int32_t *n_alive, int32_t
     launch_scan(w, R, w.offs, 1, nullptr, cap, n_out, st);
     alive_fill_kernel<<<grid_for((int64_t)R * 64, 256, 16), 256, 0, st>>>(packed_info, w.counts, w.offs,
                                                                          R, cap, idx_out);
+    return launch_status(__func__);
+}
+
+int snake_window_accept(const double *rays_o, const double *rays_d, int32_t R, const double *window,
+                        const double *zband, uint8_t *accept, int32_t *idx_out, int64_t *n_out,
+                        void *workspace, size_t workspace_bytes, snake_stream_t stream)
+{
+    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "snake_window_accept: R = %d < 0", R);
+    SNAKE_NOT_NULL(window);
+    SNAKE_NOT_NULL(zband);
+    SNAKE_NOT_NULL(n_out);
+    Window w{window[0], window[1], window[2], window[3], zband[0], zband[1]};
+    SNAKE_REQUIRE(w.x_lo <= w.x_hi && w.y_lo <= w.y_hi && w.z_lo <= w.z_hi, SNAKE_ERR_INVALID_ARG,
+                  "snake_window_accept: empty window or band");
+    if (R > 0) {
+        SNAKE_NOT_NULL(rays_o);
+        SNAKE_NOT_NULL(rays_d);
+        SNAKE_NOT_NULL(idx_out);
+    }
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= scan_ws_bytes(R), SNAKE_ERR_WORKSPACE,
+                  "snake_window_accept: workspace needs %zu bytes", scan_ws_bytes(R));
+    SNAKE_ALIGNED(workspace, 256);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (R == 0) {
+        set_i64_kernel<<<1, 1, 0, st>>>(n_out, 0);
+        return launch_status(__func__);
+    }
+    ScanWs ws = carve(workspace, R);
+    accept_count_kernel<<<grid_for(R, 256, 8), 256, 0, st>>>(rays_o, rays_d, R, w, ws.counts, accept);
+    launch_scan(ws, R, ws.offs, 1, nullptr, R, n_out, st);
+    accept_fill_kernel<<<grid_for(R, 256, 8), 256, 0, st>>>(ws.counts, ws.offs, R, idx_out);
     return launch_status(__func__);
 }
 

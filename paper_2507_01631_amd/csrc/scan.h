@@ -68,7 +68,8 @@ static __global__ __launch_bounds__(kScanBlock) void scan_top_kernel(int64_t *__
     }
 }
 
-// start[r * stride] = exclusive prefix; count_dst[r * stride] = count (if given)
+// start[r * stride] = exclusive prefix; count_dst[r * stride] = count (if given).
+// start and count_dst must not alias counts (the pointers are restrict).
 static __global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const int32_t *__restrict__ counts, int64_t R,
                                                                 const int64_t *__restrict__ bsum,
                                                                 int32_t *__restrict__ start, int stride,

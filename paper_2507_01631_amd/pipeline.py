@@ -7,7 +7,8 @@ Sec. 4.4 -> adjoints -> Adam, the I-NGP strategy of Sec. 4.6):
     snake_sample_segmented -> snake_hashgrid_fwd -> snake_mlp_fwd
     -> snake_composite_fwd (early stop -> n_alive)
     -> snake_composite_bwd -> snake_pack_alive
-    -> snake_mlp_bwd (recompute) -> snake_hashgrid_bwd (FP32 atomics)
+    -> snake_mlp_bwd (recompute, or stored activations)
+    -> snake_hashgrid_bwd (binned fixed-point sums, or FP32 atomics)
     -> snake_adam_step (table) + snake_adam_step (MLP)
 
 PyTorch only owns device memory and the stream; every step runs in libsnake.
@@ -48,7 +49,7 @@ class TileNeRF:
     def __init__(self, *, res, n_features, log2_table, n_dir, colour_layers, colour_out,
                  boxes, zband=None, samples=64, early_stop=0.0, precision="fp32",
                  table=None, mlp_params=None, max_rays=4096, lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-15, hash_bwd="binned", hash_ws_gib=16.0, device="cuda"):
+                 eps=1e-15, hash_bwd="binned", hash_ws_gib=16.0, recompute=True, device="cuda"):
         self.device = torch.device(device)
         self.res = [int(r) for r in res]
         self.F = int(n_features)
@@ -84,6 +85,10 @@ class TileNeRF:
         # "atomic": one FP32 atomic add per corner contribution
         assert hash_bwd in ("binned", "atomic")
         self.hash_bwd, self.hash_ws_gib = hash_bwd, float(hash_ws_gib)
+        # recompute=False: the forward stores every sample's activations and the
+        # adjoint reads them back instead of recomputing them
+        self.recompute = bool(recompute)
+        self.act = None
         self.step_count = 0
         self.R = 0
         self.R_cur = 0
@@ -123,6 +128,8 @@ class TileNeRF:
         self.ws_sample = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=dev)
         self.ws_mlp = torch.empty(L.snake_mlp_bwd_workspace_bytes(self.mlp), dtype=torch.uint8,
                                   device=dev)
+        if not self.recompute:
+            self.act = torch.empty((cap, L.snake_mlp_act_width(self.mlp)), dtype=f32, device=dev)
         self.ws_hash = None
         if self.hash_bwd == "binned":
             # as many levels per pass as fit in the budget (at least one)
@@ -149,7 +156,7 @@ class TileNeRF:
         L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.pos, self.tile_id, None, self.cap,
                              self.n_out, self.feat, None, stream)
         L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, sun, self.ray_id, self.R_cur, None,
-                        self.cap, self.n_out, self.sigma, self.rgb, stream)
+                        self.cap, self.n_out, self.sigma, self.rgb, act=self.act, stream=stream)
 
     def render(self, R, target=None, loss_scale=0.0, stream=None):
         L.snake_composite_fwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R,
@@ -169,7 +176,7 @@ class TileNeRF:
             idx, n_dev = None, self.n_out
         L.snake_mlp_bwd(self.mlp, self.params, self.feat, self.cap, self.view, sun, self.ray_id, R, idx,
                         self.cap, n_dev, self.dsigma, self.drgb, self.g_w, self.dfeat, self.ws_mlp,
-                        stream)
+                        act=self.act, stream=stream)
         L.snake_hashgrid_bwd(self.grid, self.K, self.pos, self.tile_id, idx, self.cap, n_dev, self.dfeat,
                              self.g_t, self.ws_hash, stream)
         return n_dev

@@ -61,6 +61,13 @@ def test_level_resolutions_match_oracle(orc):
         assert list(orc.level_resolutions(Lv, lo, hi)) == level_resolutions(Lv, lo, hi)
 
 
+def test_act_width(L):
+    # h1 64 | o 16 | g1 64 | (g2 64) | out 16 floats per sample
+    assert L.snake_mlp_act_width(L.mlp_desc(8, 2, 3, 1, 3)) == 160
+    assert L.snake_mlp_act_width(L.mlp_desc(16, 2, 6, 2, 4)) == 224
+    assert L.snake_mlp_act_width(L.mlp_desc(8, 2, 3, 3, 3)) == -1
+
+
 def test_workspace_queries(L):
     assert L.snake_sample_workspace_bytes(4096) >= 2 * 4096 * 4
     d = L.mlp_desc(16, 2, 6, 2, 4)
@@ -97,15 +104,19 @@ def test_host_side_argument_errors(L):
     # MLP descriptor checks
     m = L.mlp_desc(8, 2, 5, 1, 3)
     assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, 1, None, 16, None, None, None,
-                            None) == SNAKE_ERR_INVALID_ARG
+                            None, None) == SNAKE_ERR_INVALID_ARG
     m = L.mlp_desc(8, 2, 3, 3, 3)
     assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, 1, None, 16, None, None, None,
-                            None) == SNAKE_ERR_UNSUPPORTED
+                            None, None) == SNAKE_ERR_UNSUPPORTED
     m = L.mlp_desc(17, 2, 3, 1, 3)
     assert so.snake_mlp_param_count(ctypes.byref(m)) == -1
     m = L.mlp_desc(8, 2, 6, 2, 4)
     assert so.snake_mlp_bwd(ctypes.byref(m), None, None, 0, None, None, None, 1, None, 16, None, None,
-                            None, None, None, None, 0, None) == SNAKE_ERR_INVALID_ARG
+                            None, None, None, None, None, 0, None) == SNAKE_ERR_INVALID_ARG
+    # stored activations must be 16-byte aligned
+    fake = ctypes.c_void_p(256)
+    assert so.snake_mlp_fwd(ctypes.byref(m), fake, fake, fake, fake, fake, 1, None, 16, None, fake, fake,
+                            ctypes.c_void_p(260), None) == -3
     # sampler checks (boxes are host memory)
     boxes = np.array([[0, 0, 0, 1, 1, 1]], np.float64)
     assert so.snake_sample_segmented(None, None, 4, boxes.ctypes.data, 0, None, None, 8, None, None,

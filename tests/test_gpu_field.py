@@ -106,6 +106,7 @@ def test_hashgrid_bwd(L, orc, name, mode):
         ws = torch.empty(L.snake_hashgrid_bwd_workspace_bytes(g, K, n, lg), dtype=torch.uint8, device=DEV)
     L.snake_hashgrid_bwd(g, K, dev(pos), None if tid is None else dev(tid), None, n, None, dfd, dtab, ws)
     sync()
+    assert L.snake_check_device_error() == 0
     dpad = np.zeros((n, 32))
     dpad[:, :W] = dfeat.astype(np.float32)
     ref = orc.hashgrid_bwd(res, c["log2T"], table.shape, pos, dpad, tid)
@@ -202,6 +203,19 @@ def test_mlp_bwd(L, orc, name, prec):
                     dev(sel), n, None, dev(ds), dev(dr), dW2, dfeat, ws)
     sync()
     assert torch.equal(dW2 - dW, dW)
+    # stored activations (forward over all N samples, adjoint reads them through
+    # the index list) give bit-identical gradients to recomputation
+    act = torch.empty((N, L.snake_mlp_act_width(m)), device=DEV)
+    sig, rgb = torch.empty(N, device=DEV), torch.empty((N, 3), device=DEV)
+    L.snake_mlp_fwd(m, dev(w), fd, dev(view), dev(sun) if cfg.n_dir == 6 else None, dev(rid), R, None, N,
+                    None, sig, rgb, act=act)
+    dW3 = torch.zeros_like(dW)
+    dfeat3 = torch.zeros_like(dfeat)
+    L.snake_mlp_bwd(m, dev(w), fd, N, dev(view), dev(sun) if cfg.n_dir == 6 else None, dev(rid), R,
+                    dev(sel), n, None, dev(ds), dev(dr), dW3, dfeat3, ws, act=act)
+    sync()
+    assert torch.equal(dW3, dW)
+    assert torch.equal(dfeat3, dfeat)
 
 
 def test_hashgrid_bwd_binned_indexed_ray_ordered(L, orc):

@@ -118,3 +118,36 @@ def test_pack_alive(L):
     expect = np.concatenate([np.arange(s, s + k) for s, k in zip(start, keep)]).astype(np.int32)
     assert int(host(n_out)[0]) == expect.size
     assert np.array_equal(host(idx)[:expect.size], expect)
+
+
+def test_window_accept_bitexact(L, orc):
+    """Sliding-window acceptance decisions and the compacted index list match
+    the oracle exactly, including rays whose chord ends exactly on the window
+    edge, vertical rays, rays parallel to the band and origins inside it."""
+    rng = np.random.default_rng(31)
+    o, d = _slanted(rng, 5000, -0.4, 2.4, z_top=1.4)
+    # exact edge cases: vertical rays on and just off the closed edge
+    o[:4] = [[2.0, 1.0, 3.0], [2.0 + 2**-40, 1.0, 3.0], [0.0, 0.0, 3.0], [1.0, 1.0, 0.5]]
+    d[:4] = [[0.0, 0.0, -1.0], [0.0, 0.0, -1.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]]
+    win, zb = (0.0, 0.0, 2.0, 2.0), (0.0, 1.0)
+    R = o.shape[0]
+    acc = torch.empty(R, dtype=torch.uint8, device=DEV)
+    idx = torch.full((R,), -1, dtype=torch.int32, device=DEV)
+    n = torch.zeros(1, dtype=torch.int64, device=DEV)
+    ws = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=DEV)
+    L.snake_window_accept(dev(o), dev(d), R, win, zb, acc, idx, n, ws)
+    sync()
+    ref = orc.window_accept(o, d, win, zb)
+    assert np.array_equal(host(acc).astype(np.int32), ref)
+    assert int(n.item()) == int(ref.sum())
+    assert np.array_equal(host(idx)[:int(ref.sum())], np.nonzero(ref)[0].astype(np.int32))
+    assert ref[:4].tolist() == [1, 0, 1, 0]
+    assert 1000 < ref.sum() < R - 1000
+    # no output array for the flags, and an empty call
+    idx2 = torch.full((R,), -1, dtype=torch.int32, device=DEV)
+    L.snake_window_accept(dev(o), dev(d), R, win, zb, None, idx2, n, ws)
+    sync()
+    assert torch.equal(idx2, idx)
+    L.snake_window_accept(dev(o), dev(d), 0, win, zb, None, idx2, n, ws)
+    sync()
+    assert int(n.item()) == 0

@@ -291,6 +291,64 @@ def test_sampler_truncation_is_a_prefix(orc):
             assert np.array_equal(tr[key][ts:ts + tc], full[key][fs:fs + tc])
 
 
+def test_window_accept_closed_forms(orc):
+    """Vertical rays accept inside or on the window edge (closed rectangle)
+    and reject outside; a slanted ray's band chord end points are
+    o + t d at t = (z - o_z) / d_z; rays parallel to the band are rejected;
+    an origin inside the band starts the chord at t = 0."""
+    win = (0.0, 0.0, 2.0, 2.0)
+    o = np.array([[1.0, 1.0, 3.0], [2.0, 0.5, 3.0], [2.0 + 2**-40, 0.5, 3.0], [-0.25, 1.0, 3.0],
+                  [0.5, 0.5, 2.0], [0.5, 0.5, 2.0], [0.5, 0.5, 2.0], [1.0, 1.0, 0.5], [1.0, 1.0, 0.5],
+                  [1.0, 1.0, 0.5]])
+    d = np.array([[0, 0, -1.0], [0, 0, -1.0], [0, 0, -1.0], [0, 0, -1.0],
+                  # band [0.5, 1.5]: chord t in [0.5, 1.5], x from 0.625 to 0.875 (all exact)
+                  [0.25, 0, -1.0], [-0.375, 0, -1.0], [-0.5, 0, -1.0],
+                  [1.0, 0, 0.0],                               # parallel to the band
+                  [1.5, 0, 1.0],                               # inside, going up: t in [0, 1]
+                  [0.75, 0, 1.0]])
+    acc = orc.window_accept(o, d, win, (0.5, 1.5))
+    # x at chord ends: ray 5: 0.5-0.1875=0.3125, 0.5-0.5625=-0.0625 -> out;
+    # ray 6: 0.25, -0.25 -> out; ray 8: 1, 2.5 -> out; ray 9: 1, 1.75 -> in
+    assert acc.tolist() == [1, 1, 0, 0, 1, 0, 0, 0, 0, 1]
+    acc2 = orc.window_accept(o[4:5], d[4:5], (0.0, 0.0, 0.875, 1.0), (0.5, 1.5))
+    acc3 = orc.window_accept(o[4:5], d[4:5], (0.0, 0.0, 0.875 - 2**-40, 1.0), (0.5, 1.5))
+    assert acc2.tolist() == [1] and acc3.tolist() == [0]
+
+
+def test_window_accept_equals_chord_covered_by_window_tiles(orc):
+    """A ray is accepted exactly when the 2x2 window's tiles cover its whole
+    chord through the band: the sampler's intervals inside the window then
+    span the same length as over a 4x4 grid around it (checked through the
+    independently pinned segmented sampler)."""
+    rng = np.random.default_rng(21)
+    win_boxes = _grid_boxes(2, 2)                         # [0,2]^2 x [0,1]
+    big = _grid_boxes(4, 4, x0=-1.0, y0=-1.0)             # [-1,3]^2 x [0,1]
+    o, d = _slanted_rays(rng, 3000, -0.3, 2.3, z_top=1.4, max_deg=30.0)
+    acc = orc.window_accept(o, d, (0.0, 0.0, 2.0, 2.0), (0.0, 1.0))
+    sw = orc.sample_segmented(o, d, win_boxes, 16)
+    sb = orc.sample_segmented(o, d, big, 16)
+    n_acc = n_rej_partial = 0
+    for r in range(3000):
+        ws, wc = sw["packed_info"][r]
+        bs, bc = sb["packed_info"][r]
+        assert bc > 0
+        lw = float(np.sum(sw["t1"][ws:ws + wc].astype(np.float64) - sw["t0"][ws:ws + wc]))
+        lb = float(np.sum(sb["t1"][bs:bs + bc].astype(np.float64) - sb["t0"][bs:bs + bc]))
+        # band end points, to skip rays that graze the window edge
+        t = np.array([(1.0 - o[r, 2]) / d[r, 2], (0.0 - o[r, 2]) / d[r, 2]])
+        xy = o[r, :2][None, :] + t[:, None] * d[r, :2][None, :]
+        edge = np.min(np.abs(np.concatenate([xy.ravel(), xy.ravel() - 2.0])))
+        if edge < 1e-6:
+            continue
+        if acc[r]:
+            n_acc += 1
+            assert abs(lw - lb) <= 1e-6 * lb
+        else:
+            assert lw < lb - 1e-6
+            n_rej_partial += wc > 0
+    assert n_acc > 500 and n_rej_partial > 200
+
+
 def test_sampler_capacity_error(orc):
     w = synth.tiny_tile(seed=0, n_rays=16, samples=8)
     with pytest.raises(ValueError):
