@@ -249,7 +249,15 @@ typedef struct {
  * [colour_out][64]. */
 int64_t snake_mlp_param_count(const snake_mlp_desc *m);
 
-/* Forward.  feat [L][n][F] (level-major; sample j's row is j), view/sun
+/* Per-tile networks (the window step, Sec. 4.4): with K > 1, weights is
+ * [K][P] and tile_start [K+2] (device int64, as written by
+ * snake_tile_partition) splits the call's entries j into groups; group k < K
+ * uses weight set k, entries of group K are dropped (sigma = rgb = 0, dfeat =
+ * 0), and dW is [K][P].  K == 1 takes tile_start = NULL (one group [0, n)).
+ * The groups are processed in 64-entry units that never mix two weight sets.
+ * 1 <= K <= 16.
+ *
+ * Forward.  feat [L][n][F] (level-major; sample j's row is j), view/sun
  * [R][3] float per ray (sun may be NULL when n_dir == 3), ray_id per input
  * sample (read through sample_idx); a ray id outside [0, R) gives sigma = 0,
  * rgb = 0 and raises SNAKE_DEVERR_RAY_ID.  Writes sigma [n], rgb [n][3].  BF16
@@ -260,7 +268,8 @@ int64_t snake_mlp_param_count(const snake_mlp_desc *m);
  * receives every sample's hidden and output activations for an adjoint
  * that does not recompute them (samples with a bad ray id are not written). */
 int32_t snake_mlp_act_width(const snake_mlp_desc *m);
-int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat,
+int snake_mlp_fwd(const snake_mlp_desc *m, int32_t K, const float *weights,
+                  const int64_t *tile_start, const void *feat,
                   const float *view, const float *sun, const int32_t *ray_id, int32_t R,
                   const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
                   float *sigma, float *rgb, float *act, snake_stream_t stream);
@@ -273,9 +282,10 @@ int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *fea
  * j (zero for a sample whose ray id is outside [0, R), which is flagged with
  * SNAKE_DEVERR_RAY_ID).  dW [P] += the sum over samples, reduced in a fixed
  * order (deterministic for a given n).  With F == 2, feat and dfeat are
- * aligned to one row.  Workspace: snake_mlp_bwd_workspace_bytes(m). */
-size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m);
-int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat,
+ * aligned to one row.  Workspace: snake_mlp_bwd_workspace_bytes(m, K). */
+size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m, int32_t K);
+int snake_mlp_bwd(const snake_mlp_desc *m, int32_t K, const float *weights,
+                  const int64_t *tile_start, const void *feat,
                   int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
                   int32_t R, const int32_t *sample_idx, int64_t n, const int64_t *n_dev,
                   const float *dsigma, const float *drgb, const float *act, float *dW,
@@ -297,7 +307,8 @@ int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *fea
  * be NULL.
  */
 int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
-                        const int32_t *packed_info, int32_t R, float early_stop_T,
+                        const int32_t *packed_info, int32_t R, const int32_t *sample_map,
+                        float early_stop_T,
                         const float *target, float loss_scale,
                         float *rgb_out, float *opacity, float *depth, int32_t *n_alive,
                         float *loss, snake_stream_t stream);
@@ -307,9 +318,16 @@ int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, c
  *   drgb_i = w_i g,  dsigma_i = delta_i sum_ch g_ch (T_{i+1} c_i,ch - (C_ch - A_i,ch)),
  * A_i = sum_{j<=i} w_j c_j, for i < n_alive[r] (all samples if n_alive is NULL);
  * the other samples of the ray get 0.  dsigma [N], drgb [N][3] written.
+ *
+ * sample_map (both calls; NULL = identity): packed sample p's sigma and rgb
+ * are read at sample_map[p], and its dsigma and drgb written there, so the
+ * per-sample arrays may be kept in another order (the tile-partitioned order
+ * of the window step, sample_map = inv of snake_tile_partition) while t0, t1
+ * and packed_info stay packed.
  */
 int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
-                        const int32_t *packed_info, int32_t R, const int32_t *n_alive,
+                        const int32_t *packed_info, int32_t R, const int32_t *sample_map,
+                        const int32_t *n_alive,
                         const float *target, float loss_scale,
                         float *dsigma, float *drgb, snake_stream_t stream);
 
@@ -321,10 +339,17 @@ int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, c
 
 /* g' = g + l2 p; m = b1 m + (1-b1) g'; v = b2 v + (1-b2) g'^2;
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), step >= 1.
- * p, g, m, v [n] float, 16-byte aligned. */
+ * p, g, m, v [n] float, 16-byte aligned.  The bias corrections are
+ * fl32(1 - b^step) with b^step formed by binary powering in FP64.
+ * step_dev: NULL, or a device int32 holding the step (then `step` is
+ * ignored), so that a captured HIP graph replays with the current step;
+ * snake_counter_add advances it inside the same graph. */
 int snake_adam_step(float *p, float *g, float *m, float *v, int64_t n,
-                    float lr, float b1, float b2, float eps, int32_t step, float l2,
-                    uint32_t flags, snake_stream_t stream);
+                    float lr, float b1, float b2, float eps, int32_t step,
+                    const int32_t *step_dev, float l2, uint32_t flags, snake_stream_t stream);
+
+/* *counter += delta on the stream (device int32). */
+int snake_counter_add(int32_t *counter, int32_t delta, snake_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -304,28 +304,51 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
     sun = wl.sun if rays is None else rays[3]
     R = rays_o.shape[0]
     out = {}
-    smp = sample_segmented(rays_o, rays_d, wl.boxes, wl.samples_per_ray, zband=wl.zband)
+    spr = wl.samples_per_ray
+    if np.ndim(spr) == 0:
+        smp = sample_segmented(rays_o, rays_d, wl.boxes, int(spr), zband=wl.zband)
+    else:
+        smp = sample_segmented(rays_o, rays_d, wl.boxes, 0, zband=wl.zband,
+                               samples_per_ray=np.asarray(spr, dtype=np.int32))
     out["sample"] = smp
     feat = hashgrid_fwd(res, g.log2_table, table, smp["pos"], smp["tile_id"], g.out_width)
-    sigma, rgb = mlp_fwd(m, mlp_params, feat, smp["view"], smp["ray_id"], sun=sun)
+    # one weight set ([P]) shared by the tiles, or one per tile ([K][P]): each
+    # sample then goes through the networks of the tile it lies in
+    per_tile = np.ndim(mlp_params) == 2
+    groups = ([(np.ones(smp["n"], dtype=bool), mlp_params)] if not per_tile else
+              [(smp["tile_id"] == k, mlp_params[k]) for k in range(mlp_params.shape[0])])
+    sigma, rgb = np.zeros(smp["n"]), np.zeros((smp["n"], 3))
+    for sel, w in groups:
+        if sel.any():
+            sigma[sel], rgb[sel] = mlp_fwd(m, w, feat[sel], smp["view"], smp["ray_id"][sel], sun=sun)
     loss_scale = 1.0 / (3.0 * R)
     comp = composite_fwd(smp["packed_info"], sigma, rgb, smp["t0"], smp["t1"], target,
                          loss_scale, early_stop=wl.early_stop, alive=alive)
     n_alive = comp["n_alive"] if alive is None else np.asarray(alive, dtype=np.int32)
     dsigma, drgb = composite_bwd(smp["packed_info"], sigma, rgb, smp["t0"], smp["t1"],
                                  target, loss_scale, n_alive=n_alive)
-    dW, dfeat = mlp_bwd(m, mlp_params, feat, smp["view"], smp["ray_id"], dsigma, drgb, sun=sun)
+    dW = np.zeros(mlp_params.shape)
+    dfeat = np.zeros((smp["n"], feat.shape[1]))
+    for k, (sel, w) in enumerate(groups):
+        if sel.any():
+            dWk, dfeat[sel] = mlp_bwd(m, w, feat[sel], smp["view"], smp["ray_id"][sel], dsigma[sel], drgb[sel],
+                                      sun=sun)
+            if per_tile:
+                dW[k] += dWk
+            else:
+                dW += dWk
+    dW = dW.ravel()
     dtable = hashgrid_bwd(res, g.log2_table, table.shape, smp["pos"], dfeat, smp["tile_id"])
     if adam_state is None:
         adam_state = dict(m_t=np.zeros(table.size), v_t=np.zeros(table.size),
                           m_w=np.zeros(mlp_params.size), v_w=np.zeros(mlp_params.size))
     p_t = table.astype(np.float64).ravel().copy()
-    p_w = mlp_params.astype(np.float64).copy()
+    p_w = mlp_params.astype(np.float64).ravel().copy()
     adam_step(p_t, dtable.ravel(), adam_state["m_t"], adam_state["v_t"], wl.lr, step)
     adam_step(p_w, dW, adam_state["m_w"], adam_state["v_w"], wl.lr, step)
     out.update(res=res, feat=feat, sigma=sigma, rgb=rgb, comp=comp, n_alive=n_alive,
                dsigma=dsigma, drgb=drgb, dW=dW, dfeat=dfeat, dtable=dtable,
-               table_new=p_t.reshape(table.shape), mlp_new=p_w, adam=adam_state,
+               table_new=p_t.reshape(table.shape), mlp_new=p_w.reshape(mlp_params.shape), adam=adam_state,
                loss=comp["loss"], n_samples=int(n_alive.sum()), n_total=smp["n"])
     if timings is not None:
         timings.append(time.perf_counter() - t_start)

@@ -31,7 +31,7 @@ EXPORTS = (
     "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
-    "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step",
+    "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step", "snake_counter_add",
 )
 
 
@@ -90,15 +90,17 @@ _SIGS = {
     "snake_hashgrid_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_hashgrid_bwd_workspace_bytes": ([_P, _I32, _I64, _I32], _SZ),
     "snake_mlp_param_count": ([_P], _I64),
-    "snake_mlp_bwd_workspace_bytes": ([_P], _SZ),
+    "snake_mlp_bwd_workspace_bytes": ([_P, _I32], _SZ),
     "snake_mlp_act_width": ([_P], _I32),
-    "snake_mlp_fwd": ([_P, _P, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
-    "snake_mlp_bwd": ([_P, _P, _P, _I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _P],
+    "snake_mlp_fwd": ([_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
+    "snake_mlp_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
+                       _SZ, _P],
                       ctypes.c_int),
-    "snake_composite_fwd": ([_P, _P, _P, _P, _P, _I32, _F, _P, _F, _P, _P, _P, _P, _P, _P],
+    "snake_composite_fwd": ([_P, _P, _P, _P, _P, _I32, _P, _F, _P, _F, _P, _P, _P, _P, _P, _P],
                             ctypes.c_int),
-    "snake_composite_bwd": ([_P, _P, _P, _P, _P, _I32, _P, _P, _F, _P, _P, _P], ctypes.c_int),
-    "snake_adam_step": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _F, _U32, _P], ctypes.c_int),
+    "snake_composite_bwd": ([_P, _P, _P, _P, _P, _I32, _P, _P, _P, _F, _P, _P, _P], ctypes.c_int),
+    "snake_adam_step": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P, _F, _U32, _P], ctypes.c_int),
+    "snake_counter_add": ([_P, _I32, _P], ctypes.c_int),
 }
 
 _lib = None
@@ -237,21 +239,23 @@ def snake_mlp_act_width(m: MlpDesc) -> int:
     return int(lib().snake_mlp_act_width(ctypes.byref(m)))
 
 
-def snake_mlp_bwd_workspace_bytes(m: MlpDesc) -> int:
-    return int(lib().snake_mlp_bwd_workspace_bytes(ctypes.byref(m)))
+def snake_mlp_bwd_workspace_bytes(m: MlpDesc, K=1) -> int:
+    return int(lib().snake_mlp_bwd_workspace_bytes(ctypes.byref(m), int(K)))
 
 
 def snake_mlp_fwd(m: MlpDesc, weights, feat, view, sun, ray_id, R, sample_idx, n, n_dev, sigma, rgb,
-                  act=None, stream=None):
-    rc = lib().snake_mlp_fwd(ctypes.byref(m), _ptr(weights), _ptr(feat), _ptr(view), _ptr(sun),
+                  act=None, K=1, tile_start=None, stream=None):
+    rc = lib().snake_mlp_fwd(ctypes.byref(m), int(K), _ptr(weights), _ptr(tile_start), _ptr(feat), _ptr(view),
+                             _ptr(sun),
                              _ptr(ray_id), int(R), _ptr(sample_idx), int(n), _ptr(n_dev), _ptr(sigma),
                              _ptr(rgb), _ptr(act), _stream(stream))
     _check("snake_mlp_fwd", rc)
 
 
 def snake_mlp_bwd(m: MlpDesc, weights, feat, feat_ld, view, sun, ray_id, R, sample_idx, n, n_dev,
-                  dsigma, drgb, dW, dfeat, workspace, act=None, stream=None):
-    rc = lib().snake_mlp_bwd(ctypes.byref(m), _ptr(weights), _ptr(feat), int(feat_ld), _ptr(view),
+                  dsigma, drgb, dW, dfeat, workspace, act=None, K=1, tile_start=None, stream=None):
+    rc = lib().snake_mlp_bwd(ctypes.byref(m), int(K), _ptr(weights), _ptr(tile_start), _ptr(feat), int(feat_ld),
+                             _ptr(view),
                              _ptr(sun), _ptr(ray_id), int(R), _ptr(sample_idx), int(n), _ptr(n_dev),
                              _ptr(dsigma), _ptr(drgb), _ptr(act), _ptr(dW), _ptr(dfeat), _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream))
@@ -259,24 +263,28 @@ def snake_mlp_bwd(m: MlpDesc, weights, feat, feat_ld, view, sun, ray_id, R, samp
 
 
 def snake_composite_fwd(sigma, rgb, t0, t1, packed_info, R, early_stop_T, target, loss_scale,
-                        rgb_out, opacity, depth, n_alive, loss, stream=None):
+                        rgb_out, opacity, depth, n_alive, loss, sample_map=None, stream=None):
     rc = lib().snake_composite_fwd(_ptr(sigma), _ptr(rgb), _ptr(t0), _ptr(t1), _ptr(packed_info),
-                                   int(R), float(early_stop_T), _ptr(target), float(loss_scale),
+                                   int(R), _ptr(sample_map), float(early_stop_T), _ptr(target), float(loss_scale),
                                    _ptr(rgb_out), _ptr(opacity), _ptr(depth), _ptr(n_alive),
                                    _ptr(loss), _stream(stream))
     _check("snake_composite_fwd", rc)
 
 
 def snake_composite_bwd(sigma, rgb, t0, t1, packed_info, R, n_alive, target, loss_scale, dsigma,
-                        drgb, stream=None):
+                        drgb, sample_map=None, stream=None):
     rc = lib().snake_composite_bwd(_ptr(sigma), _ptr(rgb), _ptr(t0), _ptr(t1), _ptr(packed_info),
-                                   int(R), _ptr(n_alive), _ptr(target), float(loss_scale),
+                                   int(R), _ptr(sample_map), _ptr(n_alive), _ptr(target), float(loss_scale),
                                    _ptr(dsigma), _ptr(drgb), _stream(stream))
     _check("snake_composite_bwd", rc)
 
 
-def snake_adam_step(p, g, m, v, n, lr, b1, b2, eps, step, l2=0.0, flags=0, stream=None):
+def snake_adam_step(p, g, m, v, n, lr, b1, b2, eps, step, l2=0.0, flags=0, step_dev=None, stream=None):
     rc = lib().snake_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(n), float(lr), float(b1),
-                               float(b2), float(eps), int(step), float(l2), int(flags),
+                               float(b2), float(eps), int(step), _ptr(step_dev), float(l2), int(flags),
                                _stream(stream))
     _check("snake_adam_step", rc)
+
+
+def snake_counter_add(counter, delta, stream=None):
+    _check("snake_counter_add", lib().snake_counter_add(_ptr(counter), int(delta), _stream(stream)))

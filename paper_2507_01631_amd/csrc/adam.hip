@@ -10,7 +10,27 @@ namespace {
 struct AdamArgs {
     float lr, b1, b2, eps, l2, c1, c2;   // c1 = 1 - b1^step, c2 = 1 - b2^step
     int zero_grad;
+    const int32_t *step_dev;             // step read on the device when set
 };
+
+// b^k by binary powering in FP64: the same multiplications, in the same
+// order, on the host and on the device, so both give the same bits.
+__host__ __device__ inline double pow_int(double b, int k)
+{
+    double r = 1.0;
+    while (k > 0) {
+        if (k & 1) r *= b;
+        b *= b;
+        k >>= 1;
+    }
+    return r;
+}
+
+__host__ __device__ inline void bias_corrections(AdamArgs &a, int step)
+{
+    a.c1 = (float)(1.0 - pow_int((double)a.b1, step));
+    a.c2 = (float)(1.0 - pow_int((double)a.b2, step));
+}
 
 __device__ __forceinline__ void adam1(float &p, float &g, float &m, float &v, const AdamArgs &a)
 {
@@ -28,6 +48,10 @@ __global__ __launch_bounds__(256) void adam_kernel(float4 *__restrict__ p, float
                                                    float *__restrict__ ms, float *__restrict__ vs, int tail,
                                                    AdamArgs a)
 {
+    if (a.step_dev) {
+        const int step = *a.step_dev;
+        bias_corrections(a, step < 1 ? 1 : step);
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
         float4 P = p[i], G = g[i], M = m[i], V = v[i];
         adam1(P.x, G.x, M.x, V.x, a);
@@ -50,6 +74,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float4 *__restrict__ p, float
     }
 }
 
+__global__ void counter_add_kernel(int32_t *c, int32_t d) { *c += d; }
+
 }  // namespace
 }  // namespace snake
 
@@ -57,11 +83,19 @@ using namespace snake;
 
 extern "C" {
 
+int snake_counter_add(int32_t *counter, int32_t delta, snake_stream_t stream)
+{
+    SNAKE_NOT_NULL(counter);
+    counter_add_kernel<<<1, 1, 0, reinterpret_cast<hipStream_t>(stream)>>>(counter, delta);
+    return launch_status(__func__);
+}
+
 int snake_adam_step(float *p, float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
-                    int32_t step, float l2, uint32_t flags, snake_stream_t stream)
+                    int32_t step, const int32_t *step_dev, float l2, uint32_t flags, snake_stream_t stream)
 {
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_adam_step: n < 0");
-    SNAKE_REQUIRE(step >= 1, SNAKE_ERR_INVALID_ARG, "snake_adam_step: step = %d < 1", step);
+    SNAKE_REQUIRE(step_dev != nullptr || step >= 1, SNAKE_ERR_INVALID_ARG, "snake_adam_step: step = %d < 1",
+                  step);
     SNAKE_REQUIRE(b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f, SNAKE_ERR_INVALID_ARG,
                   "snake_adam_step: betas must be in [0, 1)");
     if (n == 0) return SNAKE_OK;
@@ -79,8 +113,8 @@ int snake_adam_step(float *p, float *g, float *m, float *v, int64_t n, float lr,
     a.b2 = b2;
     a.eps = eps;
     a.l2 = l2;
-    a.c1 = (float)(1.0 - pow((double)b1, (double)step));
-    a.c2 = (float)(1.0 - pow((double)b2, (double)step));
+    a.step_dev = step_dev;
+    bias_corrections(a, step_dev ? 1 : step);
     a.zero_grad = (flags & SNAKE_ADAM_ZERO_GRAD) ? 1 : 0;
     const int64_t n4 = n / 4;
     const int tail = (int)(n - n4 * 4);

@@ -2,6 +2,9 @@
 // colour-consistency MSE loss (Sec. 4.4), and their adjoint.
 //
 // One wavefront per ray, one lane per sample, 64-sample chunks with a carry.
+// An optional sample map redirects the per-sample values (sigma, rgb and the
+// adjoints): the window step keeps them in tile-partitioned order while t0,
+// t1 and packed_info stay in ray order.
 // Transmittance T_i = prod_{j<i} exp(-s_j) is taken in the log domain: an
 // exclusive wave64 prefix sum of the optical depths s_j = sigma_j delta_j,
 // then one exp per sample; alpha_i = -expm1(-s_i) keeps full relative
@@ -23,8 +26,8 @@ struct SampleVals {
 // Per-sample quantities of chunk [c0, c0+64) of a ray with `count` samples
 // and optical depth `carry` accumulated before the chunk.
 __device__ __forceinline__ SampleVals chunk_vals(const float *sigma, const float *rgb, const float *t0,
-                                                 const float *t1, int64_t start, int count, int c0,
-                                                 float carry, float &chunk_depth_sum, float &incl)
+                                                 const float *t1, const int32_t *map, int64_t start, int count,
+                                                 int c0, float carry, float &chunk_depth_sum, float &incl)
 {
     const int lane = lane_id();
     SampleVals v;
@@ -34,12 +37,13 @@ __device__ __forceinline__ SampleVals chunk_vals(const float *sigma, const float
     v.c[0] = v.c[1] = v.c[2] = 0.0f;
     if (v.valid) {
         const int64_t idx = start + k;
+        const int64_t m = map ? (int64_t)map[idx] : idx;
         a0 = t0[idx];
         a1 = t1[idx];
-        s = sigma[idx] * (a1 - a0);
-        v.c[0] = rgb[3 * idx];
-        v.c[1] = rgb[3 * idx + 1];
-        v.c[2] = rgb[3 * idx + 2];
+        s = sigma[m] * (a1 - a0);
+        v.c[0] = rgb[3 * m];
+        v.c[1] = rgb[3 * m + 1];
+        v.c[2] = rgb[3 * m + 2];
     }
     incl = wave_inclusive_sum(s);
     // exclusive prefix = the previous lane's inclusive one (no subtraction,
@@ -63,7 +67,8 @@ __device__ __forceinline__ int first_dead(const SampleVals &v, float thr)
 
 __global__ __launch_bounds__(256) void composite_fwd_kernel(
     const float *__restrict__ sigma, const float *__restrict__ rgb, const float *__restrict__ t0,
-    const float *__restrict__ t1, const int32_t *__restrict__ info, int R, float thr,
+    const float *__restrict__ t1, const int32_t *__restrict__ info, int R, const int32_t *__restrict__ map,
+    float thr,
     const float *__restrict__ target, float loss_scale, float *__restrict__ rgb_out,
     float *__restrict__ opacity, float *__restrict__ depth, int32_t *__restrict__ n_alive,
     float *__restrict__ loss)
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(
         int kept = 0;
         for (int c0 = 0; c0 < count; c0 += 64) {
             float tot, incl;
-            SampleVals v = chunk_vals(sigma, rgb, t0, t1, start, count, c0, carry, tot, incl);
+            SampleVals v = chunk_vals(sigma, rgb, t0, t1, map, start, count, c0, carry, tot, incl);
             const int fd = first_dead(v, thr);
             const bool alive = v.valid && lane < fd;
             if (alive) {
@@ -125,7 +130,8 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(
 
 __global__ __launch_bounds__(256) void composite_bwd_kernel(
     const float *__restrict__ sigma, const float *__restrict__ rgb, const float *__restrict__ t0,
-    const float *__restrict__ t1, const int32_t *__restrict__ info, int R, const int32_t *__restrict__ n_alive,
+    const float *__restrict__ t1, const int32_t *__restrict__ info, int R, const int32_t *__restrict__ map,
+    const int32_t *__restrict__ n_alive,
     const float *__restrict__ target, float loss_scale, float *__restrict__ dsigma, float *__restrict__ drgb)
 {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
@@ -141,7 +147,7 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(
         float C[3] = {0.f, 0.f, 0.f}, carry = 0.f;
         for (int c0 = 0; c0 < kept; c0 += 64) {
             float tot, incl;
-            SampleVals v = chunk_vals(sigma, rgb, t0, t1, start, kept, c0, carry, tot, incl);
+            SampleVals v = chunk_vals(sigma, rgb, t0, t1, map, start, kept, c0, carry, tot, incl);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) C[ch] += v.w * v.c[ch];
             carry += tot;
@@ -156,15 +162,16 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(
         carry = 0.f;
         for (int c0 = 0; c0 < count; c0 += 64) {
             const int64_t idx = start + c0 + lane;
+            const int64_t m = (c0 + lane < count) ? (map ? (int64_t)map[idx] : idx) : 0;
             if (c0 >= kept) {
                 if (c0 + lane < count) {
-                    dsigma[idx] = 0.f;
-                    drgb[3 * idx] = drgb[3 * idx + 1] = drgb[3 * idx + 2] = 0.f;
+                    dsigma[m] = 0.f;
+                    drgb[3 * m] = drgb[3 * m + 1] = drgb[3 * m + 2] = 0.f;
                 }
                 continue;
             }
             float tot, incl;
-            SampleVals v = chunk_vals(sigma, rgb, t0, t1, start, kept, c0, carry, tot, incl);
+            SampleVals v = chunk_vals(sigma, rgb, t0, t1, map, start, kept, c0, carry, tot, incl);
             const float Tn = expf(-(carry + incl));
             float Ai[3], ds = 0.f;
 #pragma unroll
@@ -177,13 +184,13 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(
             if (c0 + lane < count) {
                 if (v.valid) {
                     const float delta = t1[idx] - t0[idx];
-                    dsigma[idx] = delta * ds;
-                    drgb[3 * idx] = v.w * g[0];
-                    drgb[3 * idx + 1] = v.w * g[1];
-                    drgb[3 * idx + 2] = v.w * g[2];
+                    dsigma[m] = delta * ds;
+                    drgb[3 * m] = v.w * g[0];
+                    drgb[3 * m + 1] = v.w * g[1];
+                    drgb[3 * m + 2] = v.w * g[2];
                 } else {
-                    dsigma[idx] = 0.f;
-                    drgb[3 * idx] = drgb[3 * idx + 1] = drgb[3 * idx + 2] = 0.f;
+                    dsigma[m] = 0.f;
+                    drgb[3 * m] = drgb[3 * m + 1] = drgb[3 * m + 2] = 0.f;
                 }
             }
             carry += tot;
@@ -199,9 +206,9 @@ using namespace snake;
 extern "C" {
 
 int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
-                        const int32_t *packed_info, int32_t R, float early_stop_T, const float *target,
-                        float loss_scale, float *rgb_out, float *opacity, float *depth, int32_t *n_alive,
-                        float *loss, snake_stream_t stream)
+                        const int32_t *packed_info, int32_t R, const int32_t *sample_map, float early_stop_T,
+                        const float *target, float loss_scale, float *rgb_out, float *opacity, float *depth,
+                        int32_t *n_alive, float *loss, snake_stream_t stream)
 {
     SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "snake_composite_fwd: R < 0");
     SNAKE_REQUIRE(early_stop_T >= 0.0f && early_stop_T < 1.0f, SNAKE_ERR_INVALID_ARG,
@@ -215,14 +222,14 @@ int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, c
     SNAKE_NOT_NULL(rgb_out);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     composite_fwd_kernel<<<grid_for((int64_t)R * 64, 256, 8), 256, 0, st>>>(
-        sigma, rgb, t0, t1, packed_info, R, early_stop_T, target, loss_scale, rgb_out, opacity, depth, n_alive,
-        loss);
+        sigma, rgb, t0, t1, packed_info, R, sample_map, early_stop_T, target, loss_scale, rgb_out, opacity, depth,
+        n_alive, loss);
     return launch_status(__func__);
 }
 
 int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
-                        const int32_t *packed_info, int32_t R, const int32_t *n_alive, const float *target,
-                        float loss_scale, float *dsigma, float *drgb, snake_stream_t stream)
+                        const int32_t *packed_info, int32_t R, const int32_t *sample_map, const int32_t *n_alive,
+                        const float *target, float loss_scale, float *dsigma, float *drgb, snake_stream_t stream)
 {
     SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "snake_composite_bwd: R < 0");
     if (R == 0) return SNAKE_OK;
@@ -236,7 +243,7 @@ int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, c
     SNAKE_NOT_NULL(drgb);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     composite_bwd_kernel<<<grid_for((int64_t)R * 64, 256, 8), 256, 0, st>>>(
-        sigma, rgb, t0, t1, packed_info, R, n_alive, target, loss_scale, dsigma, drgb);
+        sigma, rgb, t0, t1, packed_info, R, sample_map, n_alive, target, loss_scale, dsigma, drgb);
     return launch_status(__func__);
 }
 

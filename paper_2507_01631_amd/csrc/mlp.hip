@@ -38,11 +38,56 @@ struct MlpArgs {
     int L, F, n_feat;       // encoding levels, features per level, L*F
     int n_dir, CL, CO;      // directions (3|6), colour hidden layers (1|2), colour outputs (3|4)
     int cin_real;           // 15 + n_dir
-    int64_t off[5];         // offsets of D1, D2, C1, C2, CO in the packed weights
-    int64_t P;              // packed parameter count
-    int64_t R;              // rows of view / sun (ray ids must be below)
+    int32_t off[5];         // offsets of D1, D2, C1, C2, CO in the packed weights
+    int32_t P;              // packed parameter count
+    int32_t R;              // rows of view / sun (ray ids must be below)
     unsigned int *err;      // device error word
+    int K;                  // NeRF tiles, each with its own weight set
+    const int64_t *tile_start;  // [K+2] sample groups per tile (NULL: one group)
 };
+
+constexpr int kMaxMlpTiles = 16;
+const int64_t kNoTable = 0;   // stands in for tile_start in size queries
+
+// Work units of 64 samples (one 16-sample matrix tile per wavefront) that
+// never straddle two NeRF tiles.  Group k < K is samples [ts[k], ts[k+1]) of
+// the call; group K holds samples whose tile id was invalid (dropped).  The
+// bounds are clamped to be non-decreasing and within [0, ne], so a corrupt
+// table cannot send a unit out of range.  Every thread of a block sees the
+// same units, so branches on them are block-uniform.
+struct UnitTable {
+    int64_t ts[kMaxMlpTiles + 2];
+    int64_t ub[kMaxMlpTiles + 2];   // first unit of each group; ub[K+1] = total
+};
+
+__device__ void setup_units(UnitTable &U, const MlpArgs &a, int64_t ne)
+{
+    if (threadIdx.x == 0) {
+        int64_t prev = 0, units = 0;
+        for (int k = 0; k <= a.K + 1; ++k) {
+            int64_t v;
+            if (a.tile_start)
+                v = a.tile_start[k];
+            else
+                v = k == 0 ? 0 : ne;
+            v = v < prev ? prev : (v > ne ? ne : v);
+            if (k > 0) units += (v - prev + 63) / 64;
+            U.ts[k] = v;
+            U.ub[k] = units;        // ub[k] = units of groups < k
+            prev = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Group, first sample and end of unit u.
+__device__ __forceinline__ void locate(const UnitTable &U, int K, int64_t u, int &k, int64_t &s0, int64_t &s1)
+{
+    k = 0;
+    while (k < K && u >= U.ub[k + 1]) ++k;
+    s0 = U.ts[k] + 64 * (u - U.ub[k]);
+    s1 = U.ts[k + 1];
+}
 
 // Padded weight value: D1 [64][32], D2 [16][64], C1 [64][32] whose column p
 // is o_p (p < 16, column 0 = sigma logit is 0) or direction p-16, C2 [64][64],
@@ -353,10 +398,16 @@ __device__ __forceinline__ void load_acts(const float *row, Acts<PREC, CL> &A)
     act_get(row, AL::OUT, A.out);
 }
 
-// Per-lane inputs of one 16-sample tile of the adjoint.
-struct BwdIn {
+// Per-lane inputs of one 16-sample tile of the adjoint: where they are, and
+// the values.
+struct BwdIdx {
     int64_t s, si;
-    bool in_range, valid;
+    int ray;
+    bool in_range;
+};
+
+struct BwdIn {
+    bool valid;
     float x[2][4], dirs[4], dsig, dr[3];
 };
 
@@ -373,15 +424,31 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
 {
     typedef Layout<PREC, CL> Lt;
     __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::FWD];
-    build_forward<PREC, CL>(lds, w, a);
-    __syncthreads();
+    __shared__ UnitTable U;
     const int64_t ne = effective_n(n, n_dev);
-    const int64_t tiles = (ne + 15) / 16;
-    const int lane = lane_id(), i = lane & 15, q = lane >> 4;
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); t < tiles; t += nw) {
-        const int64_t s = t * 16 + i;
-        const bool valid = s < ne;
+    setup_units(U, a, ne);
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+    const int64_t total = U.ub[a.K + 1];
+    int cur = -1;
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        int k;
+        int64_t s0, s1;
+        locate(U, a.K, u, k, s0, s1);
+        const int64_t s = s0 + 16 * wv + i;
+        const bool valid = s < s1;
+        if (k == a.K) {                                      // invalid tile id: dropped
+            if (q == 0 && valid) {
+                sigma[s] = 0.0f;
+                rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
+            }
+            continue;
+        }
+        if (k != cur) {                                      // block-uniform
+            __syncthreads();
+            build_forward<PREC, CL>(lds, w + (int64_t)k * a.P, a);
+            __syncthreads();
+            cur = k;
+        }
         const int64_t si = valid ? (sidx ? sidx[s] : s) : 0;
         Acts<PREC, CL> A;
         int64_t ray = valid ? ray_id[si] : 0;
@@ -500,6 +567,54 @@ __device__ __forceinline__ void flush(float *R, int base, int cols, const f4 (&a
             }
 }
 
+// Padded weight-gradient row of one block and weight set: D1 [64][32] | D2
+// [16][64] | C1 [64][32] | C2 [64][64] (two colour layers) | CO [16][64].
+template <int CL>
+struct PadRow {
+    static constexpr int D1 = 0, D2 = 2048, C1 = 3072, C2 = 5120;
+    static constexpr int CO = C2 + (CL == 2 ? 4096 : 0);
+    static constexpr int W = CO + 1024;
+};
+
+// Position of packed weight p in the padded row.
+__device__ __forceinline__ int padded_index(const MlpArgs &a, int p)
+{
+    const int C2 = 5120, CO = C2 + (a.CL == 2 ? 4096 : 0);
+    if (p < a.off[1]) return p;
+    if (p < a.off[2]) return 2048 + (p - a.off[1]);
+    if (p < a.off[2] + 64 * a.cin_real) {
+        const int e = p - a.off[2], h = e / a.cin_real, c = e - h * a.cin_real;
+        return 3072 + h * 32 + (c < 15 ? c + 1 : 16 + (c - 15));
+    }
+    if (a.CL == 2 && p < a.off[4]) return C2 + (p - a.off[3]);
+    return CO + (p - a.off[4]);
+}
+
+// Sum the four wavefronts' weight-gradient tiles in a fixed order into LDS,
+// then copy the padded row out.  Block-uniform: every thread calls it.
+template <int PREC, int CL>
+__device__ void flush_partial(float *R, float *out, const f4 (&acc_d1)[4][2], const f4 (&acc_d2)[1][4],
+                              const f4 (&acc_c1)[4][2], const f4 (&acc_c2)[4][4], const f4 (&acc_co)[1][4])
+{
+    typedef PadRow<CL> PR;
+    static_assert(PR::W <= 4 * kStageRows * kStageStride, "reduction buffer");
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (wv == w) {
+            flush(R, PR::D1, 32, acc_d1, w == 0);
+            flush(R, PR::D2, 64, acc_d2, w == 0);
+            flush(R, PR::C1, 32, acc_c1, w == 0);
+            if (CL == 2) flush(R, PR::C2, 64, acc_c2, w == 0);
+            flush(R, PR::CO, 64, acc_co, w == 0);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < PR::W / 4; e += kBlock)
+        reinterpret_cast<f4 *>(out)[e] = reinterpret_cast<const f4 *>(R)[e];
+    __syncthreads();
+}
+
 template <typename FT>
 __device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s, bool valid, const MlpArgs &a,
                                             const float (&dx)[2][4])
@@ -536,199 +651,227 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
     const float *__restrict__ view, const float *__restrict__ sun, const int32_t *__restrict__ ray_id,
     const int32_t *__restrict__ sidx, int64_t n, const int64_t *__restrict__ n_dev,
     const float *__restrict__ dsigma, const float *__restrict__ drgb, const float *__restrict__ act,
-    float *__restrict__ dfeat, float *__restrict__ partial)
+    float *__restrict__ dfeat, float *__restrict__ partial, const typename FragT<PREC>::T *__restrict__ frag)
 {
     typedef Layout<PREC, CL> Lt;
     __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::ALL];
     __shared__ __attribute__((aligned(16))) float stage_buf[4 * kStageRows * kStageStride];
-    build_forward<PREC, CL>(lds, w, a);
-    build_frag<PREC, 64, 16>(lds + Lt::COT, w, a, M_CO, true);
-    if (CL == 2) build_frag<PREC, 64, 64>(lds + Lt::C2T, w, a, M_C2, true);
-    build_frag<PREC, 16, 64>(lds + Lt::C1T, w, a, M_C1, true);
-    build_frag<PREC, 64, 16>(lds + Lt::D2T, w, a, M_D2, true);
-    build_frag<PREC, 32, 64>(lds + Lt::D1T, w, a, M_D1, true);
-    __syncthreads();
-
+    __shared__ UnitTable U;
     const int64_t ne = effective_n(n, n_dev);
-    const int64_t tiles = (ne + 15) / 16;
+    setup_units(U, a, ne);
     const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
     float *st = stage_buf + wv * kStageRows * kStageStride;
 
     f4 acc_d1[4][2], acc_d2[1][4], acc_c1[4][2], acc_c2[4][4], acc_co[1][4];
-    zero(acc_d1);
-    zero(acc_d2);
-    zero(acc_c1);
-    zero(acc_c2);
-    zero(acc_co);
+    auto zero_all = [&]() {
+        zero(acc_d1);
+        zero(acc_d2);
+        zero(acc_c1);
+        zero(acc_c2);
+        zero(acc_co);
+    };
 
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    // inputs of the next tile are loaded while the current one is computed
-    auto load = [&](int64_t t, BwdIn &in) {
-        in.s = t * 16 + i;
-        in.in_range = in.s < ne;
+    // inputs of the next unit are loaded while the current one is computed
+    int64_t g1 = 0, gbase = 0;   // end of the current group; sample of unit 0 in its numbering
+    const int lofs = 16 * wv + i;
+    // the index chain (list entry -> sample -> ray) of the next unit is
+    // resolved while the current unit is computed
+    auto load_idx = [&](int u, BwdIdx &in) {
+        in.s = gbase + 64 * (int64_t)u + lofs;
+        in.in_range = in.s < g1;
         in.si = in.in_range ? (sidx ? sidx[in.s] : in.s) : 0;
-        int64_t ray = in.in_range ? ray_id[in.si] : 0;
-        in.valid = in.in_range && ray >= 0 && ray < a.R;    // a bad ray id drops the sample
-        if (in.in_range && !in.valid && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
-        ray = in.valid ? ray : 0;
-        load_features(feat, feat_ld, in.si, in.valid, a, in.x);
+        in.ray = in.in_range ? ray_id[in.si] : 0;
+    };
+    auto load_data = [&](const BwdIdx &ix, BwdIn &in) {
+        in.valid = ix.in_range && ix.ray >= 0 && ix.ray < a.R;    // a bad ray id drops the sample
+        if (ix.in_range && !in.valid && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
+        const int ray = in.valid ? ix.ray : 0;
+        load_features(feat, feat_ld, ix.si, in.valid, a, in.x);
         load_dirs(view, sun, ray, in.valid, a, in.dirs);
         in.dsig = in.dr[0] = in.dr[1] = in.dr[2] = 0.0f;
         if (q == 0 && in.valid) {
-            in.dsig = dsigma[in.si];
+            in.dsig = dsigma[ix.si];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) in.dr[c] = drgb[3 * in.si + c];
+            for (int c = 0; c < 3; ++c) in.dr[c] = drgb[3 * ix.si + c];
         }
     };
-    int64_t t = (int64_t)blockIdx.x * (kBlock / 64) + wv;
-    BwdIn cur;
-    if (t < tiles) load(t, cur);
-    for (; t < tiles; t += nw) {
-        BwdIn nxt;
-        if (t + nw < tiles) load(t + nw, nxt);
-        const int64_t s = cur.s;
-        const bool in_range = cur.in_range, valid = cur.valid;
-        Acts<PREC, CL> A;
+    const int G = (int)gridDim.x;
+    for (int k = 0; k <= a.K; ++k) {                          // block-uniform
+        // this block's units of group k: u = blockIdx.x (mod G) in [ub[k], ub[k+1])
+        const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
+        int u = ua + (((int)blockIdx.x - ua) % G + G) % G;
+        if (u >= ue) continue;
+        g1 = U.ts[k + 1];
+        gbase = U.ts[k] - 64 * (int64_t)ua;
+        if (k == a.K) {                                       // invalid tile id: dropped
+            const float zx[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            for (; u < ue; u += G) {
+                const int64_t s = gbase + 64 * (int64_t)u + lofs;
+                store_dfeat<FT>(dfeat, n, s, s < g1, a, zx);
+            }
+            continue;
+        }
+        {
+            // tile k's fragments, prepared once by mlp_frag_kernel, into LDS
+            constexpr int n16 = Lt::ALL * (int)sizeof(typename Lt::T) / 16;
+            const uint4 *src = reinterpret_cast<const uint4 *>(frag + (int64_t)k * Lt::ALL);
+            uint4 *dst = reinterpret_cast<uint4 *>(lds);
+            __syncthreads();
+            for (int e = threadIdx.x; e < n16; e += kBlock) dst[e] = src[e];
+            __syncthreads();
+        }
+        zero_all();
+        BwdIdx ix;
+        load_idx(u, ix);
+        for (; u < ue; u += G) {
+            BwdIn cur;
+            load_data(ix, cur);
+            const int64_t s = ix.s, si = ix.si;
+            const bool in_range = ix.in_range, valid = cur.valid;
+            if (u + G < ue) load_idx(u + G, ix);
+            Acts<PREC, CL> A;
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) A.x[u][r] = cur.x[u][r];
+                for (int r = 0; r < 4; ++r) A.x[h][r] = cur.x[h][r];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) A.cin[1][r] = cur.dirs[r];
-        if constexpr (LOAD) {
-            if (valid) {
-                load_acts<PREC, CL>(act + cur.si * ActLayout<CL>::W, A);
+            for (int r = 0; r < 4; ++r) A.cin[1][r] = cur.dirs[r];
+            if constexpr (LOAD) {
+                if (valid) {
+                    load_acts<PREC, CL>(act + si * ActLayout<CL>::W, A);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        A.o[0][r] = A.cin[0][r] = A.out[0][r] = 0.0f;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) A.h1[t][r] = A.g1[t][r] = A.g2[t][r] = 0.0f;
+                    }
+                }
             } else {
+                forward_tile<PREC, CL>(lds, A);
+            }
+
+            // output activation adjoint (rows 0..3 live in lane group 0)
+            float dout[1][4] = {{0.f, 0.f, 0.f, 0.f}};
+            const float dsig = cur.dsig;
+            if (q == 0 && valid) {
+                const float *dr = cur.dr;
+                if (a.CO == 3) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    A.o[0][r] = A.cin[0][r] = A.out[0][r] = 0.0f;
+                    for (int c = 0; c < 3; ++c) {
+                        const float y = sigmoidf(A.out[0][c]);
+                        dout[0][c] = dr[c] * y * (1.0f - y);
+                    }
+                } else {
+                    const float vis = sigmoidf(A.out[0][3]);
+                    float dvis = 0.0f;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) A.h1[t][r] = A.g1[t][r] = A.g2[t][r] = 0.0f;
+                    for (int c = 0; c < 3; ++c) {
+                        const float alb = sigmoidf(A.out[0][c]);
+                        dout[0][c] = dr[c] * vis * alb * (1.0f - alb);
+                        dvis += dr[c] * alb;
+                    }
+                    dout[0][3] = dvis * vis * (1.0f - vis);
                 }
             }
-        } else {
-            forward_tile<PREC, CL>(lds, A);
-        }
-
-        // output activation adjoint (rows 0..3 live in lane group 0)
-        float dout[1][4] = {{0.f, 0.f, 0.f, 0.f}};
-        const float dsig = cur.dsig;
-        if (q == 0 && valid) {
-            const float *dr = cur.dr;
-            if (a.CO == 3) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float y = sigmoidf(A.out[0][c]);
-                    dout[0][c] = dr[c] * y * (1.0f - y);
-                }
+            float dg2[4][4], dg1[4][4], dob[1][4], dh1[4][4], dx[2][4];
+            if constexpr (CL == 2) {
+                apply<PREC, 64, 16>(lds + Lt::COT, dout, dg2);
+                relu_mask(dg2, A.g2);
+                apply<PREC, 64, 64>(lds + Lt::C2T, dg2, dg1);
             } else {
-                const float vis = sigmoidf(A.out[0][3]);
-                float dvis = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float alb = sigmoidf(A.out[0][c]);
-                    dout[0][c] = dr[c] * vis * alb * (1.0f - alb);
-                    dvis += dr[c] * alb;
-                }
-                dout[0][3] = dvis * vis * (1.0f - vis);
+                apply<PREC, 64, 16>(lds + Lt::COT, dout, dg1);
             }
-        }
-        float dg2[4][4], dg1[4][4], dob[1][4], dh1[4][4], dx[2][4];
-        if constexpr (CL == 2) {
-            apply<PREC, 64, 16>(lds + Lt::COT, dout, dg2);
-            relu_mask(dg2, A.g2);
-            apply<PREC, 64, 64>(lds + Lt::C2T, dg2, dg1);
-        } else {
-            apply<PREC, 64, 16>(lds + Lt::COT, dout, dg1);
-        }
-        relu_mask(dg1, A.g1);
-        apply<PREC, 16, 64>(lds + Lt::C1T, dg1, dob);
-        if (q == 0) dob[0][0] = dsig * expf(A.o[0][0]);   // sigma = exp(o_0)
-        apply<PREC, 64, 16>(lds + Lt::D2T, dob, dh1);
-        relu_mask(dh1, A.h1);
-        apply<PREC, 32, 64>(lds + Lt::D1T, dh1, dx);
-        store_dfeat<FT>(dfeat, n, s, in_range, a, dx);       // dropped samples store zeros
+            relu_mask(dg1, A.g1);
+            apply<PREC, 16, 64>(lds + Lt::C1T, dg1, dob);
+            if (q == 0) dob[0][0] = dsig * expf(A.o[0][0]);   // sigma = exp(o_0)
+            apply<PREC, 64, 16>(lds + Lt::D2T, dob, dh1);
+            relu_mask(dh1, A.h1);
+            apply<PREC, 32, 64>(lds + Lt::D1T, dh1, dx);
+            store_dfeat<FT>(dfeat, n, s, in_range, a, dx);       // dropped samples store zeros
 
-        // weight gradients: stage (dy, x) pairs as [row][sample], MFMA over samples
-        stage<1>(st, 0, dout);
-        stage<4>(st, 16, CL == 2 ? A.g2 : A.g1);
-        wave_sync();
-        dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_co);
-        wave_sync();
-        if constexpr (CL == 2) {
-            stage<4>(st, 0, dg2);
-            stage<4>(st, 64, A.g1);
+            // weight gradients: stage (dy, x) pairs as [row][sample], MFMA over samples
+            stage<1>(st, 0, dout);
+            stage<4>(st, 16, CL == 2 ? A.g2 : A.g1);
             wave_sync();
-            dw_accumulate<PREC, 4, 4>(st, 0, 64, acc_c2);
+            dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_co);
+            wave_sync();
+            if constexpr (CL == 2) {
+                stage<4>(st, 0, dg2);
+                stage<4>(st, 64, A.g1);
+                wave_sync();
+                dw_accumulate<PREC, 4, 4>(st, 0, 64, acc_c2);
+                wave_sync();
+            }
+            stage<4>(st, 0, dg1);
+            stage<2>(st, 64, A.cin);
+            wave_sync();
+            dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_c1);
+            wave_sync();
+            stage<1>(st, 0, dob);
+            stage<4>(st, 16, A.h1);
+            wave_sync();
+            dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_d2);
+            wave_sync();
+            stage<4>(st, 0, dh1);
+            stage<2>(st, 64, A.x);
+            wave_sync();
+            dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_d1);
             wave_sync();
         }
-        stage<4>(st, 0, dg1);
-        stage<2>(st, 64, A.cin);
-        wave_sync();
-        dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_c1);
-        wave_sync();
-        stage<1>(st, 0, dob);
-        stage<4>(st, 16, A.h1);
-        wave_sync();
-        dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_d2);
-        wave_sync();
-        stage<4>(st, 0, dh1);
-        stage<2>(st, 64, A.x);
-        wave_sync();
-        dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_d1);
-        wave_sync();
-        cur = nxt;
-    }
-
-    // block reduction in a fixed wave order into the padded buffer R
-    // (D1 [64][32] | D2 [16][64] | C1 [64][32] | C2 [64][64] | CO [16][64])
-    constexpr int RD1 = 0, RD2 = 2048, RC1 = 3072, RC2 = 5120, RCO = 5120 + (CL == 2 ? 4096 : 0);
-    float *R = stage_buf;
-    static_assert(RCO + 1024 <= 4 * kStageRows * kStageStride, "reduction buffer");
-    __syncthreads();
-    for (int w = 0; w < kBlock / 64; ++w) {
-        if (wv == w) {
-            flush(R, RD1, 32, acc_d1, w == 0);
-            flush(R, RD2, 64, acc_d2, w == 0);
-            flush(R, RC1, 32, acc_c1, w == 0);
-            if (CL == 2) flush(R, RC2, 64, acc_c2, w == 0);
-            flush(R, RCO, 64, acc_co, w == 0);
-        }
-        __syncthreads();
-    }
-    // unpadded packed order into this block's partial row
-    float *out = partial + (int64_t)blockIdx.x * a.P;
-    for (int64_t p = threadIdx.x; p < a.P; p += kBlock) {
-        float v;
-        if (p < a.off[1]) {
-            v = R[RD1 + p];
-        } else if (p < a.off[2]) {
-            v = R[RD2 + (p - a.off[1])];
-        } else if (p < a.off[2] + 64 * a.cin_real) {
-            const int e = (int)(p - a.off[2]), h = e / a.cin_real, c = e - h * a.cin_real;
-            const int col = c < 15 ? c + 1 : 16 + (c - 15);
-            v = R[RC1 + h * 32 + col];
-        } else if (CL == 2 && p < a.off[4]) {
-            v = R[RC2 + (p - a.off[3])];
-        } else {
-            v = R[RCO + (p - a.off[4])];
-        }
-        out[p] = v;
+        flush_partial<PREC, CL>(stage_buf, partial + ((int64_t)blockIdx.x * a.K + k) * PadRow<CL>::W, acc_d1,
+                                acc_d2, acc_c1, acc_c2, acc_co);
     }
 }
 
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const float *__restrict__ partial, int nb,
-                                                              int64_t P, float *__restrict__ dW)
+// Matrix-core fragments (forward and transposed) of weight set blockIdx.x,
+// in the LDS layout of the adjoint kernel.
+template <int PREC, int CL>
+__global__ __launch_bounds__(kBlock) void mlp_frag_kernel(MlpArgs a, const float *__restrict__ w,
+                                                          typename FragT<PREC>::T *__restrict__ frag)
 {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    typedef Layout<PREC, CL> Lt;
+    typename Lt::T *dst = frag + (int64_t)blockIdx.x * Lt::ALL;
+    const float *wk = w + (int64_t)blockIdx.x * a.P;
+    build_forward<PREC, CL>(dst, wk, a);
+    build_frag<PREC, 64, 16>(dst + Lt::COT, wk, a, M_CO, true);
+    if (CL == 2) build_frag<PREC, 64, 64>(dst + Lt::C2T, wk, a, M_C2, true);
+    build_frag<PREC, 16, 64>(dst + Lt::C1T, wk, a, M_C1, true);
+    build_frag<PREC, 64, 16>(dst + Lt::D2T, wk, a, M_D2, true);
+    build_frag<PREC, 32, 64>(dst + Lt::D1T, wk, a, M_D1, true);
+}
+
+// dW[k][p] += the sum, over the blocks that processed units of weight set k
+// (in block order), of their padded rows.  Which blocks those are follows from
+// the same unit table the adjoint used (block b takes units u = b mod grid).
+__global__ __launch_bounds__(256) void reduce_partials_kernel(MlpArgs a, const float *__restrict__ partial, int nb,
+                                                              int W, int64_t n, const int64_t *__restrict__ n_dev,
+                                                              float *__restrict__ dW)
+{
+    __shared__ UnitTable U;
+    setup_units(U, a, effective_n(n, n_dev));
+    const int64_t total = (int64_t)a.K * a.P;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / a.P), p = (int)(e - (int64_t)k * a.P);
+        const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
+        const float *src = partial + (int64_t)k * W + padded_index(a, p);
         float s = 0.0f;
-        for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * P + p];
-        dW[p] += s;
+        for (int b = 0; b < nb; ++b) {
+            const int u = ua + ((b - ua) % nb + nb) % nb;   // block b's first unit of set k
+            if (u < ue) s += src[(int64_t)b * a.K * W];
+        }
+        dW[e] += s;
     }
 }
 
-int make_args(const snake_mlp_desc *m, int64_t R, MlpArgs &a, const char *fn)
+int make_args(const snake_mlp_desc *m, int64_t R, MlpArgs &a, const char *fn, int K = 1,
+              const int64_t *tile_start = nullptr)
 {
+    SNAKE_REQUIRE(K >= 1 && K <= kMaxMlpTiles, SNAKE_ERR_INVALID_ARG, "%s: K = %d not in [1, %d]", fn, K,
+                  kMaxMlpTiles);
+    SNAKE_REQUIRE(K == 1 || tile_start != nullptr, SNAKE_ERR_NULL, "%s: tile_start is NULL with K = %d", fn, K);
+    a.K = K;
+    a.tile_start = tile_start;
     SNAKE_REQUIRE(m != nullptr, SNAKE_ERR_NULL, "%s: MLP descriptor is NULL", fn);
     SNAKE_REQUIRE(m->n_levels >= 1 && (m->n_features == 1 || m->n_features == 2 || m->n_features == 4),
                   SNAKE_ERR_INVALID_ARG, "%s: bad encoding shape L=%d F=%d", fn, m->n_levels, m->n_features);
@@ -769,12 +912,26 @@ int make_args(const snake_mlp_desc *m, int64_t R, MlpArgs &a, const char *fn)
     return SNAKE_OK;
 }
 
+// Adjoint workspace: per-block partial rows [blocks][K][P] float, then the
+// K weight sets' fragments (FP32 size, the larger of the two forms).
+size_t partial_bytes(const MlpArgs &a)
+{
+    const size_t W = a.CL == 2 ? PadRow<2>::W : PadRow<1>::W;
+    return ((size_t)kMaxBwdBlocks * (size_t)a.K * W * sizeof(float) + 255) / 256 * 256;
+}
+
+size_t bwd_ws_bytes(const MlpArgs &a)
+{
+    const size_t frag = a.CL == 2 ? (size_t)Layout<P_F32, 2>::ALL : (size_t)Layout<P_F32, 1>::ALL;
+    return partial_bytes(a) + (size_t)a.K * frag * sizeof(float);
+}
+
 template <int PREC, int CL, typename FT>
 void launch_fwd(const MlpArgs &a, const float *w, const void *feat, const float *view, const float *sun,
                 const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev, float *sigma,
                 float *rgb, float *act, hipStream_t st)
 {
-    const unsigned grid = grid_for((n + 15) / 16 * 64, kBlock, 4);
+    const unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, 4);
     if (act)
         mlp_fwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun,
                                                                     ray_id, sidx, n, n_dev, sigma, rgb, act);
@@ -789,17 +946,22 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
                 const float *dsigma, const float *drgb, const float *act, float *dW, float *dfeat, float *partial,
                 hipStream_t st)
 {
-    unsigned grid = grid_for((n + 15) / 16 * 64, kBlock, PREC == P_BF16 ? 2 : 1);
+    unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, PREC == P_BF16 ? 2 : 1);
     if (grid > (unsigned)kMaxBwdBlocks) grid = kMaxBwdBlocks;
+    typedef typename FragT<PREC>::T FragEl;
+    FragEl *frag = reinterpret_cast<FragEl *>(reinterpret_cast<char *>(partial) + partial_bytes(a));
+    mlp_frag_kernel<PREC, CL><<<a.K, kBlock, 0, st>>>(a, w, frag);
     if (act)
         mlp_bwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view,
                                                                     sun, ray_id, sidx, n, n_dev, dsigma, drgb, act,
-                                                                    dfeat, partial);
+                                                                    dfeat, partial, frag);
     else
         mlp_bwd_kernel<PREC, CL, FT, false><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld,
                                                                      view, sun, ray_id, sidx, n, n_dev, dsigma, drgb,
-                                                                     act, dfeat, partial);
-    reduce_partials_kernel<<<(unsigned)((a.P + 255) / 256), 256, 0, st>>>(partial, (int)grid, a.P, dW);
+                                                                     act, dfeat, partial, frag);
+    const int64_t kp = (int64_t)a.K * a.P;
+    reduce_partials_kernel<<<(unsigned)((kp + 255) / 256), 256, 0, st>>>(a, partial, (int)grid, PadRow<CL>::W, n,
+                                                                         n_dev, dW);
 }
 
 }  // namespace
@@ -823,19 +985,20 @@ int32_t snake_mlp_act_width(const snake_mlp_desc *m)
     return a.CL == 2 ? ActLayout<2>::W : ActLayout<1>::W;
 }
 
-size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m)
+size_t snake_mlp_bwd_workspace_bytes(const snake_mlp_desc *m, int32_t K)
 {
     MlpArgs a;
-    if (make_args(m, 0, a, __func__)) return 0;
-    return (size_t)kMaxBwdBlocks * (size_t)a.P * sizeof(float);
+    if (K < 1 || K > kMaxMlpTiles || make_args(m, 0, a, __func__, K, K > 1 ? &kNoTable : nullptr)) return 0;
+    return bwd_ws_bytes(a);
 }
 
-int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *feat, const float *view,
-                  const float *sun, const int32_t *ray_id, int32_t R, const int32_t *sample_idx, int64_t n,
-                  const int64_t *n_dev, float *sigma, float *rgb, float *act, snake_stream_t stream)
+int snake_mlp_fwd(const snake_mlp_desc *m, int32_t K, const float *weights, const int64_t *tile_start,
+                  const void *feat, const float *view, const float *sun, const int32_t *ray_id, int32_t R,
+                  const int32_t *sample_idx, int64_t n, const int64_t *n_dev, float *sigma, float *rgb,
+                  float *act, snake_stream_t stream)
 {
     MlpArgs a;
-    int rc = make_args(m, R, a, __func__);
+    int rc = make_args(m, R, a, __func__, K, tile_start);
     if (rc) return rc;
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_mlp_fwd: n < 0");
     if (n == 0) return SNAKE_OK;
@@ -874,14 +1037,15 @@ int snake_mlp_fwd(const snake_mlp_desc *m, const float *weights, const void *fea
     return launch_status(__func__);
 }
 
-int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *feat, int64_t feat_ld,
-                  const float *view, const float *sun, const int32_t *ray_id, int32_t R,
+int snake_mlp_bwd(const snake_mlp_desc *m, int32_t K, const float *weights, const int64_t *tile_start,
+                  const void *feat, int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
+                  int32_t R,
                   const int32_t *sample_idx, int64_t n, const int64_t *n_dev, const float *dsigma,
                   const float *drgb, const float *act, float *dW, float *dfeat, void *workspace,
                   size_t workspace_bytes, snake_stream_t stream)
 {
     MlpArgs a;
-    int rc = make_args(m, R, a, __func__);
+    int rc = make_args(m, R, a, __func__, K, tile_start);
     if (rc) return rc;
     SNAKE_REQUIRE(n >= 0, SNAKE_ERR_INVALID_ARG, "snake_mlp_bwd: n < 0");
     if (n == 0) return SNAKE_OK;
@@ -901,10 +1065,11 @@ int snake_mlp_bwd(const snake_mlp_desc *m, const float *weights, const void *fea
         SNAKE_ALIGNED(dfeat, 8);
     }
     SNAKE_ALIGNED(act, 16);
-    const size_t need = (size_t)kMaxBwdBlocks * (size_t)a.P * sizeof(float);
+    const size_t need = bwd_ws_bytes(a);
     SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= need, SNAKE_ERR_WORKSPACE,
                   "snake_mlp_bwd: workspace needs %zu bytes", need);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SNAKE_ALIGNED(workspace, 256);
     float *partial = static_cast<float *>(workspace);
     a.err = device_error_word();
     const bool bf = m->precision == SNAKE_BF16, fb = m->feat_dtype == SNAKE_BF16;

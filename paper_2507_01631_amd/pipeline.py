@@ -90,6 +90,7 @@ class TileNeRF:
         self.recompute = bool(recompute)
         self.act = None
         self.step_count = 0
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.R = 0
         self.R_cur = 0
         self.alloc(max_rays)
@@ -162,12 +163,12 @@ class TileNeRF:
         L.snake_composite_fwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R,
                               self.early_stop, target, loss_scale, self.rgb_out, self.opacity,
                               self.depth, self.n_alive, self.loss if target is not None else None,
-                              stream)
+                              stream=stream)
 
     def field_bwd(self, R, target, loss_scale, sun=None, stream=None):
         """Adjoint chain; gradients accumulate into g_t / g_w."""
         L.snake_composite_bwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R,
-                              self.n_alive, target, loss_scale, self.dsigma, self.drgb, stream)
+                              self.n_alive, target, loss_scale, self.dsigma, self.drgb, stream=stream)
         if self.early_stop > 0.0:
             L.snake_pack_alive(self.packed_info, self.n_alive, R, self.alive_idx, self.cap,
                                self.n_alive_total, self.ws_sample, stream)
@@ -182,12 +183,16 @@ class TileNeRF:
         return n_dev
 
     def adam(self, stream=None):
+        """Adam on the table and the MLP; the step counter lives on the device
+        so that a captured step replays with the right bias corrections."""
         self.step_count += 1
+        L.snake_counter_add(self.step_dev, 1, stream=stream)
         L.snake_adam_step(self.table, self.g_t, self.m_t, self.v_t, self.table.numel(), self.lr,
-                          self.b1, self.b2, self.eps, self.step_count, 0.0, L.SNAKE_ADAM_ZERO_GRAD,
-                          stream)
+                          self.b1, self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD,
+                          step_dev=self.step_dev, stream=stream)
         L.snake_adam_step(self.params, self.g_w, self.m_w, self.v_w, self.P, self.lr, self.b1,
-                          self.b2, self.eps, self.step_count, 0.0, L.SNAKE_ADAM_ZERO_GRAD, stream)
+                          self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
+                          stream=stream)
 
     def train_step(self, rays_o, rays_d, target, sun=None, stream=None):
         """One full step on R rays (device tensors).  Returns the device count of

@@ -1,0 +1,197 @@
+"""The 2x2 window of Snake-NeRF (Sec. 4.4): four NeRF tiles, each with its own
+hash table and density/colour networks, trained together on the rays of the
+loaded window.
+
+One window step, every stage a libsnake kernel launched once for all tiles:
+
+    snake_sample_segmented (K boxes, per-ray budgets; rays cut at tile faces)
+    -> snake_tile_partition (samples grouped by tile, gathered copies)
+    -> snake_hashgrid_fwd (K tables, tile id per sample)
+    -> snake_mlp_fwd (K weight sets, one per 64-sample unit)
+    -> snake_composite_fwd / _bwd (per ray across tiles, sample map = inverse
+       partition, so the quadrature runs over the whole ray)
+    -> snake_mlp_bwd (K weight sets) -> snake_hashgrid_bwd (K tables)
+    -> snake_counter_add + snake_adam_step (all tables, all networks)
+
+Nothing in the step reads a device value on the host, so after a warm-up the
+whole step is captured in one HIP graph (``capture``) and replayed
+(``replay``) on fresh rays copied into the captured input buffers.
+
+``accept`` applies the window's ray acceptance (rays that cross only the
+loaded tiles), the filter from which training batches are drawn.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class WindowNeRF:
+    """K (normally 4) tile NeRFs with separate tables and networks."""
+
+    def __init__(self, *, boxes, zband, res, n_features, log2_table, n_dir, colour_layers, colour_out,
+                 precision="bf16", tables=None, mlp_params=None, max_rays=1 << 16, max_samples=None,
+                 samples=128, early_stop=0.0, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, hash_ws_gib=16.0,
+                 device="cuda"):
+        self.device = torch.device(device)
+        self.boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 6)
+        self.K = self.boxes.shape[0]
+        assert 1 <= self.K <= 16
+        self.zband = None if zband is None else np.asarray(zband, dtype=np.float64)
+        self.res = [int(r) for r in res]
+        self.Lv, self.F, self.log2T = len(self.res), int(n_features), int(log2_table)
+        self.S = int(samples)
+        self.early_stop = float(early_stop)
+        bf = precision == "bf16"
+        self.precision = precision
+        self.feat_dtype = L.SNAKE_BF16 if bf else L.SNAKE_F32
+        self.grid = L.grid_desc(self.res, self.F, self.log2T, self.feat_dtype)
+        self.mlp = L.mlp_desc(self.Lv, self.F, n_dir, colour_layers, colour_out,
+                              L.SNAKE_BF16 if bf else L.SNAKE_F32, self.feat_dtype)
+        self.n_dir = int(n_dir)
+        self.P = L.snake_mlp_param_count(self.mlp)
+        dev = self.device
+        tshape = (self.K, self.Lv, 1 << self.log2T, self.F)
+        self.table = (torch.zeros(tshape, device=dev) if tables is None else
+                      torch.as_tensor(np.ascontiguousarray(tables, dtype=np.float32)).to(dev).reshape(tshape))
+        self.params = (torch.zeros((self.K, self.P), device=dev) if mlp_params is None else
+                       torch.as_tensor(np.ascontiguousarray(mlp_params, dtype=np.float32)).to(dev)
+                       .reshape(self.K, self.P))
+        self.m_t, self.v_t, self.g_t = (torch.zeros_like(self.table) for _ in range(3))
+        self.m_w, self.v_w, self.g_w = (torch.zeros_like(self.params) for _ in range(3))
+        self.lr, (self.b1, self.b2), self.eps = float(lr), betas, float(eps)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.hash_ws_gib = float(hash_ws_gib)
+        self.graph = None
+        self._alloc(int(max_rays), int(max_samples) if max_samples else int(max_rays) * self.S)
+
+    # -- buffers -----------------------------------------------------------
+    def _alloc(self, R, cap):
+        dev, i32, f32, i64 = self.device, torch.int32, torch.float32, torch.int64
+        self.R, self.cap = R, cap
+        self.packed_info = torch.zeros((R, 2), dtype=i32, device=dev)
+        self.t0 = torch.empty(cap, dtype=f32, device=dev)
+        self.t1 = torch.empty(cap, dtype=f32, device=dev)
+        self.pos = torch.empty((cap, 3), dtype=f32, device=dev)
+        self.ray_id = torch.empty(cap, dtype=i32, device=dev)
+        self.tile_id = torch.empty(cap, dtype=torch.uint8, device=dev)
+        self.view = torch.empty((R, 3), dtype=f32, device=dev)
+        self.n_out = torch.zeros(1, dtype=i64, device=dev)
+        # tile-partitioned copies
+        self.perm = torch.empty(cap, dtype=i32, device=dev)
+        self.inv = torch.empty(cap, dtype=i32, device=dev)
+        self.tile_start = torch.zeros(self.K + 2, dtype=i64, device=dev)
+        self.pos_s = torch.empty((cap, 3), dtype=f32, device=dev)
+        self.tile_s = torch.empty(cap, dtype=torch.uint8, device=dev)
+        self.ray_s = torch.empty(cap, dtype=i32, device=dev)
+        fdt = torch.bfloat16 if self.feat_dtype == L.SNAKE_BF16 else f32
+        self.feat = torch.empty((self.Lv, cap, self.F), dtype=fdt, device=dev)
+        self.sigma = torch.empty(cap, dtype=f32, device=dev)
+        self.rgb = torch.empty((cap, 3), dtype=f32, device=dev)
+        self.rgb_out = torch.empty((R, 3), dtype=f32, device=dev)
+        self.opacity = torch.empty(R, dtype=f32, device=dev)
+        self.depth = torch.empty(R, dtype=f32, device=dev)
+        self.n_alive = torch.empty(R, dtype=i32, device=dev)
+        self.loss = torch.zeros(1, dtype=f32, device=dev)
+        self.dsigma = torch.empty(cap, dtype=f32, device=dev)
+        self.drgb = torch.empty((cap, 3), dtype=f32, device=dev)
+        self.dfeat = torch.empty((self.Lv, cap, self.F), dtype=f32, device=dev)
+        self.ws_sample = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=dev)
+        self.ws_part = torch.empty(L.snake_tile_partition_workspace_bytes(self.K), dtype=torch.uint8,
+                                   device=dev)
+        self.ws_mlp = torch.empty(L.snake_mlp_bwd_workspace_bytes(self.mlp, self.K), dtype=torch.uint8,
+                                  device=dev)
+        budget = int(self.hash_ws_gib * (1 << 30))
+        lg = 1
+        for c in range(self.Lv, 0, -1):
+            nb = L.snake_hashgrid_bwd_workspace_bytes(self.grid, self.K, cap, c)
+            if cap * c * 8 <= 2**31 - 1 and 0 < nb <= budget:
+                lg = c
+                break
+        self.ws_hash = torch.empty(L.snake_hashgrid_bwd_workspace_bytes(self.grid, self.K, cap, lg),
+                                   dtype=torch.uint8, device=dev)
+
+    # -- ray acceptance ----------------------------------------------------
+    def window_rect(self):
+        b = self.boxes
+        return (b[:, 0].min(), b[:, 1].min(), b[:, 3].max(), b[:, 4].max())
+
+    def band(self):
+        if self.zband is not None:
+            return tuple(self.zband)
+        return (self.boxes[:, 2].min(), self.boxes[:, 5].max())
+
+    def accept(self, rays_o, rays_d, stream=None):
+        """Indices of the rays (device FP64 [R][3] each) this window may train on,
+        and their device count."""
+        R = int(rays_o.shape[0])
+        idx = torch.empty(max(R, 1), dtype=torch.int32, device=self.device)
+        n = torch.zeros(1, dtype=torch.int64, device=self.device)
+        ws = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=self.device)
+        L.snake_window_accept(rays_o, rays_d, R, self.window_rect(), self.band(), None, idx, n, ws,
+                              stream=stream)
+        return idx, n
+
+    # -- the step ----------------------------------------------------------
+    def step(self, rays_o, rays_d, target, samples_per_ray=None, sun=None, stream=None, update=True):
+        """One training step of the window on R rays (device tensors; R fixed
+        by the buffers given at capture time when replayed).  update=False
+        stops before Adam and leaves the gradients in g_t / g_w."""
+        R = int(rays_o.shape[0])
+        assert R <= self.R
+        cap, K = self.cap, self.K
+        self.loss.zero_()
+        scale = 1.0 / (3.0 * R)
+        L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S, None,
+                                 self.packed_info, self.t0, self.t1, self.pos, self.ray_id, self.tile_id,
+                                 self.view, cap, self.n_out, self.ws_sample, stream)
+        L.snake_tile_partition(self.tile_id, self.pos, self.ray_id, cap, self.n_out, K, self.perm, self.inv,
+                               self.tile_start, self.pos_s, self.tile_s, self.ray_s, self.ws_part, stream)
+        L.snake_hashgrid_fwd(self.grid, K, self.table, self.pos_s, self.tile_s, None, cap, self.n_out, self.feat,
+                             None, stream)
+        L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, sun, self.ray_s, R, None, cap, self.n_out,
+                        self.sigma, self.rgb, K=K, tile_start=self.tile_start, stream=stream)
+        L.snake_composite_fwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R, self.early_stop,
+                              target, scale, self.rgb_out, self.opacity, self.depth, self.n_alive, self.loss,
+                              sample_map=self.inv, stream=stream)
+        # samples past a ray's early stop get zero adjoints, so the networks and
+        # the table see them without changing any gradient
+        L.snake_composite_bwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R,
+                              self.n_alive if self.early_stop > 0 else None, target, scale, self.dsigma,
+                              self.drgb, sample_map=self.inv, stream=stream)
+        L.snake_mlp_bwd(self.mlp, self.params, self.feat, cap, self.view, sun, self.ray_s, R, None, cap,
+                        self.n_out, self.dsigma, self.drgb, self.g_w, self.dfeat, self.ws_mlp, K=K,
+                        tile_start=self.tile_start, stream=stream)
+        L.snake_hashgrid_bwd(self.grid, K, self.pos_s, self.tile_s, None, cap, self.n_out, self.dfeat, self.g_t,
+                             self.ws_hash, stream)
+        if not update:
+            return
+        L.snake_counter_add(self.step_dev, 1, stream=stream)
+        L.snake_adam_step(self.table, self.g_t, self.m_t, self.v_t, self.table.numel(), self.lr, self.b1,
+                          self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
+                          stream=stream)
+        L.snake_adam_step(self.params, self.g_w, self.m_w, self.v_w, self.params.numel(), self.lr, self.b1,
+                          self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
+                          stream=stream)
+
+    # -- HIP graph ---------------------------------------------------------
+    def capture(self, rays_o, rays_d, target, samples_per_ray=None, sun=None, warmup=1):
+        """Capture one step on these (static) input buffers into a HIP graph.
+        The warm-up steps run eagerly first (they are training steps)."""
+        self._static = (rays_o, rays_d, target, samples_per_ray, sun)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.step(*self._static)
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(*self._static)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()

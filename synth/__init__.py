@@ -15,6 +15,10 @@ Workloads (all host-side, NumPy ``default_rng(seed)``, FP64 geometry):
   Gaussian bumps, value-noise albedo, hard sun shadows), 8 training views of
   1024^2 px, altitude band z in [0.2, 0.8], hash grid L=16/F=2/T=2^19
   (16 -> 2048), MLP 32->64->16 and 21->64->64->4.
+* ``window_2x2`` -- four unit NeRF tiles [i,i+1]x[j,j+1]x[0,1] of a 2x2
+  window, each with its own table and networks (small-tile shapes), rays
+  drawn per tile from the crop of each of 8 views that holds the projected
+  tile corners plus a 10 % margin, ragged per-ray sample budgets.
 
 The satellite views are affine (orthographic): every ray of a view shares one
 direction d = (sin th cos ph, sin th sin ph, -cos th) with off-nadir angle
@@ -28,7 +32,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "GridConfig", "MlpConfig", "Workload", "tiny_tile", "full_tile",
+    "GridConfig", "MlpConfig", "Workload", "tiny_tile", "full_tile", "window_2x2",
     "init_table", "init_mlp", "mlp_param_shapes", "Heightfield",
 ]
 
@@ -271,4 +275,63 @@ def full_tile(seed: int = 0, n_rays: int = 1 << 18, samples: int = 128,
     wl.scene = scene
     wl.view_dirs = dirs
     wl.sun_dirs = suns
+    return wl
+
+
+def window_2x2(seed: int = 0, rays_per_tile=None, n_views: int = 8, image_px: int = 1024,
+               spr_range=(8, 128), max_off_nadir_deg: float = 30.0) -> Workload:
+    """2x2 window of unit tiles covering [0,2]^2 x [0,1] with the small-tile
+    hash grid and networks per tile.  Tile k = (i, j) gets rays_per_tile[k]
+    rays (default: uniform in 2^15..2^18): each picks a view, then a pixel
+    centre of that view's crop of the tile -- the bounding box of the 8 box
+    corners projected along the view direction onto the z = 0.5 image plane,
+    grown by 10 % of its size on every side (pixels of side 2/image_px over
+    [0,2]^2).  Origins sit on z = 2.  Per-ray budgets are uniform in
+    spr_range; targets are uniform RGB."""
+    rng = np.random.default_rng(seed)
+    grid = GridConfig(n_levels=8, n_features=2, log2_table=14, res_min=16, res_max=256)
+    mlp = MlpConfig(feat_width=32, feat_real=16, hidden=64, dens_out=16, n_dir=3,
+                    colour_layers=1, colour_out=3)
+    boxes = np.array([[i, j, 0.0, i + 1.0, j + 1.0, 1.0] for i in range(2) for j in range(2)])
+    K = boxes.shape[0]
+    if rays_per_tile is None:
+        rays_per_tile = rng.integers(1 << 15, (1 << 18) + 1, size=K)
+    rays_per_tile = np.asarray(rays_per_tile, dtype=np.int64)
+    dirs = _view_dirs(rng, n_views, max_off_nadir_deg)
+    px = 2.0 / image_px
+    os_, ds_ = [], []
+    for k in range(K):
+        b = boxes[k]
+        corners = np.array([[b[0 + 3 * (q & 1)], b[1 + 3 * ((q >> 1) & 1)], b[2 + 3 * ((q >> 2) & 1)]]
+                            for q in range(8)])
+        view = rng.integers(0, n_views, size=rays_per_tile[k])
+        for v in range(n_views):
+            sel = np.nonzero(view == v)[0]
+            if sel.size == 0:
+                continue
+            d = dirs[v]
+            proj = corners[:, :2] + ((0.5 - corners[:, 2]) / d[2])[:, None] * d[None, :2]
+            lo, hi = proj.min(0), proj.max(0)
+            m = 0.1 * (hi - lo)
+            lo, hi = lo - m, hi + m
+            ilo = np.floor(lo / px).astype(np.int64)
+            ihi = np.ceil(hi / px).astype(np.int64)
+            pix = np.stack([rng.integers(ilo[a], ihi[a], size=sel.size) for a in range(2)], 1)
+            g = np.concatenate([(pix + 0.5) * px, np.full((sel.size, 1), 0.5)], 1)
+            s = (2.0 - 0.5) / (-d[2])
+            o = g - s * d[None, :]
+            o[:, 2] = 2.0
+            os_.append(o)
+            ds_.append(np.repeat(d[None, :], sel.size, 0))
+    rays_o = np.concatenate(os_)
+    rays_d = np.concatenate(ds_)
+    R = rays_o.shape[0]
+    spr = rng.integers(spr_range[0], spr_range[1] + 1, size=R).astype(np.int32)
+    target = rng.uniform(0.0, 1.0, size=(R, 3)).astype(np.float32)
+    table = init_table(rng, grid, n_tiles=K)
+    params = np.stack([init_mlp(rng, mlp) for _ in range(K)])
+    wl = Workload("window_2x2", grid, mlp, boxes, None, rays_o, rays_d, None, target, spr, 0.0, table,
+                  params)
+    wl.rays_per_tile = rays_per_tile
+    wl.view_dirs = dirs
     return wl

@@ -71,7 +71,7 @@ def test_act_width(L):
 def test_workspace_queries(L):
     assert L.snake_sample_workspace_bytes(4096) >= 2 * 4096 * 4
     d = L.mlp_desc(16, 2, 6, 2, 4)
-    assert L.snake_mlp_bwd_workspace_bytes(d) >= 4 * L.snake_mlp_param_count(d)
+    assert L.snake_mlp_bwd_workspace_bytes(d, 1) >= 4 * L.snake_mlp_param_count(d)
 
 
 def _raw(L):
@@ -103,20 +103,28 @@ def test_host_side_argument_errors(L):
     assert so.snake_hashgrid_fwd(None, 1, None, None, None, None, 10, None, None, None, None) == SNAKE_ERR_NULL
     # MLP descriptor checks
     m = L.mlp_desc(8, 2, 5, 1, 3)
-    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, 1, None, 16, None, None, None,
-                            None, None) == SNAKE_ERR_INVALID_ARG
+    assert so.snake_mlp_fwd(ctypes.byref(m), 1, None, None, None, None, None, None, 1, None, 16, None, None,
+                            None, None, None) == SNAKE_ERR_INVALID_ARG
     m = L.mlp_desc(8, 2, 3, 3, 3)
-    assert so.snake_mlp_fwd(ctypes.byref(m), None, None, None, None, None, 1, None, 16, None, None, None,
-                            None, None) == SNAKE_ERR_UNSUPPORTED
+    assert so.snake_mlp_fwd(ctypes.byref(m), 1, None, None, None, None, None, None, 1, None, 16, None, None,
+                            None, None, None) == SNAKE_ERR_UNSUPPORTED
+    # per-tile weights need the group table, and at most 16 tiles
+    m = L.mlp_desc(8, 2, 3, 1, 3)
+    assert so.snake_mlp_fwd(ctypes.byref(m), 4, None, None, None, None, None, None, 1, None, 16, None, None,
+                            None, None, None) == SNAKE_ERR_NULL
+    assert so.snake_mlp_fwd(ctypes.byref(m), 17, None, None, None, None, None, None, 1, None, 16, None, None,
+                            None, None, None) == SNAKE_ERR_INVALID_ARG
+    assert L.snake_mlp_bwd_workspace_bytes(m, 4) == 4 * L.snake_mlp_bwd_workspace_bytes(m, 1)
+    assert L.snake_mlp_bwd_workspace_bytes(m, 0) == 0
     m = L.mlp_desc(17, 2, 3, 1, 3)
     assert so.snake_mlp_param_count(ctypes.byref(m)) == -1
     m = L.mlp_desc(8, 2, 6, 2, 4)
-    assert so.snake_mlp_bwd(ctypes.byref(m), None, None, 0, None, None, None, 1, None, 16, None, None,
+    assert so.snake_mlp_bwd(ctypes.byref(m), 1, None, None, None, 0, None, None, None, 1, None, 16, None, None,
                             None, None, None, None, None, 0, None) == SNAKE_ERR_INVALID_ARG
     # stored activations must be 16-byte aligned
     fake = ctypes.c_void_p(256)
-    assert so.snake_mlp_fwd(ctypes.byref(m), fake, fake, fake, fake, fake, 1, None, 16, None, fake, fake,
-                            ctypes.c_void_p(260), None) == -3
+    assert so.snake_mlp_fwd(ctypes.byref(m), 1, fake, None, fake, fake, fake, fake, 1, None, 16, None, fake,
+                            fake, ctypes.c_void_p(260), None) == -3
     # sampler checks (boxes are host memory)
     boxes = np.array([[0, 0, 0, 1, 1, 1]], np.float64)
     assert so.snake_sample_segmented(None, None, 4, boxes.ctypes.data, 0, None, None, 8, None, None,
@@ -136,22 +144,22 @@ def test_host_side_argument_errors(L):
                                      fake, fake, fake, fake, None, None, 32, fake, ws, 16,
                                      None) == -6
     # composite / adam checks
-    assert so.snake_composite_fwd(None, None, None, None, None, 4, ctypes.c_float(1.5), None,
+    assert so.snake_composite_fwd(None, None, None, None, None, 4, None, ctypes.c_float(1.5), None,
                                   ctypes.c_float(0), None, None, None, None, None,
                                   None) == SNAKE_ERR_INVALID_ARG
     assert so.snake_adam_step(None, None, None, None, 4, ctypes.c_float(1e-2), ctypes.c_float(0.9),
-                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 0, ctypes.c_float(0), 0,
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 0, None, ctypes.c_float(0), 0,
                               None) == SNAKE_ERR_INVALID_ARG
     assert so.snake_adam_step(None, None, None, None, 4, ctypes.c_float(1e-2), ctypes.c_float(0.9),
-                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, ctypes.c_float(0), 0,
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, None, ctypes.c_float(0), 0,
                               None) == SNAKE_ERR_NULL
     al = ctypes.c_void_p(4)
     assert so.snake_adam_step(al, al, al, al, 4, ctypes.c_float(1e-2), ctypes.c_float(0.9),
-                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, ctypes.c_float(0), 0,
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, None, ctypes.c_float(0), 0,
                               None) == -3
     # n == 0 is a no-op
     assert so.snake_adam_step(None, None, None, None, 0, ctypes.c_float(1e-2), ctypes.c_float(0.9),
-                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, ctypes.c_float(0), 0,
+                              ctypes.c_float(0.99), ctypes.c_float(1e-15), 1, None, ctypes.c_float(0), 0,
                               None) == 0
 
 

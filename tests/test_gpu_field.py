@@ -290,3 +290,69 @@ def test_bad_tile_and_ray_ids_are_dropped_and_flagged(L, orc):
     sync()
     assert np.all(host(sig)[::9] == 0) and np.all(host(rgb)[::9] == 0) and np.all(host(sig)[1::9] > 0)
     assert L.snake_check_device_error() & L.SNAKE_DEVERR_RAY_ID
+
+
+@pytest.mark.parametrize("name", list(MLPS))
+def test_mlp_per_tile_weights(L, orc, name):
+    """Window form: K = 4 weight sets selected by each sample's tile after the
+    tile partition, with uneven group sizes (one empty), 16-sample tiles that
+    would straddle groups, and a few invalid tile ids (dropped: sigma = rgb = 0,
+    dfeat = 0).  Each group matches the oracle run on its own samples with its
+    own weights; dW is [K][P]."""
+    rng = np.random.default_rng(77)
+    cfg, Lv, F = MLPS[name]
+    K, n, R = 4, 6007, 900
+    P = orc.mlp_param_count(cfg)
+    ws_ = [synth.init_mlp(rng, cfg) * np.float32(2.0) for _ in range(K)]
+    W = np.stack(ws_)
+    _, feat, view, sun, rid = _mlp_inputs(rng, cfg, Lv, F, n, R)
+    tid = rng.choice([0, 1, 3], size=n, p=[0.6, 0.3, 0.1]).astype(np.uint8)   # group 2 empty
+    tid[::611] = 9
+    sun_d = dev(sun) if cfg.n_dir == 6 else None
+    # partition on the GPU, then run the networks in the partitioned order
+    perm = torch.empty(n, dtype=torch.int32, device=DEV)
+    ts = torch.empty(K + 2, dtype=torch.int64, device=DEV)
+    rs = torch.empty(n, dtype=torch.int32, device=DEV)
+    pws = torch.empty(L.snake_tile_partition_workspace_bytes(K), dtype=torch.uint8, device=DEV)
+    L.snake_check_device_error()
+    L.snake_tile_partition(dev(tid), None, dev(rid), n, None, K, perm, None, ts, None, None, rs, pws)
+    sync()
+    assert L.snake_check_device_error() & L.SNAKE_DEVERR_TILE_ID
+    pm = host(perm)
+    bounds = host(ts)
+    fs = feat[pm]
+    m = L.mlp_desc(Lv, F, cfg.n_dir, cfg.colour_layers, cfg.colour_out)
+    fd = dev(fs.reshape(n, Lv, F).transpose(1, 0, 2))
+    sig = torch.full((n,), 7.0, device=DEV)
+    rgb = torch.full((n, 3), 7.0, device=DEV)
+    L.snake_mlp_fwd(m, dev(W.reshape(-1)), fd, dev(view), sun_d, rs, R, None, n, None, sig, rgb, K=K,
+                    tile_start=ts)
+    ds = rng.normal(size=n).astype(np.float32)
+    dr = rng.normal(size=(n, 3)).astype(np.float32)
+    dW = torch.zeros(K * P, device=DEV)
+    dfeat = torch.full((Lv, n, F), 7.0, device=DEV)
+    wsb = torch.empty(L.snake_mlp_bwd_workspace_bytes(m, K), dtype=torch.uint8, device=DEV)
+    L.snake_mlp_bwd(m, dev(W.reshape(-1)), fd, n, dev(view), sun_d, rs, R, None, n, None, dev(ds), dev(dr),
+                    dW, dfeat, wsb, K=K, tile_start=ts)
+    sync()
+    g_sig, g_rgb = host(sig), host(rgb)
+    g_dw = host(dW).reshape(K, P)
+    g_df = host(dfeat).transpose(1, 0, 2).reshape(n, -1)
+    for k in range(K + 1):
+        sl = slice(bounds[k], bounds[k + 1])
+        if k == K:
+            assert np.all(g_sig[sl] == 0) and np.all(g_rgb[sl] == 0) and np.all(g_df[sl] == 0)
+            assert bounds[k + 1] - bounds[k] == len(range(0, n, 611))
+            continue
+        if bounds[k + 1] == bounds[k]:
+            assert np.all(g_dw[k] == 0)
+            continue
+        r_sig, r_rgb = orc.mlp_fwd(cfg, W[k], _pad32(fs[sl]), view, host(rs)[sl],
+                                   sun=sun if cfg.n_dir == 6 else None)
+        assert_values(g_sig[sl], r_sig, rel=1e-5, abs_=1e-7, what="sigma tile %d" % k)
+        assert_values(g_rgb[sl], r_rgb, rel=1e-5, abs_=1e-7, what="rgb tile %d" % k)
+        rW, rf = orc.mlp_bwd(cfg, W[k], _pad32(fs[sl]), view, host(rs)[sl], ds[sl], dr[sl],
+                             sun=sun if cfg.n_dir == 6 else None)
+        assert_grad(g_dw[k], rW, 1e-4, "dW tile %d" % k)
+        assert_grad(g_df[sl], rf[:, :Lv * F], 1e-4, "dfeat tile %d" % k)
+    assert bounds[3] == bounds[2]

@@ -115,3 +115,44 @@ def test_adam_matches_oracle(L, orc):
         # relative to the terms (|g| ~ 1, g^2 ~ 1), not to the result
         assert_values(host(M), mr, 1e-5, 1e-6, "m")
         assert_values(host(V), vr, 1e-5, 1e-6, "v")
+    # the step read on the device (graph replays): same bits as the host step
+    P2, M2, V2 = dev(p), torch.zeros(n, device=DEV), torch.zeros(n, device=DEV)
+    P3, M3, V3 = dev(p), torch.zeros(n, device=DEV), torch.zeros(n, device=DEV)
+    step_dev = torch.zeros(1, dtype=torch.int32, device=DEV)
+    for step in range(1, 6):
+        g = rng.normal(size=n).astype(np.float32)
+        L.snake_counter_add(step_dev, 1)
+        L.snake_adam_step(P2, dev(g), M2, V2, n, 1e-2, 0.9, 0.99, 1e-15, 0, 1e-3, 0, step_dev=step_dev)
+        L.snake_adam_step(P3, dev(g), M3, V3, n, 1e-2, 0.9, 0.99, 1e-15, step, 1e-3, 0)
+    sync()
+    assert int(step_dev.item()) == 5
+    assert torch.equal(P2, P3) and torch.equal(M2, M3) and torch.equal(V2, V3)
+
+
+def test_composite_sample_map(L):
+    """With a sample map the per-sample values live in another order: the
+    result equals the identity-order call on the permuted arrays, bit for bit,
+    and the adjoints land at the mapped positions."""
+    rng = np.random.default_rng(23)
+    counts = rng.integers(0, 150, size=2000)
+    info, t0, t1, sigma, rgb, tgt = _rays(rng, counts, sigma_scale=30.0)
+    n, R = sigma.size, info.shape[0]
+    inv = rng.permutation(n).astype(np.int32)            # packed p -> stored at inv[p]
+    s_perm = np.empty_like(sigma)
+    s_perm[inv] = sigma
+    c_perm = np.empty_like(rgb)
+    c_perm[inv] = rgb
+    ref = _gpu_composite(L, info, t0, t1, sigma, rgb, tgt, 1e-4, 1.0 / (3 * R))
+    o = dict(rgb_out=torch.zeros((R, 3), device=DEV), n_alive=torch.zeros(R, dtype=torch.int32, device=DEV),
+             loss=torch.zeros(1, device=DEV))
+    args = [dev(s_perm), dev(c_perm), dev(t0), dev(t1), dev(info, torch.int32)]
+    L.snake_composite_fwd(*args, R, 1e-4, dev(tgt), 1.0 / (3 * R), o["rgb_out"], None, None, o["n_alive"],
+                          o["loss"], sample_map=dev(inv))
+    ds = torch.full((n,), 9.0, device=DEV)
+    dr = torch.full((n, 3), 9.0, device=DEV)
+    L.snake_composite_bwd(*args, R, o["n_alive"], dev(tgt), 1.0 / (3 * R), ds, dr, sample_map=dev(inv))
+    sync()
+    assert np.array_equal(host(o["rgb_out"]), ref["rgb_out"])
+    assert np.array_equal(host(o["n_alive"]), ref["n_alive"])
+    assert np.array_equal(host(ds)[inv], ref["dsigma"])
+    assert np.array_equal(host(dr)[inv], ref["drgb"])

@@ -151,3 +151,42 @@ def test_window_accept_bitexact(L, orc):
     L.snake_window_accept(dev(o), dev(d), 0, win, zb, None, idx2, n, ws)
     sync()
     assert int(n.item()) == 0
+
+
+@pytest.mark.parametrize("K", [1, 4, 16])
+def test_tile_partition_is_stable_sort(L, K):
+    """perm is the stable sort of the samples by tile id (bad ids last), inv its
+    inverse, tile_start the group bounds; the gathered copies follow perm;
+    a device count shorter than n limits every output."""
+    rng = np.random.default_rng(40 + K)
+    n = 300_001
+    tid = rng.integers(0, K, size=n).astype(np.uint8)
+    tid[rng.random(n) < 0.3] = min(K - 1, 2)             # uneven group sizes
+    if K > 1:
+        tid[::997] = K + 3                                 # out-of-range ids go last
+    pos = rng.random((n, 3)).astype(np.float32)
+    rid = rng.integers(0, 1 << 20, size=n).astype(np.int32)
+    ws = torch.empty(L.snake_tile_partition_workspace_bytes(K), dtype=torch.uint8, device=DEV)
+    for ne in (n, 123_457):
+        perm = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        inv = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        ts = torch.zeros(K + 2, dtype=torch.int64, device=DEV)
+        po = torch.zeros((n, 3), device=DEV)
+        to = torch.zeros(n, dtype=torch.uint8, device=DEV)
+        ro = torch.zeros(n, dtype=torch.int32, device=DEV)
+        nd = torch.tensor([ne], dtype=torch.int64, device=DEV)
+        L.snake_check_device_error()                     # clear the sticky error word
+        L.snake_tile_partition(dev(tid), dev(pos), dev(rid), n, nd, K, perm, inv, ts, po, to, ro, ws)
+        sync()
+        key = np.minimum(tid[:ne].astype(np.int64), K)
+        ref = np.argsort(key, kind="stable").astype(np.int32)
+        assert np.array_equal(host(perm)[:ne], ref)
+        assert np.all(host(perm)[ne:] == -1)
+        assert np.array_equal(host(inv)[ref], np.arange(ne, dtype=np.int32))
+        bounds = np.searchsorted(key[ref], np.arange(K + 1))
+        assert np.array_equal(host(ts), np.concatenate([bounds, [ne]]))
+        assert np.array_equal(host(po)[:ne], pos[ref])
+        assert np.array_equal(host(to)[:ne], tid[ref])
+        assert np.array_equal(host(ro)[:ne], rid[ref])
+        err = L.snake_check_device_error()
+        assert bool(err & L.SNAKE_DEVERR_TILE_ID) == (K > 1)

@@ -716,3 +716,30 @@ def test_bf16_emulation_matches_torch_rounding(orc, which):
     s_e, c_e = orc.mlp_fwd_bf16emu(m, w, feat, view, rid, sun=sun if m.n_dir == 6 else None)
     np.testing.assert_allclose(s_e, np.exp(out[:, 0]), rtol=1e-12)
     np.testing.assert_allclose(c_e, rgb, rtol=1e-12, atol=1e-15)
+
+
+def test_train_step_per_tile_weights_reduce_to_shared(orc):
+    """Window step on 2x2 tiles with one weight set per tile: when the four
+    sets are equal, the forward, the loss and the table gradient are those of
+    the shared-weight step, and the per-tile weight gradients sum to the shared
+    one (each sample's adjoint goes to exactly its own tile's set)."""
+    import copy
+    wl = synth.tiny_tile(seed=5, n_rays=300, samples=24)
+    wl = copy.copy(wl)
+    wl.boxes = np.array([[0, 0, 0, 0.5, 0.5, 1], [0, 0.5, 0, 0.5, 1, 1], [0.5, 0, 0, 1, 0.5, 1],
+                         [0.5, 0.5, 0, 1, 1, 1]], dtype=np.float64)
+    rng = np.random.default_rng(3)
+    wl.table = synth.init_table(rng, wl.grid, n_tiles=4) * np.float32(1e4)
+    wl.samples_per_ray = rng.integers(8, 40, size=300).astype(np.int32)
+    shared = orc.train_step(wl)
+    W = np.stack([wl.mlp_params] * 4)
+    tiled = orc.train_step(wl, mlp_params=W)
+    assert len(np.unique(shared["sample"]["tile_id"])) == 4
+    assert np.array_equal(tiled["sigma"], shared["sigma"])
+    assert tiled["loss"] == shared["loss"]
+    assert np.allclose(tiled["dtable"], shared["dtable"], rtol=0, atol=1e-15)
+    dWk = tiled["dW"].reshape(4, -1)
+    assert np.allclose(dWk.sum(0), shared["dW"], rtol=1e-12, atol=1e-18)
+    # every tile holds samples, so every set receives a gradient of its own
+    assert np.all(np.abs(dWk).sum(1) > 0)
+    assert tiled["mlp_new"].shape == (4, W.shape[1])
