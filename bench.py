@@ -210,6 +210,81 @@ def recompute_check(args):
     return out
 
 
+def window_bench(args):
+    """2x2 window of small-tile NeRFs with separate tables and networks
+    (L=8, F=2, T=2^14, MLP 32-64-16 / 18-64-3 per tile; BF16 networks):
+    per-tile ray counts uniform in 2^15..2^18 from 10 %-margin crops of 8
+    views, per-ray budgets uniform in 8..128, rays filtered by the window's
+    acceptance.  The whole window step captured in one HIP graph (launch
+    shapes autotuned first) against the same rays trained as four separate
+    single-tile steps (each tile's own crop rays, its own box only)."""
+    import torch
+    import synth
+    from paper_2507_01631_amd import TileNeRF, WindowNeRF, autotune, level_resolutions
+    from paper_2507_01631_amd import _lib as L
+    dev = "cuda:0"
+    w = synth.window_2x2(seed=0)
+    g, m = w.grid, w.mlp
+    res = level_resolutions(g.n_levels, g.res_min, g.res_max)
+    ro_all, rd_all = torch.as_tensor(w.rays_o).to(dev), torch.as_tensor(w.rays_d).to(dev)
+    mk = dict(res=res, n_features=g.n_features, log2_table=g.log2_table, n_dir=m.n_dir,
+              colour_layers=m.colour_layers, colour_out=m.colour_out, lr=w.lr, device=dev)
+    probe = WindowNeRF(boxes=w.boxes, zband=None, precision="bf16", max_rays=16, **mk)
+    idx, n_acc = probe.accept(ro_all, rd_all)
+    na = int(n_acc.item())
+    idx = idx[:na].long()
+    del probe
+    ro, rd = ro_all[idx].contiguous(), rd_all[idx].contiguous()
+    tg = torch.as_tensor(w.target).to(dev)[idx].contiguous()
+    spr = torch.as_tensor(w.samples_per_ray).to(dev)[idx].contiguous()
+    cap = int(spr.sum().item())
+    nerf = WindowNeRF(boxes=w.boxes, zband=None, precision="bf16", tables=w.table, mlp_params=w.mlp_params,
+                      max_rays=na, max_samples=cap, **mk)
+    step = lambda: nerf.step(ro, rd, tg, spr)             # noqa: E731
+    default = autotune.current()
+    ms_default = autotune.time_step(step, reps=5, warmup=2)
+    table, ms_tuned, _ = autotune.tune(step, reps=5, warmup=1, log=log)
+    ms_eager = autotune.time_step(step, reps=5, warmup=1)
+    nerf.capture(ro, rd, tg, spr, warmup=1)
+    ms_graph = autotune.time_step(nerf.replay, reps=10, warmup=2)
+    n_samples = int(nerf.n_out.item())
+    # the same rays as four separate single-tile steps (each tile's crop rays)
+    starts = np.concatenate([[0], np.cumsum(w.rays_per_tile)])
+    sep_ms, sep_samples = 0.0, 0
+    for k in range(4):
+        sl = slice(int(starts[k]), int(starts[k + 1]))
+        o_k, d_k = ro_all[sl].contiguous(), rd_all[sl].contiguous()
+        t_k = torch.as_tensor(w.target[sl]).to(dev)
+        s_k = torch.as_tensor(w.samples_per_ray[sl]).to(dev)
+        t = TileNeRF(boxes=w.boxes[k:k + 1], samples=128, precision="bf16", table=w.table[k:k + 1],
+                     mlp_params=w.mlp_params[k], max_rays=o_k.shape[0], **mk)
+
+        def one():
+            R = o_k.shape[0]
+            t.alloc(R)
+            t.loss.zero_()
+            sc = 1.0 / (3.0 * R)
+            t.sample(o_k, d_k, R, samples_per_ray=s_k)
+            t.field_fwd(None)
+            t.render(R, t_k, sc)
+            t.field_bwd(R, t_k, sc, None)
+            t.adam()
+        sep_ms += autotune.time_step(one, reps=5, warmup=1)
+        sep_samples += int(t.n_out.item())
+        del t
+    autotune.apply(default)
+    out = {"config": "4 tiles [0,2]^2 x [0,1], L=8 F=2 T=2^14, MLP 32-64-16 / 18-64-3 per tile, bf16; "
+                     "rays per tile %s, per-ray budgets 8..128" % list(map(int, w.rays_per_tile)),
+           "rays_accepted": na, "rays_total": int(w.n_rays), "samples": n_samples,
+           "ms_default_shapes": round(ms_default, 4), "ms_tuned_eager": round(ms_eager, 4),
+           "ms_graph": round(ms_graph, 4), "samples_per_s_graph": n_samples / (ms_graph * 1e-3),
+           "separate": {"ms": round(sep_ms, 4), "samples": sep_samples,
+                        "samples_per_s": sep_samples / (sep_ms * 1e-3)},
+           "tuned_shapes": table}
+    log("  window: %s" % json.dumps(out))
+    return out
+
+
 def cpu_baseline(args):
     import oracle
     import synth
@@ -237,6 +312,7 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=1 << 17)
     ap.add_argument("--recompute-rays", type=int, default=1 << 16)
     ap.add_argument("--no-recompute-check", action="store_true")
+    ap.add_argument("--no-window", action="store_true", help="skip the 2x2 window (graph vs separate) run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 256 MiB device copies (byte-counter calibration)")
     args = ap.parse_args()
@@ -296,6 +372,8 @@ def main():
         line["%s_form" % p] = {"value": g["value"], "ms_per_step": g["ms_per_step"],
                                "samples_alive_per_step": g["samples_alive"],
                                "stages_ms": {k: round(v, 4) for k, v in g["stage_ms"].items()}}
+    if not args.no_window:
+        line["window"] = window_bench(args)
     if not args.no_recompute_check:
         line["recompute"] = recompute_check(args)
     if not args.no_cpu_baseline:

@@ -87,6 +87,32 @@ const char *snake_last_error(void);
  * in *bits (may be NULL). */
 int snake_check_device_error(snake_stream_t stream, uint32_t *bits);
 
+/*
+ * Launch-shape tunables.  The process-wide table below is the library's only
+ * global state; an autotuner times the calls it affects and sets it before a
+ * step is captured (a captured graph keeps the shapes it was captured with).
+ * Every value only changes how work is split across the chip, never a
+ * result, except where noted.  snake_tune_set returns SNAKE_ERR_INVALID_ARG
+ * for an unknown id or a value outside the stated range; 0 restores the
+ * default where a default is listed as 0.
+ */
+typedef enum {
+    SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU = 0,  /* hash-grid forward grid, 1..64 (16) */
+    SNAKE_TUNE_MLP_FWD_BLOCKS_PER_CU = 1,   /* network forward grid, 1..16 (4) */
+    SNAKE_TUNE_MLP_BWD_BLOCKS_PER_CU = 2,   /* network adjoint grid, 0..2 (0: 2 for BF16,
+                                               1 for FP32); changes the dW summation order */
+    SNAKE_TUNE_COMPOSITE_BLOCKS_PER_CU = 3, /* rendering grid, 1..64 (8) */
+    SNAKE_TUNE_BIN_BLOCKS = 4,              /* binned table adjoint: count/scatter blocks,
+                                               64..1024 (1024) */
+    SNAKE_TUNE_BIN_LEVELS_PER_PASS = 5,     /* binned table adjoint: most levels per pass,
+                                               0..32 (0: as many as the workspace holds) */
+    SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU = 6,   /* sampler fill grid, 1..64 (16) */
+    SNAKE_TUNE_COUNT = 7
+} snake_tunable;
+
+int snake_tune_set(int32_t which, int32_t value);
+int32_t snake_tune_get(int32_t which);   /* -1 for an unknown id */
+
 /* ------------------------------------------------------------------------ */
 /* Segmented sampler (Sec. 4.5 with the distribution kernel of Sec. 4.6 and  */
 /* the UTM-to-local mapping of Sec. 4.1-4.2)                                 */
@@ -240,6 +266,9 @@ typedef struct {
     int32_t colour_out;      /* 3: rgb = sigmoid(o); 4: rgb = sigmoid(o_0..2) sigmoid(o_3) */
     int32_t precision;       /* SNAKE_F32 or SNAKE_BF16 (MFMA with FP32 accumulation) */
     int32_t feat_dtype;      /* snake_dtype of the feature array */
+    int32_t shared_colour;   /* 0: each NeRF tile has its own colour net; 1: one colour
+                                net shared by the tiles of a call (Sec. 4.1: local
+                                density networks, a global colour network) */
 } snake_mlp_desc;
 
 /* Fixed widths: density 32 -> 64 -> 16 (ReLU hidden, sigma = exp(o_0),
@@ -249,11 +278,18 @@ typedef struct {
  * [colour_out][64]. */
 int64_t snake_mlp_param_count(const snake_mlp_desc *m);
 
-/* Per-tile networks (the window step, Sec. 4.4): with K > 1, weights is
- * [K][P] and tile_start [K+2] (device int64, as written by
+/* Floats of the weight (and weight-gradient) array for K tiles: K * P, or
+ * with shared_colour the K density sets [K][Pd] (Pd = 64*32 + 16*64) followed
+ * by one colour set [P - Pd].  -1 for a bad descriptor or K. */
+int64_t snake_mlp_weight_count(const snake_mlp_desc *m, int32_t K);
+
+/* Per-tile networks (the window step, Sec. 4.4): with K > 1, weights holds
+ * snake_mlp_weight_count(m, K) floats (per-tile sets [K][P], or per-tile
+ * density sets and one shared colour set) and tile_start [K+2] (device int64, as written by
  * snake_tile_partition) splits the call's entries j into groups; group k < K
  * uses weight set k, entries of group K are dropped (sigma = rgb = 0, dfeat =
- * 0), and dW is [K][P].  K == 1 takes tile_start = NULL (one group [0, n)).
+ * 0), and dW has the layout of weights (a shared colour net's gradient sums
+ * over all tiles).  K == 1 takes tile_start = NULL (one group [0, n)).
  * The groups are processed in 64-entry units that never mix two weight sets.
  * 1 <= K <= 16.
  *

@@ -312,11 +312,21 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
                                samples_per_ray=np.asarray(spr, dtype=np.int32))
     out["sample"] = smp
     feat = hashgrid_fwd(res, g.log2_table, table, smp["pos"], smp["tile_id"], g.out_width)
-    # one weight set ([P]) shared by the tiles, or one per tile ([K][P]): each
-    # sample then goes through the networks of the tile it lies in
-    per_tile = np.ndim(mlp_params) == 2
-    groups = ([(np.ones(smp["n"], dtype=bool), mlp_params)] if not per_tile else
-              [(smp["tile_id"] == k, mlp_params[k]) for k in range(mlp_params.shape[0])])
+    # one weight set ([P]) shared by the tiles, one per tile ([K][P]), or
+    # per-tile density nets with one shared colour net ({"density": [K][Pd],
+    # "colour": [P-Pd]}): each sample goes through the networks of its tile
+    shared_colour = isinstance(mlp_params, dict)
+    if shared_colour:
+        dens, col = mlp_params["density"], mlp_params["colour"]
+        Pd = dens.shape[1]
+        full = np.concatenate([dens, np.broadcast_to(col, (dens.shape[0], col.size))], axis=1)
+        mlp_flat = np.concatenate([dens.ravel(), col])
+    else:
+        full = mlp_params
+        mlp_flat = np.ravel(mlp_params)
+    per_tile = np.ndim(full) == 2
+    groups = ([(np.ones(smp["n"], dtype=bool), full)] if not per_tile else
+              [(smp["tile_id"] == k, full[k]) for k in range(full.shape[0])])
     sigma, rgb = np.zeros(smp["n"]), np.zeros((smp["n"], 3))
     for sel, w in groups:
         if sel.any():
@@ -327,7 +337,7 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
     n_alive = comp["n_alive"] if alive is None else np.asarray(alive, dtype=np.int32)
     dsigma, drgb = composite_bwd(smp["packed_info"], sigma, rgb, smp["t0"], smp["t1"],
                                  target, loss_scale, n_alive=n_alive)
-    dW = np.zeros(mlp_params.shape)
+    dW = np.zeros(np.shape(full))
     dfeat = np.zeros((smp["n"], feat.shape[1]))
     for k, (sel, w) in enumerate(groups):
         if sel.any():
@@ -337,18 +347,21 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
                 dW[k] += dWk
             else:
                 dW += dWk
+    if shared_colour:           # the shared colour net collects every tile's gradient
+        dW = np.concatenate([dW[:, :Pd].ravel(), dW[:, Pd:].sum(axis=0)])
     dW = dW.ravel()
     dtable = hashgrid_bwd(res, g.log2_table, table.shape, smp["pos"], dfeat, smp["tile_id"])
     if adam_state is None:
         adam_state = dict(m_t=np.zeros(table.size), v_t=np.zeros(table.size),
-                          m_w=np.zeros(mlp_params.size), v_w=np.zeros(mlp_params.size))
+                          m_w=np.zeros(mlp_flat.size), v_w=np.zeros(mlp_flat.size))
     p_t = table.astype(np.float64).ravel().copy()
-    p_w = mlp_params.astype(np.float64).ravel().copy()
+    p_w = mlp_flat.astype(np.float64).copy()
     adam_step(p_t, dtable.ravel(), adam_state["m_t"], adam_state["v_t"], wl.lr, step)
     adam_step(p_w, dW, adam_state["m_w"], adam_state["v_w"], wl.lr, step)
     out.update(res=res, feat=feat, sigma=sigma, rgb=rgb, comp=comp, n_alive=n_alive,
                dsigma=dsigma, drgb=drgb, dW=dW, dfeat=dfeat, dtable=dtable,
-               table_new=p_t.reshape(table.shape), mlp_new=p_w.reshape(mlp_params.shape), adam=adam_state,
+               table_new=p_t.reshape(table.shape), mlp_new=p_w if shared_colour else p_w.reshape(np.shape(full)),
+               adam=adam_state,
                loss=comp["loss"], n_samples=int(n_alive.sum()), n_total=smp["n"])
     if timings is not None:
         timings.append(time.perf_counter() - t_start)

@@ -23,13 +23,17 @@ SNAKE_DEVERR_TILE_ID = 2
 SNAKE_DEVERR_RAY_ID = 4
 SNAKE_DEVERR_INTERNAL = 8
 MAX_LEVELS = 32
+TUNABLES = {
+    "hash_fwd_blocks_per_cu": 0, "mlp_fwd_blocks_per_cu": 1, "mlp_bwd_blocks_per_cu": 2,
+    "composite_blocks_per_cu": 3, "bin_blocks": 4, "bin_levels_per_pass": 5, "sampler_blocks_per_cu": 6,
+}
 
 EXPORTS = (
-    "snake_abi_version", "snake_last_error", "snake_check_device_error",
+    "snake_abi_version", "snake_last_error", "snake_check_device_error", "snake_tune_set", "snake_tune_get",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_pack_alive",
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
     "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
-    "snake_mlp_param_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
+    "snake_mlp_param_count", "snake_mlp_weight_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
     "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step", "snake_counter_add",
 )
@@ -51,7 +55,7 @@ class MlpDesc(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("n_features", ctypes.c_int32),
                 ("n_dir", ctypes.c_int32), ("colour_layers", ctypes.c_int32),
                 ("colour_out", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("feat_dtype", ctypes.c_int32)]
+                ("feat_dtype", ctypes.c_int32), ("shared_colour", ctypes.c_int32)]
 
 
 def grid_desc(resolution, n_features, log2_table, feat_dtype=SNAKE_F32, flags=0) -> GridDesc:
@@ -68,14 +72,16 @@ def grid_desc(resolution, n_features, log2_table, feat_dtype=SNAKE_F32, flags=0)
 
 
 def mlp_desc(n_levels, n_features, n_dir, colour_layers, colour_out, precision=SNAKE_F32,
-             feat_dtype=SNAKE_F32) -> MlpDesc:
+             feat_dtype=SNAKE_F32, shared_colour=0) -> MlpDesc:
     return MlpDesc(int(n_levels), int(n_features), int(n_dir), int(colour_layers),
-                   int(colour_out), int(precision), int(feat_dtype))
+                   int(colour_out), int(precision), int(feat_dtype), int(shared_colour))
 
 
 _P, _I32, _I64, _U32, _F, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_uint32, ctypes.c_float, ctypes.c_size_t)
 _SIGS = {
+    "snake_tune_set": ([_I32, _I32], ctypes.c_int),
+    "snake_tune_get": ([_I32], _I32),
     "snake_abi_version": ([], ctypes.c_int),
     "snake_last_error": ([], ctypes.c_char_p),
     "snake_check_device_error": ([_P, _P], ctypes.c_int),
@@ -90,6 +96,7 @@ _SIGS = {
     "snake_hashgrid_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_hashgrid_bwd_workspace_bytes": ([_P, _I32, _I64, _I32], _SZ),
     "snake_mlp_param_count": ([_P], _I64),
+    "snake_mlp_weight_count": ([_P, _I32], _I64),
     "snake_mlp_bwd_workspace_bytes": ([_P, _I32], _SZ),
     "snake_mlp_act_width": ([_P], _I32),
     "snake_mlp_fwd": ([_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -152,6 +159,16 @@ def snake_abi_version() -> int:
 
 def snake_last_error() -> str:
     return lib().snake_last_error().decode()
+
+
+def snake_tune_set(which, value):
+    which = TUNABLES[which] if isinstance(which, str) else int(which)
+    _check("snake_tune_set", lib().snake_tune_set(which, int(value)))
+
+
+def snake_tune_get(which) -> int:
+    which = TUNABLES[which] if isinstance(which, str) else int(which)
+    return int(lib().snake_tune_get(which))
 
 
 def snake_check_device_error(stream=None) -> int:
@@ -233,6 +250,10 @@ def snake_hashgrid_bwd(g: GridDesc, K, pos, tile_id, sample_idx, n, n_dev, dfeat
 
 def snake_mlp_param_count(m: MlpDesc) -> int:
     return int(lib().snake_mlp_param_count(ctypes.byref(m)))
+
+
+def snake_mlp_weight_count(m: MlpDesc, K=1) -> int:
+    return int(lib().snake_mlp_weight_count(ctypes.byref(m), int(K)))
 
 
 def snake_mlp_act_width(m: MlpDesc) -> int:

@@ -55,9 +55,36 @@ int num_cus()
     return g_cus[dev];
 }
 
+// Launch-shape tunables (the only process-wide setting).
+static const int32_t kTuneDefault[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 1024, 0, 16};
+static const int32_t kTuneMin[SNAKE_TUNE_COUNT] = {1, 1, 0, 1, 64, 0, 1};
+static const int32_t kTuneMax[SNAKE_TUNE_COUNT] = {64, 16, 2, 64, 1024, 32, 64};
+static int32_t g_tune[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 1024, 0, 16};
+
+int tune(int which) { return g_tune[which]; }
+
 }  // namespace snake
 
 extern "C" {
+
+int snake_tune_set(int32_t which, int32_t value)
+{
+    SNAKE_REQUIRE(which >= 0 && which < SNAKE_TUNE_COUNT, SNAKE_ERR_INVALID_ARG, "snake_tune_set: unknown id %d",
+                  which);
+    if (value == 0 && snake::kTuneMin[which] > 0) value = snake::kTuneDefault[which];
+    SNAKE_REQUIRE(value >= snake::kTuneMin[which] && value <= snake::kTuneMax[which], SNAKE_ERR_INVALID_ARG,
+                  "snake_tune_set: value %d of tunable %d not in [%d, %d]", value, which, snake::kTuneMin[which],
+                  snake::kTuneMax[which]);
+    snake::g_tune[which] = value;
+    snake::clear_error();
+    return SNAKE_OK;
+}
+
+int32_t snake_tune_get(int32_t which)
+{
+    if (which < 0 || which >= SNAKE_TUNE_COUNT) return -1;
+    return snake::g_tune[which];
+}
 
 int snake_abi_version(void) { return SNAKE_ABI_VERSION; }
 

@@ -43,6 +43,9 @@ inline int launch_status(const char *fn)
 // Number of compute units of the current device (cached per device).
 int num_cus();
 
+// Current value of a launch-shape tunable (snake_tunable).
+int tune(int which);
+
 // Blocks for a grid-stride loop: enough to fill every CU `per_cu` times, but
 // no more than the work needs.
 inline unsigned grid_for(int64_t work_items, int block, int per_cu)

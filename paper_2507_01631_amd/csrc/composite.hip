@@ -221,7 +221,7 @@ int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, c
     SNAKE_NOT_NULL(packed_info);
     SNAKE_NOT_NULL(rgb_out);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    composite_fwd_kernel<<<grid_for((int64_t)R * 64, 256, 8), 256, 0, st>>>(
+    composite_fwd_kernel<<<grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_COMPOSITE_BLOCKS_PER_CU)), 256, 0, st>>>(
         sigma, rgb, t0, t1, packed_info, R, sample_map, early_stop_T, target, loss_scale, rgb_out, opacity, depth,
         n_alive, loss);
     return launch_status(__func__);
@@ -242,7 +242,7 @@ int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, c
     SNAKE_NOT_NULL(dsigma);
     SNAKE_NOT_NULL(drgb);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    composite_bwd_kernel<<<grid_for((int64_t)R * 64, 256, 8), 256, 0, st>>>(
+    composite_bwd_kernel<<<grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_COMPOSITE_BLOCKS_PER_CU)), 256, 0, st>>>(
         sigma, rgb, t0, t1, packed_info, R, sample_map, n_alive, target, loss_scale, dsigma, drgb);
     return launch_status(__func__);
 }

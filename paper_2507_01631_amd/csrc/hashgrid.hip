@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 // share a corner are first merged across the wavefront, which shortens the
 // item list on the coarse levels.
 
-constexpr int kBinBlocks = 1024;        // blocks of the count/scatter passes
+constexpr int kBinBlocks = 1024;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
 constexpr int kAccWords = 8192;         // LDS accumulator: 8192 int64 = 64 KB
 constexpr int64_t kReduceChunk = 1 << 21;
@@ -685,7 +685,7 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const float *table,
     SNAKE_ALIGNED(table, 16);
     const int F = gd->n_features;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const unsigned grid = grid_for(n * g.L, 256, 16);
+    const unsigned grid = grid_for(n * g.L, 256, tune(SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU));
     const bool bf = gd->feat_dtype == SNAKE_BF16;
 #define SNAKE_HG_FWD(FF)                                                                              \
     if (bf)                                                                                           \
@@ -751,9 +751,11 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
                       "snake_hashgrid_bwd: K * T = %lld slots per level is too many for the binned adjoint "
                       "(pass workspace = NULL for the atomic form)", (long long)K << gd->log2_table);
     }
-    // largest level group whose items fit the workspace
+    // largest level group whose items fit the workspace (and the tuned cap)
+    const int nblk = tune(SNAKE_TUNE_BIN_BLOCKS);
+    const int lg_cap = tune(SNAKE_TUNE_BIN_LEVELS_PER_PASS);
     int lg = 0;
-    for (int cand = g.L; cand >= 1; --cand) {
+    for (int cand = lg_cap > 0 && lg_cap < g.L ? lg_cap : g.L; cand >= 1; --cand) {
         const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, 0, cand);
         // item offsets are int32: a pass holds fewer than 2^31 items
         if (bp.nb <= kMaxBins && scatter_lds_bytes(bp.nb, bp.nbpl, F) <= kScatterLds &&
@@ -767,7 +769,7 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     for (int l0 = 0; l0 < g.L; l0 += lg) {
         const int lgp = l0 + lg <= g.L ? lg : g.L - l0;
         const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, l0, lgp);
-        const int64_t ncnt = (int64_t)bp.nb * kBinBlocks;
+        const int64_t ncnt = (int64_t)bp.nb * nblk;
         char *p = static_cast<char *>(workspace);
         BinWs w;
         w.counts = reinterpret_cast<int32_t *>(p);
@@ -785,13 +787,13 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         const int64_t chunks = (w.item_cap + kReduceChunk - 1) / kReduceChunk;
         const unsigned rgrid = (unsigned)(chunks < 4096 ? (chunks > 0 ? chunks : 1) : 4096);
 #define SNAKE_BIN_PASS(FF)                                                                               \
-    bin_count_kernel<FF><<<kBinBlocks, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat,   \
+    bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat,   \
                                                      w.counts, w.binmax);                                 \
     scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items,             \
                       device_error_word(), st);                                                           \
-    bin_scatter_kernel<FF><<<kBinBlocks, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(              \
+    bin_scatter_kernel<FF><<<nblk, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(              \
         g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.items, w.binmax);        \
-    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, g.L, w.offsets, kBinBlocks, w.n_items, w.items,     \
+    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, g.L, w.offsets, nblk, w.n_items, w.items,     \
                                                  w.binmax, dtable)
         if (F == 1) {
             SNAKE_BIN_PASS(1);

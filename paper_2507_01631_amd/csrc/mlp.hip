@@ -44,7 +44,23 @@ struct MlpArgs {
     unsigned int *err;      // device error word
     int K;                  // NeRF tiles, each with its own weight set
     const int64_t *tile_start;  // [K+2] sample groups per tile (NULL: one group)
+    int shared_colour;      // 1: density nets per tile, one colour net for all
+    int32_t Pd;             // density parameters of one set (D1 + D2)
 };
+
+// Base pointers of tile k's density and colour weights, so that
+// wd + off[0..1] and wc + off[2..4] address its matrices.  Per-tile sets are
+// [K][P]; with a shared colour net the layout is [K][Pd] then one colour set.
+__host__ __device__ inline void tile_weights(const MlpArgs &a, const float *w, int k, const float *&wd,
+                                             const float *&wc)
+{
+    if (a.shared_colour) {
+        wd = w + (int64_t)k * a.Pd;
+        wc = w + (int64_t)a.K * a.Pd - a.Pd;
+    } else {
+        wd = wc = w + (int64_t)k * a.P;
+    }
+}
 
 constexpr int kMaxMlpTiles = 16;
 const int64_t kNoTable = 0;   // stands in for tile_start in size queries
@@ -307,14 +323,14 @@ struct Layout {
 };
 
 template <int PREC, int CL>
-__device__ void build_forward(typename FragT<PREC>::T *lds, const float *w, const MlpArgs &a)
+__device__ void build_forward(typename FragT<PREC>::T *lds, const float *wd, const float *wc, const MlpArgs &a)
 {
     typedef Layout<PREC, CL> Lt;
-    build_frag<PREC, 64, 32>(lds + Lt::D1, w, a, M_D1, false);
-    build_frag<PREC, 16, 64>(lds + Lt::D2, w, a, M_D2, false);
-    build_frag<PREC, 64, 32>(lds + Lt::C1, w, a, M_C1, false);
-    if (CL == 2) build_frag<PREC, 64, 64>(lds + Lt::C2, w, a, M_C2, false);
-    build_frag<PREC, 16, 64>(lds + Lt::CO, w, a, M_CO, false);
+    build_frag<PREC, 64, 32>(lds + Lt::D1, wd, a, M_D1, false);
+    build_frag<PREC, 16, 64>(lds + Lt::D2, wd, a, M_D2, false);
+    build_frag<PREC, 64, 32>(lds + Lt::C1, wc, a, M_C1, false);
+    if (CL == 2) build_frag<PREC, 64, 64>(lds + Lt::C2, wc, a, M_C2, false);
+    build_frag<PREC, 16, 64>(lds + Lt::CO, wc, a, M_CO, false);
 }
 
 // Forward of one 16-sample tile; keeps every activation.
@@ -445,7 +461,9 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
         }
         if (k != cur) {                                      // block-uniform
             __syncthreads();
-            build_forward<PREC, CL>(lds, w + (int64_t)k * a.P, a);
+            const float *wd, *wc;
+            tile_weights(a, w, k, wd, wc);
+            build_forward<PREC, CL>(lds, wd, wc, a);
             __syncthreads();
             cur = k;
         }
@@ -832,33 +850,54 @@ __global__ __launch_bounds__(kBlock) void mlp_frag_kernel(MlpArgs a, const float
 {
     typedef Layout<PREC, CL> Lt;
     typename Lt::T *dst = frag + (int64_t)blockIdx.x * Lt::ALL;
-    const float *wk = w + (int64_t)blockIdx.x * a.P;
-    build_forward<PREC, CL>(dst, wk, a);
-    build_frag<PREC, 64, 16>(dst + Lt::COT, wk, a, M_CO, true);
-    if (CL == 2) build_frag<PREC, 64, 64>(dst + Lt::C2T, wk, a, M_C2, true);
-    build_frag<PREC, 16, 64>(dst + Lt::C1T, wk, a, M_C1, true);
-    build_frag<PREC, 64, 16>(dst + Lt::D2T, wk, a, M_D2, true);
-    build_frag<PREC, 32, 64>(dst + Lt::D1T, wk, a, M_D1, true);
+    const float *wd, *wc;
+    tile_weights(a, w, blockIdx.x, wd, wc);
+    build_forward<PREC, CL>(dst, wd, wc, a);
+    build_frag<PREC, 64, 16>(dst + Lt::COT, wc, a, M_CO, true);
+    if (CL == 2) build_frag<PREC, 64, 64>(dst + Lt::C2T, wc, a, M_C2, true);
+    build_frag<PREC, 16, 64>(dst + Lt::C1T, wc, a, M_C1, true);
+    build_frag<PREC, 64, 16>(dst + Lt::D2T, wd, a, M_D2, true);
+    build_frag<PREC, 32, 64>(dst + Lt::D1T, wd, a, M_D1, true);
 }
 
-// dW[k][p] += the sum, over the blocks that processed units of weight set k
-// (in block order), of their padded rows.  Which blocks those are follows from
+// dW += the sums, over the blocks that processed units of each weight set (in
+// block order), of their padded rows.  Which blocks those are follows from
 // the same unit table the adjoint used (block b takes units u = b mod grid).
+// Per-tile sets: dW[k][p] sums set k's rows.  Shared colour net: dW[k][p] for
+// the density part of set k, then one colour part summed over all sets (in
+// set order, then block order).
 __global__ __launch_bounds__(256) void reduce_partials_kernel(MlpArgs a, const float *__restrict__ partial, int nb,
                                                               int W, int64_t n, const int64_t *__restrict__ n_dev,
                                                               float *__restrict__ dW)
 {
     __shared__ UnitTable U;
     setup_units(U, a, effective_n(n, n_dev));
-    const int64_t total = (int64_t)a.K * a.P;
+    const int Pc = a.P - a.Pd;
+    const int64_t total = a.shared_colour ? (int64_t)a.K * a.Pd + Pc : (int64_t)a.K * a.P;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(e / a.P), p = (int)(e - (int64_t)k * a.P);
-        const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
-        const float *src = partial + (int64_t)k * W + padded_index(a, p);
+        int k0, k1, p;
+        if (!a.shared_colour) {
+            k0 = (int)(e / a.P);
+            p = (int)(e - (int64_t)k0 * a.P);
+            k1 = k0 + 1;
+        } else if (e < (int64_t)a.K * a.Pd) {
+            k0 = (int)(e / a.Pd);
+            p = (int)(e - (int64_t)k0 * a.Pd);
+            k1 = k0 + 1;
+        } else {
+            k0 = 0;
+            k1 = a.K;
+            p = a.Pd + (int)(e - (int64_t)a.K * a.Pd);
+        }
+        const int pi = padded_index(a, p);
         float s = 0.0f;
-        for (int b = 0; b < nb; ++b) {
-            const int u = ua + ((b - ua) % nb + nb) % nb;   // block b's first unit of set k
-            if (u < ue) s += src[(int64_t)b * a.K * W];
+        for (int k = k0; k < k1; ++k) {
+            const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
+            const float *src = partial + (int64_t)k * W + pi;
+            for (int b = 0; b < nb; ++b) {
+                const int u = ua + ((b - ua) % nb + nb) % nb;   // block b's first unit of set k
+                if (u < ue) s += src[(int64_t)b * a.K * W];
+            }
         }
         dW[e] += s;
     }
@@ -909,6 +948,10 @@ int make_args(const snake_mlp_desc *m, int64_t R, MlpArgs &a, const char *fn, in
     a.off[4] = o;
     o += a.CO * 64;
     a.P = o;
+    a.Pd = a.off[2];
+    SNAKE_REQUIRE(m->shared_colour == 0 || m->shared_colour == 1, SNAKE_ERR_INVALID_ARG,
+                  "%s: shared_colour = %d not 0 or 1", fn, m->shared_colour);
+    a.shared_colour = m->shared_colour;
     return SNAKE_OK;
 }
 
@@ -931,7 +974,7 @@ void launch_fwd(const MlpArgs &a, const float *w, const void *feat, const float 
                 const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev, float *sigma,
                 float *rgb, float *act, hipStream_t st)
 {
-    const unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, 4);
+    const unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, tune(SNAKE_TUNE_MLP_FWD_BLOCKS_PER_CU));
     if (act)
         mlp_fwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun,
                                                                     ray_id, sidx, n, n_dev, sigma, rgb, act);
@@ -946,7 +989,8 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
                 const float *dsigma, const float *drgb, const float *act, float *dW, float *dfeat, float *partial,
                 hipStream_t st)
 {
-    unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, PREC == P_BF16 ? 2 : 1);
+    const int per_cu = tune(SNAKE_TUNE_MLP_BWD_BLOCKS_PER_CU);
+    unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, per_cu ? per_cu : (PREC == P_BF16 ? 2 : 1));
     if (grid > (unsigned)kMaxBwdBlocks) grid = kMaxBwdBlocks;
     typedef typename FragT<PREC>::T FragEl;
     FragEl *frag = reinterpret_cast<FragEl *>(reinterpret_cast<char *>(partial) + partial_bytes(a));
@@ -959,7 +1003,7 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
         mlp_bwd_kernel<PREC, CL, FT, false><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld,
                                                                      view, sun, ray_id, sidx, n, n_dev, dsigma, drgb,
                                                                      act, dfeat, partial, frag);
-    const int64_t kp = (int64_t)a.K * a.P;
+    const int64_t kp = a.shared_colour ? (int64_t)a.K * a.Pd + (a.P - a.Pd) : (int64_t)a.K * a.P;
     reduce_partials_kernel<<<(unsigned)((kp + 255) / 256), 256, 0, st>>>(a, partial, (int)grid, PadRow<CL>::W, n,
                                                                          n_dev, dW);
 }
@@ -976,6 +1020,13 @@ int64_t snake_mlp_param_count(const snake_mlp_desc *m)
     MlpArgs a;
     if (make_args(m, 0, a, __func__)) return -1;
     return a.P;
+}
+
+int64_t snake_mlp_weight_count(const snake_mlp_desc *m, int32_t K)
+{
+    MlpArgs a;
+    if (K < 1 || K > kMaxMlpTiles || make_args(m, 0, a, __func__)) return -1;
+    return a.shared_colour ? (int64_t)K * a.Pd + (a.P - a.Pd) : (int64_t)K * a.P;
 }
 
 int32_t snake_mlp_act_width(const snake_mlp_desc *m)

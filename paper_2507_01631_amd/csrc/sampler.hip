@@ -376,7 +376,7 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
         return launch_status(__func__);
     }
     ScanWs w = carve(workspace, R);
-    const unsigned gc = grid_for(R, 256, 8), gf = grid_for((int64_t)R * 64, 256, 16);
+    const unsigned gc = grid_for(R, 256, 8), gf = grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU));
 #define SNAKE_SAMPLER_LAUNCH(KM)                                                                   \
     count_kernel<KM><<<gc, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, max_count,     \
                                          w.counts, view);                                        \

@@ -34,7 +34,7 @@ class WindowNeRF:
     def __init__(self, *, boxes, zband, res, n_features, log2_table, n_dir, colour_layers, colour_out,
                  precision="bf16", tables=None, mlp_params=None, max_rays=1 << 16, max_samples=None,
                  samples=128, early_stop=0.0, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, hash_ws_gib=16.0,
-                 device="cuda"):
+                 shared_colour=False, lr_colour=None, device="cuda"):
         self.device = torch.device(device)
         self.boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 6)
         self.K = self.boxes.shape[0]
@@ -48,20 +48,26 @@ class WindowNeRF:
         self.precision = precision
         self.feat_dtype = L.SNAKE_BF16 if bf else L.SNAKE_F32
         self.grid = L.grid_desc(self.res, self.F, self.log2T, self.feat_dtype)
+        # shared_colour: density nets per tile, one global colour net (Sec. 4.1)
+        # with its own optimiser; weights are [K][Pd] then the colour set
+        self.shared_colour = bool(shared_colour)
         self.mlp = L.mlp_desc(self.Lv, self.F, n_dir, colour_layers, colour_out,
-                              L.SNAKE_BF16 if bf else L.SNAKE_F32, self.feat_dtype)
+                              L.SNAKE_BF16 if bf else L.SNAKE_F32, self.feat_dtype, int(self.shared_colour))
         self.n_dir = int(n_dir)
         self.P = L.snake_mlp_param_count(self.mlp)
+        self.Pd = 64 * 32 + 16 * 64
+        self.n_w = L.snake_mlp_weight_count(self.mlp, self.K)
         dev = self.device
         tshape = (self.K, self.Lv, 1 << self.log2T, self.F)
         self.table = (torch.zeros(tshape, device=dev) if tables is None else
                       torch.as_tensor(np.ascontiguousarray(tables, dtype=np.float32)).to(dev).reshape(tshape))
-        self.params = (torch.zeros((self.K, self.P), device=dev) if mlp_params is None else
+        self.params = (torch.zeros(self.n_w, device=dev) if mlp_params is None else
                        torch.as_tensor(np.ascontiguousarray(mlp_params, dtype=np.float32)).to(dev)
-                       .reshape(self.K, self.P))
+                       .reshape(self.n_w))
         self.m_t, self.v_t, self.g_t = (torch.zeros_like(self.table) for _ in range(3))
         self.m_w, self.v_w, self.g_w = (torch.zeros_like(self.params) for _ in range(3))
         self.lr, (self.b1, self.b2), self.eps = float(lr), betas, float(eps)
+        self.lr_colour = self.lr if lr_colour is None else float(lr_colour)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
         self.hash_ws_gib = float(hash_ws_gib)
         self.graph = None
@@ -172,9 +178,14 @@ class WindowNeRF:
         L.snake_adam_step(self.table, self.g_t, self.m_t, self.v_t, self.table.numel(), self.lr, self.b1,
                           self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
                           stream=stream)
-        L.snake_adam_step(self.params, self.g_w, self.m_w, self.v_w, self.params.numel(), self.lr, self.b1,
-                          self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
-                          stream=stream)
+        # the networks: per-tile sets, or the density sets and the shared colour
+        # net as two optimisers (each may have its own learning rate)
+        nd = self.K * self.Pd if self.shared_colour else self.n_w
+        parts = [(0, nd, self.lr)] + ([(nd, self.n_w - nd, self.lr_colour)] if self.shared_colour else [])
+        for off, cnt, lr in parts:
+            L.snake_adam_step(self.params[off:], self.g_w[off:], self.m_w[off:], self.v_w[off:], cnt, lr,
+                              self.b1, self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
+                              stream=stream)
 
     # -- HIP graph ---------------------------------------------------------
     def capture(self, rays_o, rays_d, target, samples_per_ray=None, sun=None, warmup=1):

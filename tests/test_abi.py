@@ -45,7 +45,7 @@ def test_abi_version_and_error_string(L):
 def test_struct_layouts_match_header(L):
     # two int32 + int32 + int32 + uint32 + 32 int32
     assert ctypes.sizeof(L.GridDesc) == 4 * 5 + 4 * 32
-    assert ctypes.sizeof(L.MlpDesc) == 4 * 7
+    assert ctypes.sizeof(L.MlpDesc) == 4 * 8
 
 
 def test_param_count_matches_oracle(L, orc):
@@ -59,6 +59,19 @@ def test_level_resolutions_match_oracle(orc):
     from paper_2507_01631_amd import level_resolutions
     for Lv, lo, hi in [(8, 16, 256), (16, 16, 2048), (12, 8, 4096), (1, 32, 32)]:
         assert list(orc.level_resolutions(Lv, lo, hi)) == level_resolutions(Lv, lo, hi)
+
+
+def test_weight_count_shared_colour(L):
+    for d in (L.mlp_desc(8, 2, 3, 1, 3), L.mlp_desc(16, 2, 6, 2, 4)):
+        P = L.snake_mlp_param_count(d)
+        assert L.snake_mlp_weight_count(d, 4) == 4 * P
+        d.shared_colour = 1
+        Pd = 64 * 32 + 16 * 64
+        assert L.snake_mlp_weight_count(d, 4) == 4 * Pd + (P - Pd)
+        assert L.snake_mlp_weight_count(d, 1) == P
+        assert L.snake_mlp_weight_count(d, 0) == -1
+    d.shared_colour = 2
+    assert L.snake_mlp_param_count(d) == -1
 
 
 def test_act_width(L):
@@ -166,3 +179,24 @@ def test_host_side_argument_errors(L):
 def test_binding_raises_on_error(L):
     with pytest.raises(L.SnakeError):
         L.snake_adam_step(None, None, None, None, 4, 1e-2, 0.9, 0.99, 1e-15, 0, stream=0)
+
+
+def test_tunables_table(L):
+    ids = L.TUNABLES
+    assert len(ids) == 7 and sorted(ids.values()) == list(range(7))
+    saved = {k: L.snake_tune_get(k) for k in ids}
+    try:
+        assert saved["hash_fwd_blocks_per_cu"] == 16 and saved["bin_blocks"] == 1024
+        L.snake_tune_set("bin_blocks", 256)
+        assert L.snake_tune_get("bin_blocks") == 256
+        L.snake_tune_set("bin_blocks", 0)                      # 0 restores the default
+        assert L.snake_tune_get("bin_blocks") == 1024
+        for which, bad in (("bin_blocks", 2048), ("mlp_bwd_blocks_per_cu", 3), ("hash_fwd_blocks_per_cu", -1)):
+            with pytest.raises(L.SnakeError):
+                L.snake_tune_set(which, bad)
+        with pytest.raises(L.SnakeError):
+            L.snake_tune_set(99, 1)
+        assert L.snake_tune_get(99) == -1
+    finally:
+        for k, v in saved.items():
+            L.snake_tune_set(k, v)

@@ -292,13 +292,16 @@ def test_bad_tile_and_ray_ids_are_dropped_and_flagged(L, orc):
     assert L.snake_check_device_error() & L.SNAKE_DEVERR_RAY_ID
 
 
+@pytest.mark.parametrize("shared", [0, 1])
 @pytest.mark.parametrize("name", list(MLPS))
-def test_mlp_per_tile_weights(L, orc, name):
+def test_mlp_per_tile_weights(L, orc, name, shared):
     """Window form: K = 4 weight sets selected by each sample's tile after the
     tile partition, with uneven group sizes (one empty), 16-sample tiles that
     would straddle groups, and a few invalid tile ids (dropped: sigma = rgb = 0,
     dfeat = 0).  Each group matches the oracle run on its own samples with its
-    own weights; dW is [K][P]."""
+    own weights; dW is [K][P].  With a shared colour net the weights are the
+    four density sets then one colour set, and the colour gradient sums over
+    the tiles."""
     rng = np.random.default_rng(77)
     cfg, Lv, F = MLPS[name]
     K, n, R = 4, 6007, 900
@@ -321,22 +324,35 @@ def test_mlp_per_tile_weights(L, orc, name):
     pm = host(perm)
     bounds = host(ts)
     fs = feat[pm]
-    m = L.mlp_desc(Lv, F, cfg.n_dir, cfg.colour_layers, cfg.colour_out)
+    m = L.mlp_desc(Lv, F, cfg.n_dir, cfg.colour_layers, cfg.colour_out, shared_colour=shared)
+    Pd = 64 * 32 + 16 * 64
+    if shared:
+        W[:, Pd:] = W[0, Pd:]                                  # one colour set for every tile
+        Wg = np.concatenate([W[:, :Pd].ravel(), W[0, Pd:]])
+    else:
+        Wg = W.reshape(-1)
+    assert Wg.size == L.snake_mlp_weight_count(m, K)
     fd = dev(fs.reshape(n, Lv, F).transpose(1, 0, 2))
     sig = torch.full((n,), 7.0, device=DEV)
     rgb = torch.full((n, 3), 7.0, device=DEV)
-    L.snake_mlp_fwd(m, dev(W.reshape(-1)), fd, dev(view), sun_d, rs, R, None, n, None, sig, rgb, K=K,
+    L.snake_mlp_fwd(m, dev(Wg), fd, dev(view), sun_d, rs, R, None, n, None, sig, rgb, K=K,
                     tile_start=ts)
     ds = rng.normal(size=n).astype(np.float32)
     dr = rng.normal(size=(n, 3)).astype(np.float32)
-    dW = torch.zeros(K * P, device=DEV)
+    dW = torch.zeros(Wg.size, device=DEV)
     dfeat = torch.full((Lv, n, F), 7.0, device=DEV)
     wsb = torch.empty(L.snake_mlp_bwd_workspace_bytes(m, K), dtype=torch.uint8, device=DEV)
-    L.snake_mlp_bwd(m, dev(W.reshape(-1)), fd, n, dev(view), sun_d, rs, R, None, n, None, dev(ds), dev(dr),
+    L.snake_mlp_bwd(m, dev(Wg), fd, n, dev(view), sun_d, rs, R, None, n, None, dev(ds), dev(dr),
                     dW, dfeat, wsb, K=K, tile_start=ts)
     sync()
     g_sig, g_rgb = host(sig), host(rgb)
-    g_dw = host(dW).reshape(K, P)
+    g_all = host(dW)
+    g_dw = np.zeros((K, P))
+    if shared:
+        g_dw[:, :Pd] = g_all[:K * Pd].reshape(K, Pd)
+    else:
+        g_dw[:] = g_all.reshape(K, P)
+    r_col = np.zeros(P - Pd)
     g_df = host(dfeat).transpose(1, 0, 2).reshape(n, -1)
     for k in range(K + 1):
         sl = slice(bounds[k], bounds[k + 1])
@@ -353,6 +369,12 @@ def test_mlp_per_tile_weights(L, orc, name):
         assert_values(g_rgb[sl], r_rgb, rel=1e-5, abs_=1e-7, what="rgb tile %d" % k)
         rW, rf = orc.mlp_bwd(cfg, W[k], _pad32(fs[sl]), view, host(rs)[sl], ds[sl], dr[sl],
                              sun=sun if cfg.n_dir == 6 else None)
-        assert_grad(g_dw[k], rW, 1e-4, "dW tile %d" % k)
+        if shared:
+            assert_grad(g_dw[k, :Pd], rW[:Pd], 1e-4, "density dW tile %d" % k)
+            r_col += rW[Pd:]
+        else:
+            assert_grad(g_dw[k], rW, 1e-4, "dW tile %d" % k)
         assert_grad(g_df[sl], rf[:, :Lv * F], 1e-4, "dfeat tile %d" % k)
     assert bounds[3] == bounds[2]
+    if shared:
+        assert_grad(g_all[K * Pd:], r_col, 1e-4, "shared colour dW")

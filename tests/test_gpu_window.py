@@ -16,14 +16,19 @@ def _window(rays_per_tile, seed=0):
     return w
 
 
-def _nerf(w, precision, R, cap=None):
+PD = 64 * 32 + 16 * 64
+
+
+def _nerf(w, precision, R, cap=None, shared=False):
     from paper_2507_01631_amd import WindowNeRF, level_resolutions
     g, m = w.grid, w.mlp
+    params = (np.concatenate([w.mlp_params[:, :PD].ravel(), w.mlp_params[0, PD:]]) if shared
+              else w.mlp_params)
     return WindowNeRF(boxes=w.boxes, zband=None, res=level_resolutions(g.n_levels, g.res_min, g.res_max),
                       n_features=g.n_features, log2_table=g.log2_table, n_dir=m.n_dir,
                       colour_layers=m.colour_layers, colour_out=m.colour_out, precision=precision,
-                      tables=w.table, mlp_params=w.mlp_params, max_rays=R, max_samples=cap, samples=128,
-                      lr=w.lr, device=DEV)
+                      tables=w.table, mlp_params=params, max_rays=R, max_samples=cap, samples=128,
+                      lr=w.lr, shared_colour=shared, device=DEV)
 
 
 def _accepted(w, orc):
@@ -45,16 +50,19 @@ def test_window_accept_matches_oracle(orc):
     assert np.array_equal(host(idx)[:int(ref.sum())], np.nonzero(ref)[0])
 
 
-def test_window_step_matches_oracle(orc):
+@pytest.mark.parametrize("shared", [False, True])
+def test_window_step_matches_oracle(orc, shared):
     """FP32 window step on the accepted rays vs the oracle's step with one
-    weight set per tile: values within 1e-5, gradients within 1e-4."""
+    weight set per tile (or per-tile density nets and one shared colour net):
+    values within 1e-5, gradients within 1e-4."""
     w, _ = _accepted(_window([900, 700, 800, 600], seed=1), orc)
     R = w.n_rays
-    nerf = _nerf(w, "fp32", R)
+    nerf = _nerf(w, "fp32", R, shared=shared)
     ro, rd, tg, spr = dev(w.rays_o), dev(w.rays_d), dev(w.target), dev(w.samples_per_ray)
     nerf.step(ro, rd, tg, spr, update=False)
     sync()
-    o = orc.train_step(w)
+    o = orc.train_step(w, mlp_params=({"density": w.mlp_params[:, :PD], "colour": w.mlp_params[0, PD:]}
+                                      if shared else None))
     smp = o["sample"]
     n = int(host(nerf.n_out)[0])
     assert n == smp["n"]

@@ -743,3 +743,27 @@ def test_train_step_per_tile_weights_reduce_to_shared(orc):
     # every tile holds samples, so every set receives a gradient of its own
     assert np.all(np.abs(dWk).sum(1) > 0)
     assert tiled["mlp_new"].shape == (4, W.shape[1])
+
+
+def test_train_step_shared_colour_net(orc):
+    """Per-tile density nets with one shared colour net: equal to the per-tile
+    step whose four sets carry that same colour net, with the colour gradient
+    the sum of the four per-tile colour gradients."""
+    import copy
+    wl = synth.tiny_tile(seed=6, n_rays=200, samples=16)
+    wl = copy.copy(wl)
+    wl.boxes = np.array([[0, 0, 0, 0.5, 0.5, 1], [0, 0.5, 0, 0.5, 1, 1], [0.5, 0, 0, 1, 0.5, 1],
+                         [0.5, 0.5, 0, 1, 1, 1]], dtype=np.float64)
+    rng = np.random.default_rng(4)
+    wl.table = synth.init_table(rng, wl.grid, n_tiles=4) * np.float32(1e4)
+    Pd = 64 * 32 + 16 * 64
+    W = np.stack([synth.init_mlp(rng, wl.mlp) for _ in range(4)])
+    W[:, Pd:] = W[0, Pd:]
+    per_tile = orc.train_step(wl, mlp_params=W)
+    shared = orc.train_step(wl, mlp_params={"density": W[:, :Pd], "colour": W[0, Pd:]})
+    assert np.array_equal(shared["sigma"], per_tile["sigma"])
+    assert shared["loss"] == per_tile["loss"]
+    dWt = per_tile["dW"].reshape(4, -1)
+    assert np.array_equal(shared["dW"][:4 * Pd], dWt[:, :Pd].ravel())
+    assert np.allclose(shared["dW"][4 * Pd:], dWt[:, Pd:].sum(0), rtol=1e-13, atol=1e-20)
+    assert shared["mlp_new"].size == 4 * Pd + W.shape[1] - Pd
