@@ -285,6 +285,59 @@ def window_bench(args):
     return out
 
 
+def sweep_bench(args):
+    """Snake sweep over a grid of full-size tiles (L=16, F=2, T=2^19 tables
+    and Adam state in FP32, BF16 networks 32-64-16 / 18-64-3), 2x2 window
+    graph-replayed, tiles swapped host<->device by pinned async copies on a
+    side stream.  Times every window of a 3x3 and of a 4x4 grid (linearity:
+    time per window-step should not depend on the grid), then renders a
+    depth map of 2048x2048 rays over one tile (forward only)."""
+    import torch
+    import synth
+    from paper_2507_01631_amd import level_resolutions
+    from paper_2507_01631_amd.sweep import SnakeSweep, snake_path
+    dev = "cuda:0"
+    R, steps = args.sweep_rays, args.sweep_steps
+    kw = dict(res=level_resolutions(16, 16, 2048), n_features=2, log2_table=19, n_dir=3, colour_layers=1,
+              colour_out=3)
+    pool = {}
+
+    def batches(pos, k):
+        key = k % 2
+        if key not in pool:
+            o, d, t, sp = synth.window_rays(100 + key, R, spr_range=(64, 128))
+            pool[key] = tuple(torch.as_tensor(x).to(dev) for x in (o, d, t, sp))
+        return pool[key]
+    out = {"config": "tiles L=16 F=2 T=2^19 (FP32 table + Adam), BF16 MLP 32-64-16 / 18-64-3; %d rays x "
+                     "64..128 samples per step, %d steps per window" % (R, steps), "grids": []}
+    for n in args.sweep_grids:
+        sw = SnakeSweep(n, n, precision="bf16", max_rays=R, samples=128, seed=n, device=dev, **kw)
+        t = sw.run(steps, batches, graph=True)
+        npath = len(snake_path(n, n))
+        # the first window also pays for the graph capture and the initial load
+        steady = t[1:] if len(t) > 1 else t
+        out["grids"].append({"tiles": n * n, "windows": npath, "total_s": round(sum(t), 4),
+                             "ms_per_window_step": round(1e3 * float(np.mean(steady)) / steps, 4),
+                             "window_ms": [round(1e3 * x, 2) for x in t]})
+        log("  sweep %dx%d: %s" % (n, n, json.dumps(out["grids"][-1])))
+        win = sw.win
+        del sw
+    # depth render of one tile, 2048 x 2048 rays, forward only
+    nr = args.render_px ** 2
+    o, d, _, _ = synth.window_rays(7, nr, margin=0.0)
+    o[:, :2] = o[:, :2] * 0.5                     # ground points over tile (0, 0) only
+    o_t, d_t = torch.as_tensor(o).to(dev), torch.as_tensor(d).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    depth = win.render_depth(o_t, d_t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["depth_render"] = {"rays": nr, "s": round(dt, 4), "rays_per_s": nr / dt,
+                           "depth_mean": float(depth.mean().item())}
+    log("  depth render: %s" % json.dumps(out["depth_render"]))
+    return out
+
+
 def cpu_baseline(args):
     import oracle
     import synth
@@ -313,6 +366,11 @@ def main():
     ap.add_argument("--recompute-rays", type=int, default=1 << 16)
     ap.add_argument("--no-recompute-check", action="store_true")
     ap.add_argument("--no-window", action="store_true", help="skip the 2x2 window (graph vs separate) run")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the snake sweep run")
+    ap.add_argument("--sweep-grids", type=int, nargs="+", default=[3, 4])
+    ap.add_argument("--sweep-steps", type=int, default=5)
+    ap.add_argument("--sweep-rays", type=int, default=1 << 16)
+    ap.add_argument("--render-px", type=int, default=2048)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 256 MiB device copies (byte-counter calibration)")
     args = ap.parse_args()
@@ -376,6 +434,8 @@ def main():
         line["window"] = window_bench(args)
     if not args.no_recompute_check:
         line["recompute"] = recompute_check(args)
+    if not args.no_sweep:
+        line["sweep"] = sweep_bench(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(args)

@@ -73,6 +73,7 @@ typedef enum {
 #define SNAKE_DEVERR_TILE_ID 2u   /* a tile_id >= K (the sample is dropped) */
 #define SNAKE_DEVERR_RAY_ID 4u    /* a ray_id >= R (the sample is dropped) */
 #define SNAKE_DEVERR_INTERNAL 8u  /* an internal consistency check failed (nothing written out of range) */
+#define SNAKE_DEVERR_NONFINITE 16u /* binned table adjoint: a non-finite feature gradient (its level adds nothing) */
 
 typedef enum { SNAKE_F32 = 0, SNAKE_BF16 = 1 } snake_dtype;
 
@@ -202,6 +203,38 @@ int snake_tile_partition(const uint8_t *tile_id, const float *pos, const int32_t
                          int32_t *ray_out, void *workspace, size_t workspace_bytes,
                          snake_stream_t stream);
 
+/*
+ * Coarse occupancy grid and culling (the SAT-NGP procedure the paper follows
+ * in training, Sec. 4.1).  Each of K tiles has a G^3 grid over its [0,1]^3
+ * frame (G a power of two in [2, 1024]); a tile-frame position x lies in cell
+ * c_a = min(floor(x_a G), G-1), flattened (c_x G + c_y) G + c_z, tile k's grid
+ * at offset k G^3; occupancy is bit c % 32 of word c / 32.
+ *
+ * snake_occupancy_cells writes the centre ((i+.5)/G, (j+.5)/G, (k+.5)/G) of
+ * every cell of the K grids (pos [K G^3][3]) and its tile id (tile_id may be
+ * NULL), for evaluating the density there with the encoding and networks.
+ * snake_occupancy_update keeps density [n_cells] float as
+ * max(decay * density, sigma) and sets bits [ceil(n_cells/32)] uint32 to
+ * density > threshold.
+ * snake_cull_samples keeps, ray by ray and in order, the packed samples
+ * whose cell is occupied (a tile id >= K is dropped with
+ * SNAKE_DEVERR_TILE_ID) and writes them packed again: packed_info_out [R][2],
+ * t0/t1/pos/ray_id/tile_id outputs (tile_id_out may be NULL) for up to cap
+ * samples, *n_out (device) = the kept total (SNAKE_DEVERR_CAPACITY past cap).
+ * Culled intervals then add no optical depth to the quadrature.
+ * Workspace: snake_cull_workspace_bytes(R).
+ */
+int snake_occupancy_cells(int32_t G, int32_t K, float *pos, uint8_t *tile_id, snake_stream_t stream);
+int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, float threshold,
+                           float *density, uint32_t *bits, snake_stream_t stream);
+size_t snake_cull_workspace_bytes(int32_t R);
+int snake_cull_samples(int32_t G, const uint32_t *bits, int32_t K, int32_t R,
+                       const int32_t *packed_info, const float *t0, const float *t1,
+                       const float *pos, const int32_t *ray_id, const uint8_t *tile_id,
+                       int32_t *packed_info_out, float *t0_out, float *t1_out, float *pos_out,
+                       int32_t *ray_id_out, uint8_t *tile_id_out, int64_t cap, int64_t *n_out,
+                       void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Multiresolution hash encoding (Sec. 4.1; the NGP representation)          */
 /* ------------------------------------------------------------------------ */
@@ -238,14 +271,19 @@ int snake_hashgrid_fwd(const snake_grid_desc *g, int32_t K, const float *table,
 /* Adjoint: dtable[tile][l][idx_b][f] += w_b * dfeat[l][s][f] for the K tiles
  * of dtable [K][L][T][F] float; dfeat [L][n][F] float (compact, indexed by j).
  * With a workspace the corner contributions are binned by table slot (count,
- * scan, scatter) and each bin is summed in LDS, then added to dtable once per
- * touched slot; the workspace size decides how many levels share a pass
- * (snake_hashgrid_bwd_workspace_bytes(g, K, n, levels_per_pass); one level per
- * pass is the minimum).  With workspace == NULL every contribution is a direct
- * FP32 atomic add.  Either way the order of additions, hence the last bits,
- * is not deterministic.  A tile_id >= K contributes nothing and raises
- * SNAKE_DEVERR_TILE_ID.  Limits: 1 <= K <= 256, K*T <= 2^28; the binned form
- * needs 8 n < 2^31 and puts at most (2^31 - 1) / (8 n) levels in a pass. */
+ * scan, scatter) and summed exactly in 64-bit fixed point: each contribution
+ * is rounded once to an integer multiple of 2^-E_l, where E_l = 24 - e and
+ * 2^(e-1) <= max|dfeat of level l| < 2^e, then every table entry receives its
+ * sum, rounded once to FP32.  The result is deterministic (the same bits for
+ * any grid or scheduling).  A level whose dfeat holds a non-finite value adds
+ * nothing and raises SNAKE_DEVERR_NONFINITE.  The workspace size decides how
+ * many levels share a pass (snake_hashgrid_bwd_workspace_bytes(g, K, n,
+ * levels_per_pass); one level per pass is the minimum).  With workspace ==
+ * NULL every contribution is a direct FP32 atomic add, whose order, hence
+ * last bits, is not deterministic.  A tile_id >= K contributes nothing and
+ * raises SNAKE_DEVERR_TILE_ID.  Limits: 1 <= K <= 256, K*T <= 2^28; the
+ * binned form needs 8 n < 2^31 and puts at most (2^31 - 1) / (8 n) levels in
+ * a pass. */
 size_t snake_hashgrid_bwd_workspace_bytes(const snake_grid_desc *g, int32_t K, int64_t n,
                                           int32_t levels_per_pass);
 int snake_hashgrid_bwd(const snake_grid_desc *g, int32_t K, const float *pos, const uint8_t *tile_id,
@@ -384,8 +422,9 @@ int snake_adam_step(float *p, float *g, float *m, float *v, int64_t n,
                     float lr, float b1, float b2, float eps, int32_t step,
                     const int32_t *step_dev, float l2, uint32_t flags, snake_stream_t stream);
 
-/* *counter += delta on the stream (device int32). */
-int snake_counter_add(int32_t *counter, int32_t delta, snake_stream_t stream);
+/* counter[i] += delta for i < n on the stream (device int32 [n]; per-tile
+ * Adam step counters). */
+int snake_counter_add(int32_t *counter, int32_t n, int32_t delta, snake_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -237,6 +237,54 @@ def window_accept(rays_o, rays_d, window, zband):
 
 
 # ---------------------------------------------------------------------------
+# coarse occupancy grid (SAT-NGP culling, Sec. 4.1)
+# ---------------------------------------------------------------------------
+def occupancy_cell(pos, G):
+    """Cell of each tile-frame position in a G^3 grid: min(floor(fl32(x G)), G-1)
+    per axis (G a power of two, so the product is exact), flattened as
+    (i G + j) G + k with i along x."""
+    p = np.asarray(pos, dtype=np.float32).reshape(-1, 3)
+    c = np.minimum(np.floor(p * np.float32(G)).astype(np.int64), G - 1)
+    c = np.maximum(c, 0)
+    return (c[:, 0] * G + c[:, 1]) * G + c[:, 2]
+
+
+def occupancy_cell_centres(G, K=1):
+    """Tile-frame centres ((i+0.5)/G, (j+0.5)/G, (k+0.5)/G) of every cell of K
+    grids, in cell order, with their tile ids."""
+    i = np.arange(G, dtype=np.float64)
+    x = (i + 0.5) / G
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    one = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
+    return np.tile(one, (K, 1)), np.repeat(np.arange(K, dtype=np.uint8), G ** 3)
+
+
+def occupancy_update(density, sigma, decay, threshold):
+    """EMA of the cell densities: d = max(decay d, sigma); occupied iff d > threshold."""
+    d = np.maximum(np.asarray(density, dtype=np.float64) * decay, np.asarray(sigma, dtype=np.float64))
+    return d, d > threshold
+
+
+def cull_samples(smp, occupied, G):
+    """Keep the samples whose cell (in their own tile's grid) is occupied, in
+    order; returns a sampler-like dict over the kept samples."""
+    tid = smp["tile_id"].astype(np.int64)
+    cell = tid * G ** 3 + occupancy_cell(smp["pos"], G)
+    keep = np.asarray(occupied, dtype=bool)[cell]
+    info = smp["packed_info"]
+    R = info.shape[0]
+    counts = np.zeros(R, dtype=np.int32)
+    rid = smp["ray_id"]
+    np.add.at(counts, rid[keep], 1)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int32)
+    out = dict(packed_info=np.stack([starts, counts], 1), view=smp["view"], n=int(keep.sum()))
+    for k in ("t0", "t1", "pos", "ray_id", "tile_id"):
+        out[k] = smp[k][keep]
+    out["keep"] = keep
+    return out
+
+
+# ---------------------------------------------------------------------------
 # volume rendering
 # ---------------------------------------------------------------------------
 def composite_fwd(packed_info, sigma, rgb, t0, t1, target=None, loss_scale=0.0,
@@ -284,7 +332,7 @@ def adam_step(p, g, m, v, lr, step, b1=0.9, b2=0.99, eps=1e-15, l2=0.0):
 # one training step, composed in the paper's order
 # ---------------------------------------------------------------------------
 def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=1,
-               alive=None, rays=None, timings=None):
+               alive=None, rays=None, timings=None, occupancy=None):
     """One step of the tile-NeRF: segmented sampling -> hash encoding -> density
     and colour nets -> volume rendering + MSE loss -> adjoints -> Adam.
 
@@ -310,6 +358,9 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
     else:
         smp = sample_segmented(rays_o, rays_d, wl.boxes, 0, zband=wl.zband,
                                samples_per_ray=np.asarray(spr, dtype=np.int32))
+    if occupancy is not None:          # (G, occupied cells): SAT-NGP culling before the field
+        out["sample_raw"] = smp
+        smp = cull_samples(smp, occupancy[1], occupancy[0])
     out["sample"] = smp
     feat = hashgrid_fwd(res, g.log2_table, table, smp["pos"], smp["tile_id"], g.out_width)
     # one weight set ([P]) shared by the tiles, one per tile ([K][P]), or

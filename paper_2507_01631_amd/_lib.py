@@ -22,6 +22,7 @@ SNAKE_DEVERR_CAPACITY = 1
 SNAKE_DEVERR_TILE_ID = 2
 SNAKE_DEVERR_RAY_ID = 4
 SNAKE_DEVERR_INTERNAL = 8
+SNAKE_DEVERR_NONFINITE = 16
 MAX_LEVELS = 32
 TUNABLES = {
     "hash_fwd_blocks_per_cu": 0, "mlp_fwd_blocks_per_cu": 1, "mlp_bwd_blocks_per_cu": 2,
@@ -32,6 +33,7 @@ EXPORTS = (
     "snake_abi_version", "snake_last_error", "snake_check_device_error", "snake_tune_set", "snake_tune_get",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_pack_alive",
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
+    "snake_occupancy_cells", "snake_occupancy_update", "snake_cull_workspace_bytes", "snake_cull_samples",
     "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_weight_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
@@ -91,6 +93,11 @@ _SIGS = {
     "snake_pack_alive": ([_P, _P, _I32, _P, _I64, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_window_accept": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_tile_partition_workspace_bytes": ([_I32], _SZ),
+    "snake_occupancy_cells": ([_I32, _I32, _P, _P, _P], ctypes.c_int),
+    "snake_occupancy_update": ([_P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
+    "snake_cull_workspace_bytes": ([_I32], _SZ),
+    "snake_cull_samples": ([_I32, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
+                            _SZ, _P], ctypes.c_int),
     "snake_tile_partition": ([_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_hashgrid_fwd": ([_P, _I32, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "snake_hashgrid_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
@@ -107,7 +114,7 @@ _SIGS = {
                             ctypes.c_int),
     "snake_composite_bwd": ([_P, _P, _P, _P, _P, _I32, _P, _P, _P, _F, _P, _P, _P], ctypes.c_int),
     "snake_adam_step": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P, _F, _U32, _P], ctypes.c_int),
-    "snake_counter_add": ([_P, _I32, _P], ctypes.c_int),
+    "snake_counter_add": ([_P, _I32, _I32, _P], ctypes.c_int),
 }
 
 _lib = None
@@ -226,6 +233,31 @@ def snake_tile_partition(tile_id, pos, ray_id, n, n_dev, K, perm, inv, tile_star
     _check("snake_tile_partition", rc)
 
 
+def snake_occupancy_cells(G, K, pos, tile_id, stream=None):
+    _check("snake_occupancy_cells", lib().snake_occupancy_cells(int(G), int(K), _ptr(pos), _ptr(tile_id),
+                                                                _stream(stream)))
+
+
+def snake_occupancy_update(sigma, n_cells, decay, threshold, density, bits, stream=None):
+    _check("snake_occupancy_update", lib().snake_occupancy_update(_ptr(sigma), int(n_cells), float(decay),
+                                                                  float(threshold), _ptr(density), _ptr(bits),
+                                                                  _stream(stream)))
+
+
+def snake_cull_workspace_bytes(R) -> int:
+    return int(lib().snake_cull_workspace_bytes(int(R)))
+
+
+def snake_cull_samples(G, bits, K, R, packed_info, t0, t1, pos, ray_id, tile_id, packed_info_out, t0_out, t1_out,
+                       pos_out, ray_id_out, tile_id_out, cap, n_out, workspace, stream=None):
+    rc = lib().snake_cull_samples(int(G), _ptr(bits), int(K), int(R), _ptr(packed_info), _ptr(t0), _ptr(t1),
+                                  _ptr(pos), _ptr(ray_id), _ptr(tile_id), _ptr(packed_info_out), _ptr(t0_out),
+                                  _ptr(t1_out), _ptr(pos_out), _ptr(ray_id_out), _ptr(tile_id_out), int(cap),
+                                  _ptr(n_out), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _stream(stream))
+    _check("snake_cull_samples", rc)
+
+
 def snake_hashgrid_fwd(g: GridDesc, K, table, pos, tile_id, sample_idx, n, n_dev, feat, idx_dbg=None,
                        stream=None):
     rc = lib().snake_hashgrid_fwd(ctypes.byref(g), int(K), _ptr(table), _ptr(pos), _ptr(tile_id),
@@ -307,5 +339,6 @@ def snake_adam_step(p, g, m, v, n, lr, b1, b2, eps, step, l2=0.0, flags=0, step_
     _check("snake_adam_step", rc)
 
 
-def snake_counter_add(counter, delta, stream=None):
-    _check("snake_counter_add", lib().snake_counter_add(_ptr(counter), int(delta), _stream(stream)))
+def snake_counter_add(counter, delta, n=None, stream=None):
+    n = counter.numel() if n is None else int(n)
+    _check("snake_counter_add", lib().snake_counter_add(_ptr(counter), n, int(delta), _stream(stream)))

@@ -74,7 +74,11 @@ __global__ __launch_bounds__(256) void adam_kernel(float4 *__restrict__ p, float
     }
 }
 
-__global__ void counter_add_kernel(int32_t *c, int32_t d) { *c += d; }
+__global__ void counter_add_kernel(int32_t *c, int n, int32_t d)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] += d;
+}
 
 }  // namespace
 }  // namespace snake
@@ -83,10 +87,12 @@ using namespace snake;
 
 extern "C" {
 
-int snake_counter_add(int32_t *counter, int32_t delta, snake_stream_t stream)
+int snake_counter_add(int32_t *counter, int32_t n, int32_t delta, snake_stream_t stream)
 {
+    SNAKE_REQUIRE(n >= 0 && n <= (1 << 20), SNAKE_ERR_INVALID_ARG, "snake_counter_add: n = %d not in [0, 2^20]", n);
+    if (n == 0) return SNAKE_OK;
     SNAKE_NOT_NULL(counter);
-    counter_add_kernel<<<1, 1, 0, reinterpret_cast<hipStream_t>(stream)>>>(counter, delta);
+    counter_add_kernel<<<(n + 63) / 64, 64, 0, reinterpret_cast<hipStream_t>(stream)>>>(counter, n, delta);
     return launch_status(__func__);
 }
 

@@ -199,16 +199,20 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 //   scan    exclusive offsets, bin-major, so each bin's items are contiguous
 //   scatter write the items to their bin (LDS cursors per block)
 //   reduce  per chunk of items: add into a 64 KB LDS copy of the bin's slots,
-//           then flush the bin once with one global atomic per touched slot
+//           then flush the bin once with one 64-bit integer atomic per touched
+//           slot into a pass-wide integer accumulator
+//   convert every accumulator slot of the pass, scaled back, into dtable
 // A pass covers `lg` levels; bins never straddle levels.
 //
 // LDS float atomics are slow on this chip (about 2e11/s) while LDS integer
-// atomics are about 20x faster, so a bin is summed in fixed point: every
-// contribution v becomes the int32 rint(v 2^E), E chosen from the bin's
-// largest |v| so that |q| < 2^30, added into 64-bit slot sums.  Integer sums
-// do not depend on the order of addition.  Consecutive samples of a ray that
-// share a corner are first merged across the wavefront, which shortens the
-// item list on the coarse levels.
+// atomics are about 20x faster, so the sums are taken in fixed point: every
+// contribution v becomes the int32 rint(v 2^E_l), with E_l fixed per level
+// from the level's largest |dfeat| (a merged item is at most 64 of them, each
+// times a weight <= 1, so |q| < 2^30), and is added into 64-bit sums.
+// Integer sums do not depend on the order of addition, so the result is the
+// same bits whatever the chunking, the scheduling or the grid.  Consecutive
+// samples of a ray that share a corner are first merged across the
+// wavefront, which shortens the item list on the coarse levels.
 
 constexpr int kBinBlocks = 1024;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
@@ -282,15 +286,11 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
                                                         const int32_t *__restrict__ sidx, int64_t n,
                                                         const int64_t *__restrict__ n_dev,
                                                         const float *__restrict__ dfeat,
-                                                        int32_t *__restrict__ counts,
-                                                        uint32_t *__restrict__ binmax)
+                                                        int32_t *__restrict__ counts)
 {
     typedef typename Vec<F>::T VT;
     __shared__ int hist[kMaxBins];
-    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) {
-        hist[b] = 0;
-        if (blockIdx.x == 0) binmax[b] = 0u;
-    }
+    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int64_t ne = effective_n(n, n_dev);
     const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
@@ -311,6 +311,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
         if (valid && !tile_ok && g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_TILE_ID);
         for (int lr = 0; lr < bp.lg; ++lr) {
             const int l = bp.l0 + lr;
+            const bool dense_l = (g.dense_bits >> l) & 1u;
             bool act = valid && tile_ok;
             if (act) act = grad_nonzero<F>(*reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F));
             uint32_t idx[8];
@@ -328,7 +329,9 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
                 // the vote must run on every lane: inside the leader's branch
                 // EXEC holds one lane and the popcount would be 1
                 const unsigned long long am = __ballot(emit);
-                if (wave_uniform(b, emit, b0)) {
+                // a whole wavefront lands in one bin only on the coarse, densely
+                // indexed levels; elsewhere the vote would cost more than it saves
+                if (dense_l && wave_uniform(b, emit, b0)) {
                     if (lane == __ffsll((long long)am) - 1) atomicAdd(&hist[b0], __popcll(am));
                 } else if (emit) {
                     atomicAdd(&hist[b], 1);
@@ -380,7 +383,7 @@ constexpr size_t kScatterLds = 64 * 1024;
 // Dynamic LDS of the scatter pass, in ints.
 static size_t scatter_lds_bytes(int nb, int nbpl, int F)
 {
-    return sizeof(int) * ((size_t)3 * nb + (size_t)3 * nbpl + 8 + (size_t)kScatterBatch * (1 + F));
+    return sizeof(int) * ((size_t)2 * nb + (size_t)3 * nbpl + 8 + (size_t)kScatterBatch * (1 + F));
 }
 
 // Each (256-sample chunk, level) batch of items is counting-sorted by bin in
@@ -395,15 +398,13 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                                                           const float *__restrict__ dfeat,
                                                           const int32_t *__restrict__ offsets,
                                                           const int32_t *__restrict__ counts,
-                                                          uint32_t *__restrict__ items,
-                                                          uint32_t *__restrict__ binmax)
+                                                          uint32_t *__restrict__ items)
 {
     typedef typename Vec<F>::T VT;
     extern __shared__ int sm[];
     int *cursor = sm;                                   // [nb] next free item of this block's range
     int *cend = cursor + bp.nb;                         // [nb] end of this block's range
-    uint32_t *bmax = reinterpret_cast<uint32_t *>(cend + bp.nb);   // [nb] largest |v| as float bits
-    int *hcnt = reinterpret_cast<int *>(bmax + bp.nb);  // [nbpl] items of the batch per bin
+    int *hcnt = cend + bp.nb;                           // [nbpl] items of the batch per bin
     int *hoff = hcnt + bp.nbpl;                         // [nbpl] their start in the staging area
     int *gbase = hoff + bp.nbpl;                        // [nbpl] their first global slot (-1: dropped)
     int *wtot = gbase + bp.nbpl;                        // [8]
@@ -413,7 +414,6 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
         const int64_t i = (int64_t)b * gridDim.x + blockIdx.x;
         cursor[b] = offsets[i];
         cend[b] = offsets[i] + counts[i];
-        bmax[b] = 0u;
     }
     for (int b = threadIdx.x; b < bp.nbpl; b += blockDim.x) hcnt[b] = 0;
     __syncthreads();
@@ -436,6 +436,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
         const bool tile_ok = tile < g.K;
         for (int lr = 0; lr < bp.lg; ++lr) {
             const int l = bp.l0 + lr;
+            const bool dense_l = (g.dense_bits >> l) & 1u;
             bool act = valid && tile_ok;
             VT gv = {};
             if (act) {
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 const bool emit = merge_runs<F>(key[q], act, v[q]);
                 const int bl = (int)(key[q] >> bp.binshift);
                 int b0;
-                if (wave_uniform(bl, emit, b0)) {
+                if (dense_l && wave_uniform(bl, emit, b0)) {
                     const unsigned long long am = __ballot(emit);
                     const int leader = __ffsll((long long)am) - 1;
                     int r0 = 0;
@@ -504,39 +505,72 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 if (gb < 0) continue;
                 uint32_t *it = items + (int64_t)(gb + (j - hoff[bl])) * (1 + F);
                 it[0] = lbase + k;
-                float m = 0.0f;
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    const float u = sval[j * F + f];
-                    it[1 + f] = __float_as_uint(u);
-                    m = fmaxf(m, fabsf(u));
-                }
-                atomicMax(&bmax[lr * bp.nbpl + bl], __float_as_uint(m));   // non-negative floats order as uints
+                for (int f = 0; f < F; ++f) it[1 + f] = __float_as_uint(sval[j * F + f]);
             }
             __syncthreads();
         }
     }
-    for (int b = threadIdx.x; b < bp.nb; b += blockDim.x)
-        if (bmax[b]) atomicMax(&binmax[b], bmax[b]);
 }
 
-// Fixed-point exponent of a bin: every item is rounded to an int32 with
-// |q| < 2^30 (max|v| < 2^e, so v 2^(30-e) < 2^30); slot sums are int64 and
-// cannot overflow for fewer than 2^33 items per slot.
-__device__ __forceinline__ int bin_exponent(uint32_t maxbits)
+// Fixed-point exponent of a level from the bit pattern of its largest
+// |dfeat| (m < 2^e): a merged item is at most 64 m, so |v 2^(24-e)| < 2^30.
+__device__ __forceinline__ int level_exponent(uint32_t maxbits)
 {
-    if (maxbits == 0u) return 0;
+    if (maxbits == 0u || maxbits >= 0x7f800000u) return 0;
     int e;
-    frexpf(__uint_as_float(maxbits), &e);                 // max < 2^e
-    return 30 - e;
+    frexpf(__uint_as_float(maxbits), &e);
+    return 24 - e;
+}
+
+// lmax[l] = largest |dfeat[l][s][f]| over s < ne, as float bits (non-negative
+// floats order as unsigned integers).  Grid: (chunks, L).  A non-finite value
+// raises SNAKE_DEVERR_NONFINITE and its level contributes nothing.
+__global__ __launch_bounds__(256) void level_absmax_kernel(const float *__restrict__ dfeat, int64_t n,
+                                                           const int64_t *__restrict__ n_dev, int F,
+                                                           uint32_t *__restrict__ lmax, unsigned int *err)
+{
+    __shared__ uint32_t red[4];
+    const int l = blockIdx.y;
+    const int64_t cnt = effective_n(n, n_dev) * F;
+    const float *src = dfeat + (int64_t)l * n * F;
+    uint32_t m = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = __float_as_uint(src[i]) & 0x7fffffffu;
+        m = b > m ? b : m;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(m, d, 64);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;
+        if (m >= 0x7f800000u && err) atomicOr(err, (unsigned)SNAKE_DEVERR_NONFINITE);
+        if (m) atomicMax(&lmax[l], m);
+    }
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 template <int F>
-__global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, const int32_t *__restrict__ offsets,
+__global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32_t *__restrict__ offsets,
                                                          int nblk, const int64_t *__restrict__ n_items,
                                                          const uint32_t *__restrict__ items,
-                                                         const uint32_t *__restrict__ binmax,
-                                                         float *__restrict__ dtable)
+                                                         const uint32_t *__restrict__ lmax,
+                                                         unsigned long long *__restrict__ acc64)
 {
     __shared__ unsigned long long acc[kAccWords];
     const int64_t total = *n_items;
@@ -553,7 +587,12 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, cons
             const int64_t be = b + 1 < bp.nb ? (int64_t)offsets[(int64_t)(b + 1) * nblk] : total;
             const int64_t lo = bs > c0 ? bs : c0, hi = be < c1 ? be : c1;
             if (lo >= hi) continue;
-            const int E = bin_exponent(binmax[b]);
+            // the bin's first key: level and table position of slot 0
+            const uint32_t kbase = (uint32_t)b << bp.binshift;
+            const int lr = (int)(kbase >> bp.kt2_log2);
+            const uint32_t lm = lmax[bp.l0 + lr];
+            if (lm == 0u || lm >= 0x7f800000u) continue;        // block-uniform
+            const int E = level_exponent(lm);
             for (int e = threadIdx.x; e < slots * F; e += blockDim.x) acc[e] = 0ull;
             __syncthreads();
             // kRU items per thread per round keep enough loads in flight
@@ -579,41 +618,56 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, int L, cons
                 }
             }
             __syncthreads();
-            // the bin's first key: level and table position of slot 0
-            const uint32_t kbase = (uint32_t)b << bp.binshift;
-            const int lr = (int)(kbase >> bp.kt2_log2);
-            const uint32_t key0 = kbase & ((1u << bp.kt2_log2) - 1u);
-            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) {
-                const long long sv = (long long)acc[e];
-                if (sv != 0) {
-                    const uint32_t key = key0 + (uint32_t)(e / F);
-                    const int64_t tile = key >> bp.T_log2;
-                    const int64_t idx = key & ((1u << bp.T_log2) - 1u);
-                    unsafeAtomicAdd(dtable + ((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + (e % F),
-                                    (float)ldexp((double)sv, -E));
-                }
-            }
+            // exact: integer partial sums of several chunks add in any order
+            unsigned long long *dst = acc64 + ((int64_t)lr << bp.kt2_log2) * F + (int64_t)(kbase & ((1u << bp.kt2_log2) - 1u)) * F;
+            for (int e = threadIdx.x; e < slots * F; e += blockDim.x)
+                if (acc[e]) atomicAdd(dst + e, acc[e]);
             __syncthreads();
         }
+    }
+}
+
+// dtable += the pass's integer sums scaled back by 2^-E_l, one value per
+// table entry (the only floating-point rounding of the sum).
+template <int F>
+__global__ __launch_bounds__(256) void bin_convert_kernel(BinPlan bp, int L, const unsigned long long *__restrict__ acc64,
+                                                          const uint32_t *__restrict__ lmax, int K,
+                                                          float *__restrict__ dtable)
+{
+    const int64_t per_level = ((int64_t)K << bp.T_log2) * F;    // real (unpadded) keys
+    const int64_t total = per_level * bp.lg;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int lr = (int)(e / per_level);
+        const int64_t r = e - (int64_t)lr * per_level;              // key * F + f
+        const long long sv = (long long)acc64[((int64_t)lr << bp.kt2_log2) * F + r];
+        if (sv == 0) continue;
+        const int64_t key = r / F, f = r - key * F;
+        const int64_t tile = key >> bp.T_log2, idx = key & ((1ll << bp.T_log2) - 1);
+        const int E = level_exponent(lmax[bp.l0 + lr]);
+        dtable[((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + f] += (float)ldexp((double)sv, -E);
     }
 }
 
 struct BinWs {
     int32_t *counts, *offsets;
     int64_t *bsum, *n_items;
-    uint32_t *binmax;
+    uint32_t *lmax;
+    unsigned long long *acc64;
     uint32_t *items;
     int64_t item_cap;
 };
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace of a pass over lg levels for n samples.
-static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F)
+// Workspace of a pass over lg levels for n samples: counts, offsets, scan
+// sums, the item count, per-level maxima, the pass's integer accumulator
+// (lg x 2^kt2 x F int64) and the items.
+static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F, int kt2_log2)
 {
     const int64_t ncnt = (int64_t)nb * kBinBlocks;
-    return 2 * align256((size_t)ncnt * 4) + align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 +
-           align256((size_t)nb * 4) + align256((size_t)n * lg * 8 * (1 + F) * 4);
+    return align256((size_t)SNAKE_MAX_LEVELS * 4) + 2 * align256((size_t)ncnt * 4) +
+           align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 + align256(((size_t)lg << kt2_log2) * F * 8) +
+           align256((size_t)n * lg * 8 * (1 + F) * 4);
 }
 
 static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
@@ -712,7 +766,7 @@ size_t snake_hashgrid_bwd_workspace_bytes(const snake_grid_desc *gd, int32_t K, 
     if (make_grid(gd, K, g, __func__) || n < 0) return 0;
     const int lg = levels_per_pass < 1 ? 1 : (levels_per_pass > g.L ? g.L : levels_per_pass);
     const BinPlan bp = make_plan(g.L, gd->n_features, gd->log2_table, K, 0, lg);
-    return bin_ws_bytes(bp.nb, n, lg, gd->n_features);
+    return bin_ws_bytes(bp.nb, n, lg, gd->n_features, bp.kt2_log2);
 }
 
 int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, const uint8_t *tile_id,
@@ -759,19 +813,31 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, 0, cand);
         // item offsets are int32: a pass holds fewer than 2^31 items
         if (bp.nb <= kMaxBins && scatter_lds_bytes(bp.nb, bp.nbpl, F) <= kScatterLds &&
-            n * cand * 8 <= (int64_t)INT32_MAX && bin_ws_bytes(bp.nb, n, cand, F) <= workspace_bytes) {
+            n * cand * 8 <= (int64_t)INT32_MAX && bin_ws_bytes(bp.nb, n, cand, F, bp.kt2_log2) <= workspace_bytes) {
             lg = cand;
             break;
         }
     }
     SNAKE_REQUIRE(lg >= 1, SNAKE_ERR_WORKSPACE, "snake_hashgrid_bwd: workspace needs at least %zu bytes",
                   snake_hashgrid_bwd_workspace_bytes(gd, K, n, 1));
+    // per-level scale of the fixed-point sums, from the largest |dfeat|
+    uint32_t *lmax = static_cast<uint32_t *>(workspace);
+    unsigned int *err = device_error_word();
+    zero_u32_kernel<<<1, 64, 0, st>>>(lmax, g.L);
+    {
+        const int64_t vals = n * F;
+        unsigned gx = (unsigned)((vals + 255) / 256);
+        const unsigned cap_x = (unsigned)(num_cus() * 8 / g.L + 1);
+        gx = gx < 1 ? 1 : (gx > cap_x ? cap_x : gx);
+        level_absmax_kernel<<<dim3(gx, g.L), 256, 0, st>>>(dfeat, n, n_dev, F, lmax, err);
+    }
     for (int l0 = 0; l0 < g.L; l0 += lg) {
         const int lgp = l0 + lg <= g.L ? lg : g.L - l0;
         const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, l0, lgp);
         const int64_t ncnt = (int64_t)bp.nb * nblk;
-        char *p = static_cast<char *>(workspace);
+        char *p = static_cast<char *>(workspace) + align256((size_t)SNAKE_MAX_LEVELS * 4);
         BinWs w;
+        w.lmax = lmax;
         w.counts = reinterpret_cast<int32_t *>(p);
         p += align256((size_t)ncnt * 4);
         w.offsets = reinterpret_cast<int32_t *>(p);
@@ -780,21 +846,23 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         p += align256((size_t)scan::scan_blocks(ncnt) * 8);
         w.n_items = reinterpret_cast<int64_t *>(p);
         p += 256;
-        w.binmax = reinterpret_cast<uint32_t *>(p);
-        p += align256((size_t)bp.nb * 4);
+        const int64_t n_acc = ((int64_t)lgp << bp.kt2_log2) * F;
+        w.acc64 = reinterpret_cast<unsigned long long *>(p);
+        p += align256((size_t)n_acc * 8);
         w.items = reinterpret_cast<uint32_t *>(p);
         w.item_cap = n * lgp * 8;
         const int64_t chunks = (w.item_cap + kReduceChunk - 1) / kReduceChunk;
         const unsigned rgrid = (unsigned)(chunks < 4096 ? (chunks > 0 ? chunks : 1) : 4096);
-#define SNAKE_BIN_PASS(FF)                                                                               \
-    bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat,   \
-                                                     w.counts, w.binmax);                                 \
-    scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items,             \
-                      device_error_word(), st);                                                           \
-    bin_scatter_kernel<FF><<<nblk, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(              \
-        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.items, w.binmax);        \
-    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, g.L, w.offsets, nblk, w.n_items, w.items,     \
-                                                 w.binmax, dtable)
+        const unsigned zgrid = grid_for(n_acc, 256, 8);
+        const unsigned cgrid = grid_for(((int64_t)lgp * K << gd->log2_table) * F, 256, 8);
+#define SNAKE_BIN_PASS(FF)                                                                                 \
+    zero_u64_kernel<<<zgrid, 256, 0, st>>>(w.acc64, n_acc);                                                \
+    bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.counts); \
+    scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items, err, st);   \
+    bin_scatter_kernel<FF><<<nblk, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(                     \
+        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.items);                    \
+    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, w.offsets, nblk, w.n_items, w.items, w.lmax, w.acc64); \
+    bin_convert_kernel<FF><<<cgrid, 256, 0, st>>>(bp, g.L, w.acc64, w.lmax, K, dtable)
         if (F == 1) {
             SNAKE_BIN_PASS(1);
         } else if (F == 2) {

@@ -49,7 +49,8 @@ class TileNeRF:
     def __init__(self, *, res, n_features, log2_table, n_dir, colour_layers, colour_out,
                  boxes, zband=None, samples=64, early_stop=0.0, precision="fp32",
                  table=None, mlp_params=None, max_rays=4096, lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-15, hash_bwd="binned", hash_ws_gib=16.0, recompute=True, device="cuda"):
+                 eps=1e-15, hash_bwd="binned", hash_ws_gib=16.0, recompute=True, occ_grid=0,
+                 occ_decay=0.95, occ_threshold=0.01, device="cuda"):
         self.device = torch.device(device)
         self.res = [int(r) for r in res]
         self.F = int(n_features)
@@ -89,6 +90,19 @@ class TileNeRF:
         # adjoint reads them back instead of recomputing them
         self.recompute = bool(recompute)
         self.act = None
+        # occ_grid = G > 0: coarse occupancy grid of G^3 cells per tile; samples in
+        # unoccupied cells are culled after sampling (SAT-NGP procedure, Sec. 4.1)
+        self.G = int(occ_grid)
+        self.occ_decay, self.occ_threshold = float(occ_decay), float(occ_threshold)
+        if self.G:
+            nc = self.K * self.G ** 3
+            # start fully occupied: the density estimate decays towards what the
+            # networks report at the cell centres
+            self.occ_density = torch.full((nc,), 2.0 * self.occ_threshold + 1.0, device=self.device)
+            self.occ_bits = torch.full(((nc + 31) // 32,), -1, dtype=torch.int32, device=self.device)
+            self.occ_pos = torch.empty((nc, 3), device=self.device)
+            self.occ_tile = torch.empty(nc, dtype=torch.uint8, device=self.device) if self.K > 1 else None
+            L.snake_occupancy_cells(self.G, self.K, self.occ_pos, self.occ_tile)
         self.step_count = 0
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.R = 0
@@ -131,6 +145,16 @@ class TileNeRF:
                                   device=dev)
         if not self.recompute:
             self.act = torch.empty((cap, L.snake_mlp_act_width(self.mlp)), dtype=f32, device=dev)
+        if self.G:
+            # the sampler writes here; culling packs the kept samples into the
+            # arrays the rest of the step reads
+            self.raw = dict(packed_info=torch.zeros((R, 2), dtype=i32, device=dev),
+                            t0=torch.empty(cap, dtype=f32, device=dev), t1=torch.empty(cap, dtype=f32, device=dev),
+                            pos=torch.empty((cap, 3), dtype=f32, device=dev),
+                            ray_id=torch.empty(cap, dtype=i32, device=dev),
+                            tile_id=torch.empty(cap, dtype=torch.uint8, device=dev) if self.K > 1 else None,
+                            n=torch.zeros(1, dtype=i64, device=dev))
+            self.ws_cull = torch.empty(L.snake_cull_workspace_bytes(R), dtype=torch.uint8, device=dev)
         self.ws_hash = None
         if self.hash_bwd == "binned":
             # as many levels per pass as fit in the budget (at least one)
@@ -148,10 +172,38 @@ class TileNeRF:
     # -- stages ------------------------------------------------------------
     def sample(self, rays_o, rays_d, R, samples_per_ray=None, stream=None):
         self.R_cur = int(R)
-        L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S,
-                                 None, self.packed_info, self.t0, self.t1, self.pos, self.ray_id,
-                                 self.tile_id, self.view, self.cap, self.n_out, self.ws_sample,
-                                 stream)
+        if not self.G:
+            L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S,
+                                     None, self.packed_info, self.t0, self.t1, self.pos, self.ray_id,
+                                     self.tile_id, self.view, self.cap, self.n_out, self.ws_sample,
+                                     stream)
+            return
+        r = self.raw
+        L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S, None,
+                                 r["packed_info"], r["t0"], r["t1"], r["pos"], r["ray_id"], r["tile_id"], self.view,
+                                 self.cap, r["n"], self.ws_sample, stream)
+        L.snake_cull_samples(self.G, self.occ_bits, self.K, R, r["packed_info"], r["t0"], r["t1"], r["pos"],
+                             r["ray_id"], r["tile_id"], self.packed_info, self.t0, self.t1, self.pos, self.ray_id,
+                             self.tile_id, self.cap, self.n_out, self.ws_cull, stream)
+
+    def update_occupancy(self, stream=None):
+        """Evaluate the density at every cell centre with the current table and
+        networks and fold it into the grid's decaying maximum."""
+        nc = self.K * self.G ** 3
+        if not hasattr(self, "occ_feat"):
+            fdt = torch.bfloat16 if self.feat_dtype == L.SNAKE_BF16 else torch.float32
+            self.occ_feat = torch.empty((len(self.res), nc, self.F), dtype=fdt, device=self.device)
+            self.occ_sigma = torch.empty(nc, device=self.device)
+            self.occ_rgb = torch.empty((nc, 3), device=self.device)
+            self.occ_view = torch.tensor([[0.0, 0.0, -1.0]], device=self.device)
+            self.occ_sun = torch.tensor([[0.0, 0.0, 1.0]], device=self.device)
+            self.occ_ray = torch.zeros(nc, dtype=torch.int32, device=self.device)
+        L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.occ_pos, self.occ_tile, None, nc, None,
+                             self.occ_feat, None, stream)
+        L.snake_mlp_fwd(self.mlp, self.params, self.occ_feat, self.occ_view, self.occ_sun, self.occ_ray, 1, None,
+                        nc, None, self.occ_sigma, self.occ_rgb, stream=stream)
+        L.snake_occupancy_update(self.occ_sigma, nc, self.occ_decay, self.occ_threshold, self.occ_density,
+                                 self.occ_bits, stream)
 
     def field_fwd(self, sun=None, stream=None):
         L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.pos, self.tile_id, None, self.cap,

@@ -68,7 +68,9 @@ class WindowNeRF:
         self.m_w, self.v_w, self.g_w = (torch.zeros_like(self.params) for _ in range(3))
         self.lr, (self.b1, self.b2), self.eps = float(lr), betas, float(eps)
         self.lr_colour = self.lr if lr_colour is None else float(lr_colour)
-        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        # Adam step of each tile (its own optimiser state travels with it when
+        # the window slides), and of the shared colour net at index K
+        self.step_dev = torch.zeros(self.K + 1, dtype=torch.int32, device=dev)
         self.hash_ws_gib = float(hash_ws_gib)
         self.graph = None
         self._alloc(int(max_rays), int(max_samples) if max_samples else int(max_rays) * self.S)
@@ -175,17 +177,55 @@ class WindowNeRF:
         if not update:
             return
         L.snake_counter_add(self.step_dev, 1, stream=stream)
-        L.snake_adam_step(self.table, self.g_t, self.m_t, self.v_t, self.table.numel(), self.lr, self.b1,
-                          self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
-                          stream=stream)
-        # the networks: per-tile sets, or the density sets and the shared colour
-        # net as two optimisers (each may have its own learning rate)
-        nd = self.K * self.Pd if self.shared_colour else self.n_w
-        parts = [(0, nd, self.lr)] + ([(nd, self.n_w - nd, self.lr_colour)] if self.shared_colour else [])
-        for off, cnt, lr in parts:
-            L.snake_adam_step(self.params[off:], self.g_w[off:], self.m_w[off:], self.v_w[off:], cnt, lr,
-                              self.b1, self.b2, self.eps, 0, 0.0, L.SNAKE_ADAM_ZERO_GRAD, step_dev=self.step_dev,
-                              stream=stream)
+        self.adam(stream)
+
+    def adam(self, stream=None):
+        """Adam per tile (table and networks of tile k use step counter k) and,
+        with a shared colour net, for the colour net (counter K)."""
+        per_t = self.Lv * (1 << self.log2T) * self.F
+        per_w = self.Pd if self.shared_colour else self.P
+        flags = L.SNAKE_ADAM_ZERO_GRAD
+        for k in range(self.K):
+            sd = self.step_dev[k:k + 1]
+            a, b = k * per_t, k * per_w
+            L.snake_adam_step(self.table.view(-1)[a:], self.g_t.view(-1)[a:], self.m_t.view(-1)[a:],
+                              self.v_t.view(-1)[a:], per_t, self.lr, self.b1, self.b2, self.eps, 0, 0.0, flags,
+                              step_dev=sd, stream=stream)
+            L.snake_adam_step(self.params[b:], self.g_w[b:], self.m_w[b:], self.v_w[b:], per_w, self.lr, self.b1,
+                              self.b2, self.eps, 0, 0.0, flags, step_dev=sd, stream=stream)
+        if self.shared_colour:
+            c = self.K * self.Pd
+            L.snake_adam_step(self.params[c:], self.g_w[c:], self.m_w[c:], self.v_w[c:], self.n_w - c,
+                              self.lr_colour, self.b1, self.b2, self.eps, 0, 0.0, flags,
+                              step_dev=self.step_dev[self.K:], stream=stream)
+
+    # -- rendering ---------------------------------------------------------
+    def render_depth(self, rays_o, rays_d, samples_per_ray=None, sun=None, stream=None):
+        """Forward-only pass (sampler, partition, encoding, networks,
+        quadrature) over any number of rays, in batches of the buffer size;
+        returns the expected depth t of each ray (device FP32)."""
+        N = int(rays_o.shape[0])
+        depth = torch.empty(N, dtype=torch.float32, device=self.device)
+        cap, K = self.cap, self.K
+        for b0 in range(0, N, self.R):
+            b1 = min(N, b0 + self.R)
+            R = b1 - b0
+            spr = None if samples_per_ray is None else samples_per_ray[b0:b1]
+            L.snake_sample_segmented(rays_o[b0:b1], rays_d[b0:b1], R, self.boxes, self.zband, spr, self.S, None,
+                                     self.packed_info, self.t0, self.t1, self.pos, self.ray_id, self.tile_id,
+                                     self.view, cap, self.n_out, self.ws_sample, stream)
+            L.snake_tile_partition(self.tile_id, self.pos, self.ray_id, cap, self.n_out, K, self.perm, self.inv,
+                                   self.tile_start, self.pos_s, self.tile_s, self.ray_s, self.ws_part, stream)
+            L.snake_hashgrid_fwd(self.grid, K, self.table, self.pos_s, self.tile_s, None, cap, self.n_out,
+                                 self.feat, None, stream)
+            L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, None if sun is None else sun[b0:b1],
+                            self.ray_s, R, None, cap, self.n_out, self.sigma, self.rgb, K=K,
+                            tile_start=self.tile_start, stream=stream)
+            L.snake_composite_fwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R, self.early_stop,
+                                  None, 0.0, self.rgb_out, self.opacity, self.depth, self.n_alive, None,
+                                  sample_map=self.inv, stream=stream)
+            depth[b0:b1].copy_(self.depth[:R])
+        return depth
 
     # -- HIP graph ---------------------------------------------------------
     def capture(self, rays_o, rays_d, target, samples_per_ray=None, sun=None, warmup=1):

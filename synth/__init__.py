@@ -32,7 +32,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "GridConfig", "MlpConfig", "Workload", "tiny_tile", "full_tile", "window_2x2",
+    "GridConfig", "MlpConfig", "Workload", "tiny_tile", "full_tile", "window_2x2", "window_rays",
     "init_table", "init_mlp", "mlp_param_shapes", "Heightfield",
 ]
 
@@ -335,3 +335,21 @@ def window_2x2(seed: int = 0, rays_per_tile=None, n_views: int = 8, image_px: in
     wl.rays_per_tile = rays_per_tile
     wl.view_dirs = dirs
     return wl
+
+
+def window_rays(seed: int, n_rays: int, max_off_nadir_deg: float = 10.0, margin: float = 0.3,
+                spr_range=(8, 128)):
+    """Rays of one 2x2 window in its local frame ([0,2]^2 x [0,1]): ground
+    points uniform in [margin, 2-margin]^2 at z = 0.5, off-nadir at most
+    max_off_nadir_deg (with the defaults every ray's chord through the band
+    stays inside the window), origins on z = 2, budgets uniform in spr_range,
+    uniform RGB targets.  Returns (rays_o, rays_d, target, samples_per_ray)."""
+    rng = np.random.default_rng(seed)
+    th = np.deg2rad(rng.uniform(0.0, max_off_nadir_deg, size=n_rays))
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n_rays)
+    d = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), -np.cos(th)], axis=1)
+    g = np.concatenate([rng.uniform(margin, 2.0 - margin, size=(n_rays, 2)), np.full((n_rays, 1), 0.5)], 1)
+    o = g - ((2.0 - 0.5) / np.cos(th))[:, None] * d
+    spr = rng.integers(spr_range[0], spr_range[1] + 1, size=n_rays).astype(np.int32)
+    target = rng.uniform(0.0, 1.0, size=(n_rays, 3)).astype(np.float32)
+    return o, d, target, spr

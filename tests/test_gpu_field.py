@@ -378,3 +378,34 @@ def test_mlp_per_tile_weights(L, orc, name, shared):
     assert bounds[3] == bounds[2]
     if shared:
         assert_grad(g_all[K * Pd:], r_col, 1e-4, "shared colour dW")
+
+
+def test_hashgrid_bwd_binned_is_deterministic(L, orc):
+    """The binned adjoint sums in exact fixed point, so the grid shape and the
+    number of levels per pass change nothing: the same bits every time.  Its
+    rounding stays within the oracle bound."""
+    rng = np.random.default_rng(19)
+    n = 200_003
+    c, res, table = _grid_setup(L, orc, "full", rng)
+    pos = _positions(rng, n)
+    dfeat = (rng.normal(size=(n, 32)) * rng.uniform(0, 3, size=(n, 1))).astype(np.float32)
+    g = L.grid_desc(res, 2, c["log2T"])
+    dfd = dev(dfeat.reshape(n, 16, 2).transpose(1, 0, 2))
+    ws = torch.empty(L.snake_hashgrid_bwd_workspace_bytes(g, 1, n, 16), dtype=torch.uint8, device=DEV)
+    saved = {k: L.snake_tune_get(k) for k in ("bin_blocks", "bin_levels_per_pass")}
+    outs = []
+    try:
+        for blocks, lg in ((1024, 0), (256, 0), (512, 3), (64, 1)):
+            L.snake_tune_set("bin_blocks", blocks)
+            L.snake_tune_set("bin_levels_per_pass", lg)
+            dtab = torch.zeros(table.shape, device=DEV)
+            L.snake_hashgrid_bwd(g, 1, dev(pos), None, None, n, None, dfd, dtab, ws)
+            outs.append(dtab)
+        sync()
+    finally:
+        for k, v in saved.items():
+            L.snake_tune_set(k, v)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    ref = orc.hashgrid_bwd(res, c["log2T"], table.shape, pos, dfeat.astype(np.float64))
+    assert_grad(host(outs[0]), ref, 1e-4, "dtable")

@@ -1,0 +1,78 @@
+"""Coarse occupancy grid and culling (SAT-NGP procedure, Sec. 4.1) on the GPU
+against the oracle: cell centres, the decaying-maximum update and the culled
+sample packing bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from _helpers import DEV, dev, host, sync
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_01631_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def test_cells_and_update(L, orc):
+    G, K = 32, 3
+    n = K * G ** 3
+    pos = torch.empty((n, 3), device=DEV)
+    tid = torch.empty(n, dtype=torch.uint8, device=DEV)
+    L.snake_occupancy_cells(G, K, pos, tid)
+    sync()
+    rp, rt = orc.occupancy_cell_centres(G, K)
+    assert np.array_equal(host(pos), rp) and np.array_equal(host(tid), rt)
+    rng = np.random.default_rng(5)
+    dens = rng.uniform(0, 2, size=n).astype(np.float32)
+    sig = rng.exponential(0.5, size=n).astype(np.float32)
+    d, bits = dev(dens), torch.zeros((n + 31) // 32, dtype=torch.int32, device=DEV)
+    L.snake_occupancy_update(dev(sig), n, 0.95, 0.8, d, bits)
+    sync()
+    ref = np.maximum(dens * np.float32(0.95), sig)             # FP32, as the kernel
+    assert np.array_equal(host(d), ref)
+    b = host(bits).view(np.uint32)
+    got = ((b[np.arange(n) >> 5] >> (np.arange(n) & 31)) & 1).astype(bool)
+    assert np.array_equal(got, ref > np.float32(0.8))
+
+
+@pytest.mark.parametrize("K", [1, 4])
+def test_cull_matches_oracle(L, orc, K):
+    G = 64
+    if K == 1:
+        w = synth.tiny_tile(seed=4, n_rays=3000, samples=64)
+        boxes = w.boxes
+        spr = None
+        S = 64
+    else:
+        w = synth.window_2x2(seed=4, rays_per_tile=[800, 700, 900, 600])
+        boxes = w.boxes
+        spr = w.samples_per_ray
+        S = 0
+    smp = orc.sample_segmented(w.rays_o, w.rays_d, boxes, S, samples_per_ray=spr)
+    rng = np.random.default_rng(9)
+    occ = rng.random(K * G ** 3) < 0.35
+    bits = np.packbits(occ.reshape(-1, 8)[:, ::-1], axis=1).reshape(-1)      # bit c % 8 of byte c / 8
+    words = torch.from_numpy(np.pad(bits, (0, (-bits.size) % 4)).view(np.int32).copy()).to(DEV)
+    n, R = smp["n"], w.n_rays
+    o = dict(info=torch.zeros((R, 2), dtype=torch.int32, device=DEV), t0=torch.zeros(n, device=DEV),
+             t1=torch.zeros(n, device=DEV), pos=torch.zeros((n, 3), device=DEV),
+             rid=torch.zeros(n, dtype=torch.int32, device=DEV), tid=torch.zeros(n, dtype=torch.uint8, device=DEV),
+             n=torch.zeros(1, dtype=torch.int64, device=DEV))
+    ws = torch.empty(L.snake_cull_workspace_bytes(R), dtype=torch.uint8, device=DEV)
+    L.snake_cull_samples(G, words, K, R, dev(smp["packed_info"], torch.int32), dev(smp["t0"]), dev(smp["t1"]),
+                         dev(smp["pos"]), dev(smp["ray_id"]), dev(smp["tile_id"]) if K > 1 else None,
+                         o["info"], o["t0"], o["t1"], o["pos"], o["rid"], o["tid"] if K > 1 else None, n, o["n"], ws)
+    sync()
+    ref = orc.cull_samples(smp, occ, G)
+    m = ref["n"]
+    assert int(o["n"].item()) == m and 0 < m < n
+    assert np.array_equal(host(o["info"]), ref["packed_info"])
+    for k, key in (("t0", "t0"), ("t1", "t1"), ("pos", "pos"), ("rid", "ray_id")):
+        assert np.array_equal(host(o[k])[:m], ref[key]), k
+    if K > 1:
+        assert np.array_equal(host(o["tid"])[:m], ref["tile_id"])

@@ -14,18 +14,22 @@ from _helpers import DEV, assert_grad, assert_values, dev, host, sync
 pytestmark = pytest.mark.gpu
 
 
-def make_nerf(w, precision="fp32", max_rays=None):
+def make_nerf(w, precision="fp32", max_rays=None, occ_grid=0):
     from paper_2507_01631_amd import TileNeRF, level_resolutions
     g, m = w.grid, w.mlp
     return TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
                     log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
                     colour_out=m.colour_out, boxes=w.boxes, zband=w.zband, samples=w.samples_per_ray,
                     early_stop=w.early_stop, precision=precision, table=w.table, mlp_params=w.mlp_params,
-                    max_rays=max_rays or w.n_rays, lr=w.lr, device=DEV)
+                    max_rays=max_rays or w.n_rays, lr=w.lr, occ_grid=occ_grid, device=DEV)
 
 
-def gpu_step(w, precision="fp32"):
-    nerf = make_nerf(w, precision)
+def gpu_step(w, precision="fp32", occupancy=None):
+    nerf = make_nerf(w, precision, occ_grid=occupancy[0] if occupancy else 0)
+    if occupancy:
+        occ = occupancy[1]
+        by = np.packbits(occ.reshape(-1, 8)[:, ::-1], axis=1).reshape(-1)
+        nerf.occ_bits.copy_(torch.from_numpy(by.view(np.int32).copy()))
     ro, rd, tg = dev(w.rays_o), dev(w.rays_d), dev(w.target)
     sun = dev(w.sun) if w.sun is not None else None
     # keep the gradients: run the step by stages and copy before Adam
@@ -238,3 +242,34 @@ def test_full_size_sampled(orc, prec):
         ref = d.sum(0)
         tol = 2e-3 * ref.abs() + 1e-6 * d.abs().sum(0)
         assert bool(((got - ref).abs() <= tol).all()), (lvl, host(got), host(ref))
+
+
+def test_tiny_tile_step_with_occupancy_culling(orc):
+    """Samples in unoccupied cells of a 32^3 grid are culled before the field:
+    the whole FP32 step matches the oracle step that culls with the same grid."""
+    w = synth.tiny_tile(seed=7)
+    G = 32
+    rng = np.random.default_rng(31)
+    occ = rng.random(G ** 3) < 0.5
+    g = gpu_step(w, "fp32", occupancy=(G, occ))
+    o = orc.train_step(w, occupancy=(G, occ))
+    assert 0 < o["sample"]["n"] < o["sample_raw"]["n"]
+    check_step(g, o, "fp32", w, orc)
+
+
+def test_occupancy_update_from_the_field(orc):
+    """update_occupancy evaluates the density networks at the cell centres:
+    the decayed maxima match the oracle's sigma there (FP32 tolerance)."""
+    w = synth.tiny_tile(seed=8)
+    G = 16
+    nerf = make_nerf(w, "fp32", occ_grid=G)
+    nerf.update_occupancy()
+    nerf.update_occupancy()
+    sync()
+    pos, _ = orc.occupancy_cell_centres(G)
+    feat = orc.hashgrid_fwd(orc.level_resolutions(8, 16, 256), 14, w.table, pos)
+    sig, _ = orc.mlp_fwd(w.mlp, w.mlp_params, feat, np.array([[0.0, 0.0, -1.0]], np.float32),
+                         np.zeros(G ** 3, np.int32))
+    init = 2.0 * 0.01 + 1.0
+    ref = np.maximum(np.maximum(init * 0.95, sig) * 0.95, sig)
+    assert_values(host(nerf.occ_density), ref, 1e-5, 1e-7, "occupancy density")

@@ -767,3 +767,39 @@ def test_train_step_shared_colour_net(orc):
     assert np.array_equal(shared["dW"][:4 * Pd], dWt[:, :Pd].ravel())
     assert np.allclose(shared["dW"][4 * Pd:], dWt[:, Pd:].sum(0), rtol=1e-13, atol=1e-20)
     assert shared["mlp_new"].size == 4 * Pd + W.shape[1] - Pd
+
+
+def test_occupancy_cells_and_culling(orc):
+    """Cell lookup: every cell centre maps to its own cell; x = 1 lands in the
+    last cell.  Culling with every cell occupied is the identity; with none
+    occupied it removes every sample; culling keeps each ray's kept samples in
+    t order and a culled ray's composite equals the composite of its kept
+    intervals (empty cells add no optical depth)."""
+    G = 16
+    c, t = orc.occupancy_cell_centres(G, K=2)
+    assert np.array_equal(orc.occupancy_cell(c[:G ** 3], G), np.arange(G ** 3))
+    assert orc.occupancy_cell(np.array([[1.0, 1.0, 1.0]]), G)[0] == G ** 3 - 1
+    assert orc.occupancy_cell(np.array([[0.0, 0.5, 0.999]]), G)[0] == (0 * G + 8) * G + 15
+    w = synth.tiny_tile(seed=11, n_rays=200, samples=40)
+    smp = orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 40)
+    allon = orc.cull_samples(smp, np.ones(G ** 3, dtype=bool), G)
+    assert allon["n"] == smp["n"] and np.array_equal(allon["packed_info"], smp["packed_info"])
+    assert orc.cull_samples(smp, np.zeros(G ** 3, dtype=bool), G)["n"] == 0
+    rng = np.random.default_rng(12)
+    occ = rng.random(G ** 3) < 0.4
+    cu = orc.cull_samples(smp, occ, G)
+    assert 0 < cu["n"] < smp["n"]
+    for r in range(200):
+        s, n = cu["packed_info"][r]
+        assert np.all(np.diff(cu["t0"][s:s + n]) > 0) and np.all(cu["ray_id"][s:s + n] == r)
+    # density zero where culled: compositing all samples with sigma = 0 in
+    # empty cells equals compositing the kept samples alone
+    sig = rng.uniform(0.0, 5.0, size=smp["n"])
+    rgb = rng.uniform(0.0, 1.0, size=(smp["n"], 3))
+    keep = cu["keep"]
+    full = orc.composite_fwd(smp["packed_info"], np.where(keep, sig, 0.0), rgb, smp["t0"], smp["t1"])
+    kept = orc.composite_fwd(cu["packed_info"], sig[keep], rgb[keep], cu["t0"], cu["t1"])
+    assert np.allclose(full["rgb"], kept["rgb"], rtol=1e-13, atol=1e-15)
+    assert np.allclose(full["opacity"], kept["opacity"], rtol=1e-13, atol=1e-15)
+    d, o = orc.occupancy_update(np.full(4, 1.0), np.array([0.0, 0.5, 2.0, 0.96]), 0.95, 0.96)
+    assert np.allclose(d, [0.95, 0.95, 2.0, 0.96]) and o.tolist() == [False, False, True, False]
