@@ -247,13 +247,31 @@ __device__ __forceinline__ bool grad_nonzero(const typename Vec<F>::T &gv)
     return any;
 }
 
+// Fixed-point exponent of a level from the bit pattern of its largest
+// |dfeat| (m < 2^e): a contribution w g (w <= 1) becomes the integer
+// rint(w g 2^(24-e)), |q| <= 2^24, and a merged run of at most 64 of them
+// stays below 2^30.
+__device__ __forceinline__ int level_exponent(uint32_t maxbits)
+{
+    if (maxbits == 0u || maxbits >= 0x7f800000u) return 0;
+    int e;
+    frexpf(__uint_as_float(maxbits), &e);
+    return 24 - e;
+}
+
+// A level takes part when it has a nonzero, finite largest gradient.
+__device__ __forceinline__ bool level_ok(uint32_t maxbits) { return maxbits != 0u && maxbits < 0x7f800000u; }
+
+__device__ __forceinline__ int32_t quantise(float v, int E) { return (int32_t)rintf(ldexpf(v, E)); }
+
 // Consecutive lanes (consecutive samples of a ray) often hit the same slot on
 // coarse levels.  Sum each run of equal keys across the wavefront (segmented
 // inclusive scan) so only the run's last lane emits an item.  Returns whether
-// this lane emits; v holds the run total there.  Count and scatter call it
-// identically, so they see the same items.
+// this lane emits; v holds the run total there.  The values are already
+// integers (fixed point), so merging only regroups exact sums and the result
+// does not depend on which lanes happened to share a wavefront.
 template <int F>
-__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, float (&v)[F])
+__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, int32_t (&v)[F])
 {
     const int lane = lane_id();
     const uint32_t pk = __shfl_up(key, 1, 64);
@@ -273,12 +291,26 @@ __device__ __forceinline__ bool merge_runs(uint32_t key, bool act, float (&v)[F]
     for (int d = 1; d < 64; d <<= 1) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            const float u = __shfl_up(v[f], d, 64);
+            const int32_t u = __shfl_up(v[f], d, 64);
             if (lane - d >= rs) v[f] += u;
         }
     }
     return tail;
 }
+
+// The lane that emits a run's item (its last lane); the same decision as
+// merge_runs, without the sums (the count pass needs only how many items).
+__device__ __forceinline__ bool run_tail(uint32_t key, bool act)
+{
+    const int lane = lane_id();
+    const uint32_t nk = __shfl_down(key, 1, 64);
+    const bool na = __shfl_down(act ? 1 : 0, 1, 64) != 0;
+    return act && (lane == 63 || !na || nk != key);
+}
+
+// Runs of equal slots along a ray are worth merging only where cells are
+// large against the sample spacing; on finer levels every item is emitted.
+constexpr int kMergeMaxRes = 512;
 
 template <int F>
 __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
@@ -286,6 +318,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
                                                         const int32_t *__restrict__ sidx, int64_t n,
                                                         const int64_t *__restrict__ n_dev,
                                                         const float *__restrict__ dfeat,
+                                                        const uint32_t *__restrict__ lmax,
                                                         int32_t *__restrict__ counts)
 {
     typedef typename Vec<F>::T VT;
@@ -312,7 +345,8 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
         for (int lr = 0; lr < bp.lg; ++lr) {
             const int l = bp.l0 + lr;
             const bool dense_l = (g.dense_bits >> l) & 1u;
-            bool act = valid && tile_ok;
+            const bool merge_l = g.res[l] <= kMergeMaxRes;
+            bool act = valid && tile_ok && level_ok(lmax[l]);
             if (act) act = grad_nonzero<F>(*reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F));
             uint32_t idx[8];
             float wt[8];
@@ -320,10 +354,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
-                float v[F];
-#pragma unroll
-                for (int f = 0; f < F; ++f) v[f] = 0.0f;
-                const bool emit = merge_runs<F>(key, act, v);
+                const bool emit = merge_l ? run_tail(key, act) : act;
                 const int b = lr * bp.nbpl + (int)(key >> bp.binshift);
                 int b0;
                 // the vote must run on every lane: inside the leader's branch
@@ -398,6 +429,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                                                           const float *__restrict__ dfeat,
                                                           const int32_t *__restrict__ offsets,
                                                           const int32_t *__restrict__ counts,
+                                                          const uint32_t *__restrict__ lmax,
                                                           uint32_t *__restrict__ items)
 {
     typedef typename Vec<F>::T VT;
@@ -409,7 +441,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
     int *gbase = hoff + bp.nbpl;                        // [nbpl] their first global slot (-1: dropped)
     int *wtot = gbase + bp.nbpl;                        // [8]
     uint32_t *skey = reinterpret_cast<uint32_t *>(wtot + 8);        // [batch]
-    float *sval = reinterpret_cast<float *>(skey + kScatterBatch);  // [batch][F]
+    int32_t *sval = reinterpret_cast<int32_t *>(skey + kScatterBatch);  // [batch][F]
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) {
         const int64_t i = (int64_t)b * gridDim.x + blockIdx.x;
         cursor[b] = offsets[i];
@@ -437,7 +469,10 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
         for (int lr = 0; lr < bp.lg; ++lr) {
             const int l = bp.l0 + lr;
             const bool dense_l = (g.dense_bits >> l) & 1u;
-            bool act = valid && tile_ok;
+            const bool merge_l = g.res[l] <= kMergeMaxRes;
+            const uint32_t lm = lmax[l];
+            const int E = level_exponent(lm);
+            bool act = valid && tile_ok && level_ok(lm);
             VT gv = {};
             if (act) {
                 gv = *reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F);
@@ -449,13 +484,13 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             // 1. rank every emitted item within its bin for this batch
             uint32_t key[8];
             int rank[8];
-            float v[8][F];
+            int32_t v[8][F];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 key[q] = ((uint32_t)tile << bp.T_log2) + idx[q];
 #pragma unroll
-                for (int f = 0; f < F; ++f) v[q][f] = wt[q] * Vec<F>::get(gv, f);
-                const bool emit = merge_runs<F>(key[q], act, v[q]);
+                for (int f = 0; f < F; ++f) v[q][f] = quantise(wt[q] * Vec<F>::get(gv, f), E);
+                const bool emit = merge_l ? merge_runs<F>(key[q], act, v[q]) : act;
                 const int bl = (int)(key[q] >> bp.binshift);
                 int b0;
                 if (dense_l && wave_uniform(bl, emit, b0)) {
@@ -506,22 +541,14 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 uint32_t *it = items + (int64_t)(gb + (j - hoff[bl])) * (1 + F);
                 it[0] = lbase + k;
 #pragma unroll
-                for (int f = 0; f < F; ++f) it[1 + f] = __float_as_uint(sval[j * F + f]);
+                for (int f = 0; f < F; ++f) it[1 + f] = (uint32_t)sval[j * F + f];
             }
             __syncthreads();
         }
     }
 }
 
-// Fixed-point exponent of a level from the bit pattern of its largest
-// |dfeat| (m < 2^e): a merged item is at most 64 m, so |v 2^(24-e)| < 2^30.
-__device__ __forceinline__ int level_exponent(uint32_t maxbits)
-{
-    if (maxbits == 0u || maxbits >= 0x7f800000u) return 0;
-    int e;
-    frexpf(__uint_as_float(maxbits), &e);
-    return 24 - e;
-}
+
 
 // lmax[l] = largest |dfeat[l][s][f]| over s < ne, as float bits (non-negative
 // floats order as unsigned integers).  Grid: (chunks, L).  A non-finite value
@@ -535,9 +562,17 @@ __global__ __launch_bounds__(256) void level_absmax_kernel(const float *__restri
     const int64_t cnt = effective_n(n, n_dev) * F;
     const float *src = dfeat + (int64_t)l * n * F;
     uint32_t m = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t b = __float_as_uint(src[i]) & 0x7fffffffu;
-        m = b > m ? b : m;
+    // eight independent loads in flight per thread
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < cnt; i0 += 8 * stride) {
+        uint32_t b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + u * stride;
+            b[u] = i < cnt ? (__float_as_uint(src[i]) & 0x7fffffffu) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m = b[u] > m ? b[u] : m;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -590,9 +625,7 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32
             // the bin's first key: level and table position of slot 0
             const uint32_t kbase = (uint32_t)b << bp.binshift;
             const int lr = (int)(kbase >> bp.kt2_log2);
-            const uint32_t lm = lmax[bp.l0 + lr];
-            if (lm == 0u || lm >= 0x7f800000u) continue;        // block-uniform
-            const int E = level_exponent(lm);
+            if (!level_ok(lmax[bp.l0 + lr])) continue;          // block-uniform
             for (int e = threadIdx.x; e < slots * F; e += blockDim.x) acc[e] = 0ull;
             __syncthreads();
             // kRU items per thread per round keep enough loads in flight
@@ -610,10 +643,9 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32
                 for (int u = 0; u < kRU; ++u) {
                     if (i0 + (int64_t)u * blockDim.x < hi) {
 #pragma unroll
-                        for (int f = 0; f < F; ++f) {
-                            const int qv = (int)rintf(ldexpf(__uint_as_float(w[u][1 + f]), E));
-                            atomicAdd(&acc[(w[u][0] & smask) * F + f], (unsigned long long)(long long)qv);
-                        }
+                        for (int f = 0; f < F; ++f)
+                            atomicAdd(&acc[(w[u][0] & smask) * F + f],
+                                      (unsigned long long)(long long)(int32_t)w[u][1 + f]);
                     }
                 }
             }
@@ -826,8 +858,8 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     zero_u32_kernel<<<1, 64, 0, st>>>(lmax, g.L);
     {
         const int64_t vals = n * F;
-        unsigned gx = (unsigned)((vals + 255) / 256);
-        const unsigned cap_x = (unsigned)(num_cus() * 8 / g.L + 1);
+        unsigned gx = (unsigned)((vals + 256 * 8 - 1) / (256 * 8));
+        const unsigned cap_x = (unsigned)(num_cus() * 16 / g.L + 1);
         gx = gx < 1 ? 1 : (gx > cap_x ? cap_x : gx);
         level_absmax_kernel<<<dim3(gx, g.L), 256, 0, st>>>(dfeat, n, n_dev, F, lmax, err);
     }
@@ -857,10 +889,11 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         const unsigned cgrid = grid_for(((int64_t)lgp * K << gd->log2_table) * F, 256, 8);
 #define SNAKE_BIN_PASS(FF)                                                                                 \
     zero_u64_kernel<<<zgrid, 256, 0, st>>>(w.acc64, n_acc);                                                \
-    bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.counts); \
+    bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.lmax,     \
+                                               w.counts);                                                  \
     scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items, err, st);   \
     bin_scatter_kernel<FF><<<nblk, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(                     \
-        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.items);                    \
+        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.lmax, w.items);            \
     bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, w.offsets, nblk, w.n_items, w.items, w.lmax, w.acc64); \
     bin_convert_kernel<FF><<<cgrid, 256, 0, st>>>(bp, g.L, w.acc64, w.lmax, K, dtable)
         if (F == 1) {

@@ -33,6 +33,7 @@ import numpy as np
 
 __all__ = [
     "GridConfig", "MlpConfig", "Workload", "tiny_tile", "full_tile", "window_2x2", "window_rays",
+    "full_tile_heldout",
     "init_table", "init_mlp", "mlp_param_shapes", "Heightfield",
 ]
 
@@ -353,3 +354,21 @@ def window_rays(seed: int, n_rays: int, max_off_nadir_deg: float = 10.0, margin:
     spr = rng.integers(spr_range[0], spr_range[1] + 1, size=n_rays).astype(np.int32)
     target = rng.uniform(0.0, 1.0, size=(n_rays, 3)).astype(np.float32)
     return o, d, target, spr
+
+
+def full_tile_heldout(wl: Workload, n_px: int = 256):
+    """Rays and rendered targets of the held-out ninth view of a full_tile
+    workload on an n_px x n_px pixel grid over the tile (pixel centres), with
+    that view's sun.  Returns (rays_o, rays_d, target, sun)."""
+    d = wl.view_dirs[-1]
+    sun = wl.sun_dirs[-1]
+    ax = (np.arange(n_px) + 0.5) / n_px
+    X, Y = np.meshgrid(ax, ax, indexing="ij")
+    g = np.stack([X.ravel(), Y.ravel(), np.full(X.size, 0.5)], 1)
+    s = (1.0 - 0.5) / (-d[2])
+    o = g - s * d[None, :]
+    o[:, 2] = 1.0
+    dd = np.repeat(d[None, :], o.shape[0], 0)
+    su = np.repeat(sun[None, :], o.shape[0], 0)
+    target = wl.scene.render(o, dd, su).astype(np.float32)
+    return o, dd, target, su.astype(np.float32)
