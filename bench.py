@@ -6,7 +6,7 @@ reported value) beside the FP32 form, with the dominant kernel's fraction of
 its roofline.  A "step" is one pass of the whole path over one batch of rays:
 segmented sampling -> hash encoding -> density/colour MLP -> volume rendering
 + MSE loss -> composite adjoint -> MLP adjoint (recomputed activations) ->
-hash-table scatter (FP32 atomics) -> Adam on the table and the MLP.
+binned fixed-point hash-table adjoint -> Adam on the table and the MLP.
 
 Workload (full-size single tile): hash grid L=16, F=2, T=2^19, resolutions
 16 -> 2048; density MLP 32->64->16, colour MLP 21->64->64->4; 2^18 rays per
@@ -31,8 +31,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm": 8.0e12, "bf16": 2.5e15, "fp32": 157.3e12}
+# Measured HBM bytes of one call of the table adjoint at this workload (BF16
+# form, 2^18 rays): FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter runs,
+# each scaled by what the same counter reads for a 256 MiB device copy.  Valid
+# only for the kernel sources the counters were taken on (their sha256); any
+# other source reports the traffic as unknown.
+ADJOINT_TRAFFIC = {"bytes": 91864980877,
+                   "sha256": "bdefc6e957e81452feb457f503e7ed08981e77c3967ace077b94eabc6dd4b5cb"}
 STAGES = ("sample", "hash_fwd", "mlp_fwd", "comp_fwd", "comp_bwd", "pack", "mlp_bwd", "hash_bwd",
           "adam")
+
+
+def adjoint_traffic(precision, rays):
+    """Counter-measured bytes per table-adjoint call, or None when the kernel
+    sources or the workload differ from those the counters were taken on."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2507_01631_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("hashgrid.hip", "scan.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != ADJOINT_TRAFFIC["sha256"] or precision != "bf16" or rays != 1 << 18:
+        return None
+    return ADJOINT_TRAFFIC["bytes"]
 
 
 def log(*a):
@@ -71,6 +92,17 @@ def run_form(wl, precision, args, pool):
         nerf.train_step(*batch(k))
     torch.cuda.synchronize()
     log("  %s: warmup %d steps done" % (precision, args.warmup))
+    tuned = None
+    if args.tune:
+        # launch shapes for this workload, picked by timing (untimed region)
+        from paper_2507_01631_amd import autotune
+        cnt = [0]
+
+        def one():
+            nerf.train_step(*batch(cnt[0]))
+            cnt[0] += 1
+        tuned, ms, _ = autotune.tune(one, reps=3, warmup=1)
+        log("  %s: tuned launch shapes %s (%.2f ms)" % (precision, tuned, ms))
 
     K = args.steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)] for _ in range(K)]
@@ -133,7 +165,7 @@ def run_form(wl, precision, args, pool):
                 samples_total=nt.mean(), value=na.sum() / (total_ms * 1e-3),
                 stage_ms=dict(zip(STAGES, stage_ms.tolist())), loss=loss,
                 params=int(nerf.table.numel() + nerf.P), table_params=int(nerf.table.numel()),
-                mlp_params=int(nerf.P), L=len(nerf.res), F=nerf.F)
+                mlp_params=int(nerf.P), L=len(nerf.res), F=nerf.F, tuned=tuned)
 
 
 def roofline(form, wl, precision, R):
@@ -432,6 +464,7 @@ def main():
     ap.add_argument("--batches", type=int, default=2, help="distinct ray batches cycled through")
     ap.add_argument("--precision", choices=["bf16", "fp32", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", type=int, default=1, help="autotune launch shapes before timing (1) or not (0)")
     ap.add_argument("--cpu-rays", type=int, default=1 << 17)
     ap.add_argument("--recompute-rays", type=int, default=1 << 16)
     ap.add_argument("--no-recompute-check", action="store_true")
@@ -495,9 +528,11 @@ def main():
                      "achieved": d["achieved"] / (1e9 if d["bound"] == "hbm" else 1e12),
                      "peak": d["peak"] / (1e9 if d["bound"] == "hbm" else 1e12),
                      "unit": "GB/s" if d["bound"] == "hbm" else "TFLOP/s", "frac": d["frac"],
-                     "traffic": None},
+                     "algorithmic_per_launch": d["per_launch"],
+                     "traffic": adjoint_traffic(head, args.rays) if dom == "hash_bwd" else None},
         "stages": {k: {"ms": round(v["ms"], 4), "frac": round(v["frac"], 4), "bound": v["bound"]}
                    for k, v in rl.items()},
+        "launch_shapes": f["tuned"],
     }
     for p in forms[1:]:
         g = res[p]
