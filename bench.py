@@ -374,7 +374,10 @@ def convergence(args):
     """BF16 against FP32 at equal step count on the full-tile scene: both forms
     train from the same initial table and networks on the same cycle of ray
     batches; the held-out ninth view (256^2 rays) is then rendered and its
-    PSNR against the scene's own rendering compared."""
+    PSNR against the scene's own rendering compared (both with early stop
+    only).  With the occupancy grid on, a third BF16 run trains with culling
+    (grid refreshed every 16 steps from step --conv-occ-start) and gives
+    culling's effect on PSNR and on the step time."""
     import torch
     import synth
     dev = "cuda:0"
@@ -386,25 +389,34 @@ def convergence(args):
         % (R * nb, nb, ho.shape[0], time.perf_counter() - t))
     pool = [torch.as_tensor(x).to(dev) for x in (wl.rays_o, wl.rays_d, wl.target, wl.sun)]
     held = [torch.as_tensor(x).to(dev) for x in (ho, hd, ht, hs)]
-    out = {"config": "full_tile, %d rays/step, %d steps, lr %g, batches cycled from %d" % (R, steps, wl.lr, nb)}
+    G = 128 if args.conv_occupancy else 0
+    out = {"config": "full_tile, %d rays/step, %d steps, lr %g, batches cycled from %d, occupancy grid %s"
+                     % (R, steps, wl.lr, nb, "%d^3 (optical thickness of one step > min(0.01, mean))" % G
+                        if G else "off")}
     from paper_2507_01631_amd import TileNeRF, level_resolutions
     g, m = wl.grid, wl.mlp
-    for prec in ("fp32", "bf16"):
-        # a 128^3 occupancy grid rides along (refreshed every 16 steps, culling on)
+    runs = [("fp32", 0), ("bf16", 0)] + ([("bf16", G)] if G else [])
+    for prec, grid in runs:
+        name = prec if grid == 0 else prec + "_grid"
         nerf = TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
                         log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
                         colour_out=m.colour_out, boxes=wl.boxes, zband=wl.zband, samples=wl.samples_per_ray,
                         early_stop=wl.early_stop, precision=prec, table=wl.table, mlp_params=wl.mlp_params,
-                        max_rays=max(R, held[0].shape[0]), lr=wl.lr, occ_grid=128 if args.conv_occupancy else 0,
-                        device=dev)
+                        max_rays=max(R, held[0].shape[0]), lr=wl.lr, occ_grid=grid, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        kept = 0
         for k in range(steps):
             b = k % nb
             sl = slice(b * R, (b + 1) * R)
-            if nerf.G and k % 16 == 0:
+            if nerf.G and k >= args.conv_occ_start and k % 16 == 0:
                 nerf.update_occupancy()
-            nerf.train_step(pool[0][sl], pool[1][sl], pool[2][sl], pool[3][sl])
+            n_dev = nerf.train_step(pool[0][sl], pool[1][sl], pool[2][sl], pool[3][sl])
+            if k == steps - 1:
+                kept = int(n_dev.item())
+            if (k + 1) % 250 == 0:
+                torch.cuda.synchronize()
+                log("    %s step %d (%.1f s)" % (name, k + 1, time.perf_counter() - t0))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         Rh = held[0].shape[0]
@@ -414,29 +426,16 @@ def convergence(args):
         torch.cuda.synchronize()
         mse = float(((nerf.rgb_out[:Rh] - held[2]) ** 2).mean().item())
         psnr = -10.0 * np.log10(max(mse, 1e-12))
-        out[prec] = {"psnr_db": round(psnr, 3), "train_s": round(dt, 3), "ms_per_step": round(1e3 * dt / steps, 3)}
+        out[name] = {"psnr_db": round(psnr, 3), "train_s": round(dt, 3), "ms_per_step": round(1e3 * dt / steps, 3),
+                     "samples_last_step": kept}
         if nerf.G:
-            # the trained field's empty space, culled against early stop alone
-            occ = float(torch.count_nonzero(nerf.occ_density > nerf.occ_threshold).item()) / nerf.occ_density.numel()
-            cmp = {}
-            sl = slice(0, R)
-            for name, G in (("culling", nerf.G), ("early_stop_only", 0)):
-                keep, nerf.G = nerf.G, G
-                for _ in range(2):
-                    nerf.train_step(pool[0][sl], pool[1][sl], pool[2][sl], pool[3][sl])
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                for _ in range(5):
-                    nerf.train_step(pool[0][sl], pool[1][sl], pool[2][sl], pool[3][sl])
-                b.record()
-                torch.cuda.synchronize()
-                cmp[name] = {"ms_per_step": round(a.elapsed_time(b) / 5, 3), "samples": int(nerf.n_out.item()),
-                             "samples_after_early_stop": int(nerf.n_alive_total.item())}
-                nerf.G = keep
-            out[prec]["occupancy"] = dict(cmp, occupied_fraction=round(occ, 4))
-        log("  convergence %s: %s" % (prec, json.dumps(out[prec])))
+            out[name]["occupied_fraction"] = round(nerf.occupied_fraction(), 4)
+        log("  convergence %s: %s" % (name, json.dumps(out[name])))
         del nerf
     out["psnr_gap_db"] = round(out["bf16"]["psnr_db"] - out["fp32"]["psnr_db"], 3)
+    if G:
+        out["culling_psnr_delta_db"] = round(out["bf16_grid"]["psnr_db"] - out["bf16"]["psnr_db"], 3)
+        out["culling_speedup"] = round(out["bf16"]["ms_per_step"] / out["bf16_grid"]["ms_per_step"], 3)
     return out
 
 
@@ -477,7 +476,9 @@ def main():
     ap.add_argument("--convergence-steps", type=int, default=0,
                     help="also train FP32 and BF16 this many steps and compare held-out PSNR")
     ap.add_argument("--conv-rays", type=int, default=1 << 17)
-    ap.add_argument("--conv-occupancy", type=int, default=1, help="train the convergence runs with a 128^3 grid")
+    ap.add_argument("--conv-occupancy", type=int, default=1,
+                    help="add a BF16 convergence run with a 128^3 occupancy grid")
+    ap.add_argument("--conv-occ-start", type=int, default=256, help="first step that updates the grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 256 MiB device copies (byte-counter calibration)")
     args = ap.parse_args()

@@ -213,9 +213,16 @@ int snake_tile_partition(const uint8_t *tile_id, const float *pos, const int32_t
  * snake_occupancy_cells writes the centre ((i+.5)/G, (j+.5)/G, (k+.5)/G) of
  * every cell of the K grids (pos [K G^3][3]) and its tile id (tile_id may be
  * NULL), for evaluating the density there with the encoding and networks.
- * snake_occupancy_update keeps density [n_cells] float as
- * max(decay * density, sigma) and sets bits [ceil(n_cells/32)] uint32 to
- * density > threshold.
+ * snake_occupancy_update folds the density sigma [n_cells] evaluated at the
+ * cell centres into the grid: density [n_cells] float becomes
+ * max(decay * density, sigma_scale * sigma) -- with sigma_scale the sample
+ * step, the grid holds the optical thickness of one step -- and bits
+ * [ceil(n_cells/32)] uint32 are set to density > thr, where thr = threshold,
+ * or with SNAKE_OCC_MEAN_CAP in flags thr = min(threshold, mean of the new
+ * density over the n_cells cells), so that while the whole field is thin the
+ * denser half of it stays occupied.  The mean is summed in FP64 in a fixed
+ * order (the same bits on every call).  decay in [0, 1], sigma_scale > 0.
+ * Workspace: snake_occupancy_workspace_bytes(n_cells), 8-byte aligned.
  * snake_cull_samples keeps, ray by ray and in order, the packed samples
  * whose cell is occupied (a tile id >= K is dropped with
  * SNAKE_DEVERR_TILE_ID) and writes them packed again: packed_info_out [R][2],
@@ -225,8 +232,11 @@ int snake_tile_partition(const uint8_t *tile_id, const float *pos, const int32_t
  * Workspace: snake_cull_workspace_bytes(R).
  */
 int snake_occupancy_cells(int32_t G, int32_t K, float *pos, uint8_t *tile_id, snake_stream_t stream);
-int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, float threshold,
-                           float *density, uint32_t *bits, snake_stream_t stream);
+#define SNAKE_OCC_MEAN_CAP 1u          /* threshold capped at the mean density */
+size_t snake_occupancy_workspace_bytes(int64_t n_cells);
+int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, float sigma_scale,
+                           float threshold, uint32_t flags, float *density, uint32_t *bits,
+                           void *workspace, size_t workspace_bytes, snake_stream_t stream);
 size_t snake_cull_workspace_bytes(int32_t R);
 int snake_cull_samples(int32_t G, const uint32_t *bits, int32_t K, int32_t R,
                        const int32_t *packed_info, const float *t0, const float *t1,

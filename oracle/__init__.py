@@ -259,10 +259,16 @@ def occupancy_cell_centres(G, K=1):
     return np.tile(one, (K, 1)), np.repeat(np.arange(K, dtype=np.uint8), G ** 3)
 
 
-def occupancy_update(density, sigma, decay, threshold):
-    """EMA of the cell densities: d = max(decay d, sigma); occupied iff d > threshold."""
-    d = np.maximum(np.asarray(density, dtype=np.float64) * decay, np.asarray(sigma, dtype=np.float64))
-    return d, d > threshold
+def occupancy_update(density, sigma, decay, threshold, scale=1.0, mean_cap=False):
+    """Decaying maximum of the cells' optical thickness: d = max(decay d,
+    scale sigma) (scale = the sample step).  A cell is occupied iff
+    d > threshold, or with the mean cap iff d > min(threshold, mean of d).
+    The paper names the SAT-NGP culling (Sec. 4.1) without its rule; this is
+    the usual I-NGP one, taken as a reading.  FP64."""
+    d = np.maximum(np.asarray(density, dtype=np.float64) * decay,
+                   scale * np.asarray(sigma, dtype=np.float64))
+    thr = min(threshold, float(d.mean())) if mean_cap else threshold
+    return d, d > thr
 
 
 def cull_samples(smp, occupied, G):

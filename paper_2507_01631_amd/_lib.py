@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsnake.so")
 SNAKE_F32, SNAKE_BF16 = 0, 1
 SNAKE_GRID_ALWAYS_HASH = 1
 SNAKE_ADAM_ZERO_GRAD = 1
+SNAKE_OCC_MEAN_CAP = 1
 SNAKE_DEVERR_CAPACITY = 1
 SNAKE_DEVERR_TILE_ID = 2
 SNAKE_DEVERR_RAY_ID = 4
@@ -33,7 +34,8 @@ EXPORTS = (
     "snake_abi_version", "snake_last_error", "snake_check_device_error", "snake_tune_set", "snake_tune_get",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_pack_alive",
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
-    "snake_occupancy_cells", "snake_occupancy_update", "snake_cull_workspace_bytes", "snake_cull_samples",
+    "snake_occupancy_cells", "snake_occupancy_workspace_bytes", "snake_occupancy_update",
+    "snake_cull_workspace_bytes", "snake_cull_samples",
     "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_weight_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
@@ -94,7 +96,8 @@ _SIGS = {
     "snake_window_accept": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_tile_partition_workspace_bytes": ([_I32], _SZ),
     "snake_occupancy_cells": ([_I32, _I32, _P, _P, _P], ctypes.c_int),
-    "snake_occupancy_update": ([_P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
+    "snake_occupancy_workspace_bytes": ([_I64], _SZ),
+    "snake_occupancy_update": ([_P, _I64, _F, _F, _F, ctypes.c_uint32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_cull_workspace_bytes": ([_I32], _SZ),
     "snake_cull_samples": ([_I32, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
                             _SZ, _P], ctypes.c_int),
@@ -238,10 +241,16 @@ def snake_occupancy_cells(G, K, pos, tile_id, stream=None):
                                                                 _stream(stream)))
 
 
-def snake_occupancy_update(sigma, n_cells, decay, threshold, density, bits, stream=None):
-    _check("snake_occupancy_update", lib().snake_occupancy_update(_ptr(sigma), int(n_cells), float(decay),
-                                                                  float(threshold), _ptr(density), _ptr(bits),
-                                                                  _stream(stream)))
+def snake_occupancy_workspace_bytes(n_cells) -> int:
+    return int(lib().snake_occupancy_workspace_bytes(int(n_cells)))
+
+
+def snake_occupancy_update(sigma, n_cells, decay, sigma_scale, threshold, flags, density, bits, workspace,
+                           stream=None):
+    _check("snake_occupancy_update", lib().snake_occupancy_update(
+        _ptr(sigma), int(n_cells), float(decay), float(sigma_scale), float(threshold), int(flags), _ptr(density),
+        _ptr(bits), _ptr(workspace), workspace.numel() * workspace.element_size() if workspace is not None else 0,
+        _stream(stream)))
 
 
 def snake_cull_workspace_bytes(R) -> int:

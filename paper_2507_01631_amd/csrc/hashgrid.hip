@@ -852,6 +852,12 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     }
     SNAKE_REQUIRE(lg >= 1, SNAKE_ERR_WORKSPACE, "snake_hashgrid_bwd: workspace needs at least %zu bytes",
                   snake_hashgrid_bwd_workspace_bytes(gd, K, n, 1));
+    {
+        // as few passes as that allows, with their levels spread evenly
+        // (each pass re-reads every sample's position)
+        const int npass = (g.L + lg - 1) / lg;
+        lg = (g.L + npass - 1) / npass;
+    }
     // per-level scale of the fixed-point sums, from the largest |dfeat|
     uint32_t *lmax = static_cast<uint32_t *>(workspace);
     unsigned int *err = device_error_word();

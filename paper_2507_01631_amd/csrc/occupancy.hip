@@ -41,26 +41,70 @@ __global__ __launch_bounds__(256) void cells_kernel(int G, int K, float *__restr
     }
 }
 
-// density = max(decay density, sigma); bit = density > threshold.  One
-// wavefront writes the two 32-bit words of its 64 cells.
-__global__ __launch_bounds__(256) void occ_update_kernel(const float *__restrict__ sigma, int64_t n, float decay,
-                                                         float thr, float *__restrict__ density,
-                                                         uint32_t *__restrict__ bits)
+// Occupancy update, first half: density = max(decay density, scale sigma)
+// for every cell, and each block's FP64 sum of the new densities (for the
+// mean cap).  The grid is a function of n alone and every block sums its
+// cells in a fixed order, so the partial sums are reproducible.
+__global__ __launch_bounds__(256) void occ_decay_kernel(const float *__restrict__ sigma, int64_t n, float decay,
+                                                        float scale, float *__restrict__ density,
+                                                        double *__restrict__ partial)
 {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const float d = fmaxf(density[c] * decay, scale * sigma[c]);
+        density[c] = d;
+        acc += (double)d;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Second half: bit = density > thr, with thr = min(threshold, mean density)
+// under the mean cap (every block adds the partial sums in the same order).
+// One wavefront writes the two 32-bit words of its 64 cells.
+__global__ __launch_bounds__(256) void occ_bits_kernel(const float *__restrict__ density, int64_t n, float threshold,
+                                                       int mean_cap, const double *__restrict__ partial, int nparts,
+                                                       uint32_t *__restrict__ bits)
+{
+    __shared__ double red[4];
+    __shared__ float thr_s;
+    if (mean_cap) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[i];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const float mean = (float)(((red[0] + red[1]) + (red[2] + red[3])) / (double)n);
+            thr_s = fminf(threshold, mean);
+        }
+    } else if (threadIdx.x == 0) {
+        thr_s = threshold;
+    }
+    __syncthreads();
+    const float thr = thr_s;
     const int lane = lane_id();
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
     for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); w * 64 < n; w += waves) {
         const int64_t c = w * 64 + lane;
-        bool occ = false;
-        if (c < n) {
-            const float d = fmaxf(density[c] * decay, sigma[c]);
-            density[c] = d;
-            occ = d > thr;
-        }
+        const bool occ = c < n && density[c] > thr;
         const unsigned long long m = __ballot(occ);
         if (lane == 0) bits[2 * w] = (uint32_t)m;
         if (lane == 32 && w * 64 + 32 < n) bits[2 * w + 1] = (uint32_t)(m >> 32);
     }
+}
+
+constexpr int kOccBlocks = 1024;
+
+static unsigned occ_blocks(int64_t n)
+{
+    const int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > kOccBlocks ? kOccBlocks : b));
 }
 
 __device__ __forceinline__ bool sample_kept(const float *pos, const uint8_t *tile_id, int64_t s, int G, int K,
@@ -156,17 +200,35 @@ int snake_occupancy_cells(int32_t G, int32_t K, float *pos, uint8_t *tile_id, sn
     return launch_status(__func__);
 }
 
-int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, float threshold, float *density,
-                           uint32_t *bits, snake_stream_t stream)
+size_t snake_occupancy_workspace_bytes(int64_t n_cells)
+{
+    return n_cells < 0 ? 0 : (size_t)occ_blocks(n_cells) * sizeof(double);
+}
+
+int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, float sigma_scale, float threshold,
+                           uint32_t flags, float *density, uint32_t *bits, void *workspace, size_t workspace_bytes,
+                           snake_stream_t stream)
 {
     SNAKE_REQUIRE(n_cells >= 0, SNAKE_ERR_INVALID_ARG, "snake_occupancy_update: n_cells < 0");
     SNAKE_REQUIRE(decay >= 0.0f && decay <= 1.0f, SNAKE_ERR_INVALID_ARG, "snake_occupancy_update: decay not in [0, 1]");
+    SNAKE_REQUIRE(sigma_scale > 0.0f && sigma_scale <= 3.4e38f, SNAKE_ERR_INVALID_ARG,
+                  "snake_occupancy_update: sigma_scale must be positive and finite");
+    SNAKE_REQUIRE((flags & ~SNAKE_OCC_MEAN_CAP) == 0u, SNAKE_ERR_INVALID_ARG, "snake_occupancy_update: unknown flags");
     if (n_cells == 0) return SNAKE_OK;
     SNAKE_NOT_NULL(sigma);
     SNAKE_NOT_NULL(density);
     SNAKE_NOT_NULL(bits);
-    occ_update_kernel<<<grid_for(n_cells, 256, 8), 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
-        sigma, n_cells, decay, threshold, density, bits);
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= snake_occupancy_workspace_bytes(n_cells),
+                  SNAKE_ERR_WORKSPACE, "snake_occupancy_update: workspace needs %zu bytes",
+                  snake_occupancy_workspace_bytes(n_cells));
+    SNAKE_ALIGNED(workspace, 8);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const unsigned nb = occ_blocks(n_cells);
+    double *partial = static_cast<double *>(workspace);
+    occ_decay_kernel<<<nb, 256, 0, st>>>(sigma, n_cells, decay, sigma_scale, density, partial);
+    occ_bits_kernel<<<grid_for(n_cells, 256, 8), 256, 0, st>>>(density, n_cells, threshold,
+                                                               (flags & SNAKE_OCC_MEAN_CAP) ? 1 : 0, partial,
+                                                               (int)nb, bits);
     return launch_status(__func__);
 }
 

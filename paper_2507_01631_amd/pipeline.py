@@ -49,8 +49,8 @@ class TileNeRF:
     def __init__(self, *, res, n_features, log2_table, n_dir, colour_layers, colour_out,
                  boxes, zband=None, samples=64, early_stop=0.0, precision="fp32",
                  table=None, mlp_params=None, max_rays=4096, lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-15, hash_bwd="binned", hash_ws_gib=16.0, recompute=True, occ_grid=0,
-                 occ_decay=0.95, occ_threshold=0.01, device="cuda"):
+                 eps=1e-15, hash_bwd="binned", hash_ws_gib=24.0, recompute=True, occ_grid=0,
+                 occ_decay=0.95, occ_threshold=0.01, occ_mean_cap=True, device="cuda"):
         self.device = torch.device(device)
         self.res = [int(r) for r in res]
         self.F = int(n_features)
@@ -91,17 +91,28 @@ class TileNeRF:
         self.recompute = bool(recompute)
         self.act = None
         # occ_grid = G > 0: coarse occupancy grid of G^3 cells per tile; samples in
-        # unoccupied cells are culled after sampling (SAT-NGP procedure, Sec. 4.1)
+        # unoccupied cells are culled after sampling (SAT-NGP procedure, Sec. 4.1).
+        # The grid holds a decaying maximum of the optical thickness sigma * step
+        # of one nominal sample step (band height / samples, unit-length rays) at
+        # the cell centres; a cell is occupied while that exceeds occ_threshold,
+        # capped at the grid's mean when occ_mean_cap is set.
         self.G = int(occ_grid)
         self.occ_decay, self.occ_threshold = float(occ_decay), float(occ_threshold)
+        self.occ_flags = L.SNAKE_OCC_MEAN_CAP if occ_mean_cap else 0
+        b = self.boxes
+        zlo, zhi = float(b[:, 2].min()), float(b[:, 5].max())
+        if self.zband is not None:
+            zlo, zhi = max(zlo, float(self.zband[0])), min(zhi, float(self.zband[1]))
+        self.occ_step = (zhi - zlo) / self.S
         if self.G:
             nc = self.K * self.G ** 3
-            # start fully occupied: the density estimate decays towards what the
-            # networks report at the cell centres
-            self.occ_density = torch.full((nc,), 2.0 * self.occ_threshold + 1.0, device=self.device)
+            # every cell occupied until the first update; the estimate then
+            # starts from what the networks report at the cell centres
+            self.occ_density = torch.zeros((nc,), device=self.device)
             self.occ_bits = torch.full(((nc + 31) // 32,), -1, dtype=torch.int32, device=self.device)
             self.occ_pos = torch.empty((nc, 3), device=self.device)
             self.occ_tile = torch.empty(nc, dtype=torch.uint8, device=self.device) if self.K > 1 else None
+            self.ws_occ = torch.empty(L.snake_occupancy_workspace_bytes(nc), dtype=torch.uint8, device=self.device)
             L.snake_occupancy_cells(self.G, self.K, self.occ_pos, self.occ_tile)
         self.step_count = 0
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -188,7 +199,8 @@ class TileNeRF:
 
     def update_occupancy(self, stream=None):
         """Evaluate the density at every cell centre with the current table and
-        networks and fold it into the grid's decaying maximum."""
+        networks, fold sigma * step into the grid's decaying maximum and
+        recompute the occupancy bits."""
         nc = self.K * self.G ** 3
         if not hasattr(self, "occ_feat"):
             fdt = torch.bfloat16 if self.feat_dtype == L.SNAKE_BF16 else torch.float32
@@ -202,8 +214,15 @@ class TileNeRF:
                              self.occ_feat, None, stream)
         L.snake_mlp_fwd(self.mlp, self.params, self.occ_feat, self.occ_view, self.occ_sun, self.occ_ray, 1, None,
                         nc, None, self.occ_sigma, self.occ_rgb, stream=stream)
-        L.snake_occupancy_update(self.occ_sigma, nc, self.occ_decay, self.occ_threshold, self.occ_density,
-                                 self.occ_bits, stream)
+        L.snake_occupancy_update(self.occ_sigma, nc, self.occ_decay, self.occ_step, self.occ_threshold,
+                                 self.occ_flags, self.occ_density, self.occ_bits, self.ws_occ, stream)
+
+    def occupied_fraction(self):
+        """Fraction of the grid's cells marked occupied (reads the bits back)."""
+        nc = self.K * self.G ** 3
+        w = self.occ_bits.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        bits = (w.unsqueeze(1) >> torch.arange(32, device=w.device)) & 1
+        return float(bits.reshape(-1)[:nc].sum().item()) / nc
 
     def field_fwd(self, sun=None, stream=None):
         L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.pos, self.tile_id, None, self.cap,

@@ -30,14 +30,28 @@ def test_cells_and_update(L, orc):
     rng = np.random.default_rng(5)
     dens = rng.uniform(0, 2, size=n).astype(np.float32)
     sig = rng.exponential(0.5, size=n).astype(np.float32)
-    d, bits = dev(dens), torch.zeros((n + 31) // 32, dtype=torch.int32, device=DEV)
-    L.snake_occupancy_update(dev(sig), n, 0.95, 0.8, d, bits)
-    sync()
-    ref = np.maximum(dens * np.float32(0.95), sig)             # FP32, as the kernel
-    assert np.array_equal(host(d), ref)
-    b = host(bits).view(np.uint32)
-    got = ((b[np.arange(n) >> 5] >> (np.arange(n) & 31)) & 1).astype(bool)
-    assert np.array_equal(got, ref > np.float32(0.8))
+    ws = torch.empty(L.snake_occupancy_workspace_bytes(n), dtype=torch.uint8, device=DEV)
+    unpack = lambda bits: ((host(bits).view(np.uint32)[np.arange(n) >> 5] >> (np.arange(n) & 31)) & 1).astype(bool)  # noqa: E731
+    for scale, thr, cap in ((1.0, 0.8, 0), (0.25, 0.8, L.SNAKE_OCC_MEAN_CAP), (0.25, 2.0, L.SNAKE_OCC_MEAN_CAP)):
+        d, bits = dev(dens), torch.zeros((n + 31) // 32, dtype=torch.int32, device=DEV)
+        L.snake_occupancy_update(dev(sig), n, 0.95, scale, thr, cap, d, bits, ws)
+        sync()
+        ref = np.maximum(dens * np.float32(0.95), np.float32(scale) * sig)     # FP32, as the kernel
+        assert np.array_equal(host(d), ref)
+        _, occ = orc.occupancy_update(dens, sig, 0.95, thr, scale=scale, mean_cap=bool(cap))
+        # the threshold the oracle takes in FP64; cells within FP32 rounding of it may go either way
+        t = min(thr, float(ref.astype(np.float64).mean())) if cap else thr
+        sure = np.abs(ref.astype(np.float64) - t) > 1e-6 * t
+        got = unpack(bits)
+        assert np.array_equal(got[sure], occ[sure]) and sure.mean() > 0.999
+        assert np.array_equal(got, ref > np.float32(t)) or cap
+    # the same call twice gives the same bits (fixed-order mean)
+    outs = []
+    for _ in range(2):
+        d, bits = dev(dens), torch.zeros((n + 31) // 32, dtype=torch.int32, device=DEV)
+        L.snake_occupancy_update(dev(sig), n, 0.95, 0.25, 0.1, L.SNAKE_OCC_MEAN_CAP, d, bits, ws)
+        outs.append(host(bits))
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("K", [1, 4])

@@ -270,6 +270,9 @@ def test_occupancy_update_from_the_field(orc):
     feat = orc.hashgrid_fwd(orc.level_resolutions(8, 16, 256), 14, w.table, pos)
     sig, _ = orc.mlp_fwd(w.mlp, w.mlp_params, feat, np.array([[0.0, 0.0, -1.0]], np.float32),
                          np.zeros(G ** 3, np.int32))
-    init = 2.0 * 0.01 + 1.0
-    ref = np.maximum(np.maximum(init * 0.95, sig) * 0.95, sig)
-    assert_values(host(nerf.occ_density), ref, 1e-5, 1e-7, "occupancy density")
+    # the grid starts at zero: after two updates it holds sigma * step
+    ref = np.maximum(sig * nerf.occ_step * 0.95, sig * nerf.occ_step)
+    assert_values(host(nerf.occ_density), ref, 1e-5, 1e-9, "occupancy density")
+    frac = nerf.occupied_fraction()
+    mean_occ = (ref > min(0.01, ref.mean())).mean()
+    assert abs(frac - mean_occ) < 0.01, (frac, mean_occ)

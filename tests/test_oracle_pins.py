@@ -803,3 +803,23 @@ def test_occupancy_cells_and_culling(orc):
     assert np.allclose(full["opacity"], kept["opacity"], rtol=1e-13, atol=1e-15)
     d, o = orc.occupancy_update(np.full(4, 1.0), np.array([0.0, 0.5, 2.0, 0.96]), 0.95, 0.96)
     assert np.allclose(d, [0.95, 0.95, 2.0, 0.96]) and o.tolist() == [False, False, True, False]
+    # the step scale multiplies sigma, not the decayed estimate
+    d, o = orc.occupancy_update(np.zeros(3), np.array([1.0, 3.0, 10.0]), 0.5, 0.02, scale=0.01)
+    assert np.allclose(d, [0.01, 0.03, 0.1]) and o.tolist() == [False, True, True]
+
+
+def test_occupancy_mean_cap(orc):
+    """Mean cap: with every cell below the threshold, exactly the cells above
+    the mean stay occupied; with the mean above the threshold the cap is
+    inactive; a uniform field below the threshold is all empty (strict >)."""
+    sig = np.array([0.001, 0.002, 0.003, 0.010])             # mean 0.004
+    d, o = orc.occupancy_update(np.zeros(4), sig, 0.95, 0.01, mean_cap=True)
+    assert o.tolist() == [False, False, False, True]
+    d, o = orc.occupancy_update(np.zeros(4), sig, 0.95, 0.0025, mean_cap=True)
+    assert o.tolist() == [False, False, True, True]
+    big = np.array([0.5, 0.005, 0.02, 1.0])                  # mean 0.38 > 0.01
+    _, o1 = orc.occupancy_update(np.zeros(4), big, 0.95, 0.01, mean_cap=True)
+    _, o2 = orc.occupancy_update(np.zeros(4), big, 0.95, 0.01, mean_cap=False)
+    assert o1.tolist() == o2.tolist() == [True, False, True, True]
+    _, o = orc.occupancy_update(np.zeros(5), np.full(5, 0.001), 0.95, 0.01, mean_cap=True)
+    assert not o.any()
