@@ -122,8 +122,14 @@ def run_form(wl, precision, args, pool):
         e[0].record()
         nerf.sample(ro, rd, R)
         e[1].record()
-        L.snake_hashgrid_fwd(nerf.grid, nerf.K, nerf.table, nerf.pos, nerf.tile_id, None, nerf.cap,
-                             nerf.n_out, nerf.feat)
+        if nerf.table_bf16:
+            # the BF16 form gathers from a BF16 mirror refreshed from the FP32 table
+            L.snake_convert_bf16(nerf.table, nerf.table.numel(), nerf.table_h)
+            L.snake_hashgrid_fwd(nerf.grid_fwd, nerf.K, nerf.table_h, nerf.pos, nerf.tile_id, None, nerf.cap,
+                                 nerf.n_out, nerf.feat)
+        else:
+            L.snake_hashgrid_fwd(nerf.grid, nerf.K, nerf.table, nerf.pos, nerf.tile_id, None, nerf.cap,
+                                 nerf.n_out, nerf.feat)
         e[2].record()
         L.snake_mlp_fwd(nerf.mlp, nerf.params, nerf.feat, nerf.view, sun, nerf.ray_id, R, None, nerf.cap,
                         nerf.n_out, nerf.sigma, nerf.rgb)
@@ -165,7 +171,7 @@ def run_form(wl, precision, args, pool):
                 samples_total=nt.mean(), value=na.sum() / (total_ms * 1e-3),
                 stage_ms=dict(zip(STAGES, stage_ms.tolist())), loss=loss,
                 params=int(nerf.table.numel() + nerf.P), table_params=int(nerf.table.numel()),
-                mlp_params=int(nerf.P), L=len(nerf.res), F=nerf.F, tuned=tuned)
+                mlp_params=int(nerf.P), L=len(nerf.res), F=nerf.F, tuned=tuned, table_bf16=nerf.table_bf16)
 
 
 def roofline(form, wl, precision, R):
@@ -173,10 +179,12 @@ def roofline(form, wl, precision, R):
     Lv, F = form["L"], form["F"]
     nt, na = form["samples_total"], form["samples_alive"]
     fb = 2 if precision == "bf16" else 4
+    tb = 2 if form.get("table_bf16") else 4
     macs = mlp_macs(wl.mlp.n_dir, wl.mlp.colour_layers, wl.mlp.colour_out)
     work = {
         "sample": ("hbm", R * (48 + 8 + 12) + nt * (4 + 4 + 12 + 4)),
-        "hash_fwd": ("hbm", nt * (12 + Lv * 8 * F * 4 + Lv * F * fb)),
+        # gathers of FP32 entries, or of the BF16 mirror (plus refreshing it: 4 B read, 2 B written per entry)
+        "hash_fwd": ("hbm", nt * (12 + Lv * 8 * F * tb + Lv * F * fb) + (form["table_params"] * 6 if tb == 2 else 0)),
         "mlp_fwd": ("mfma", nt * 2 * macs),
         "comp_fwd": ("hbm", nt * (4 + 12 + 4 + 4) + R * (8 + 12 + 12 + 4 + 4 + 4)),
         "comp_bwd": ("hbm", nt * (4 + 12 + 4 + 4 + 4 + 12) + R * (8 + 12 + 4)),

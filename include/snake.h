@@ -251,6 +251,7 @@ int snake_cull_samples(int32_t G, const uint32_t *bits, int32_t K, int32_t R,
 
 #define SNAKE_MAX_LEVELS 32
 #define SNAKE_GRID_ALWAYS_HASH 1u      /* hash every level, even when dense fits */
+#define SNAKE_GRID_TABLE_BF16 2u       /* forward: the table is a BF16 mirror */
 
 typedef struct {
     int32_t n_levels;                  /* L, 1..32 */
@@ -268,15 +269,24 @@ typedef struct {
  *   hashed: (i*1 XOR j*2654435761 XOR k*805459861) mod 2^32 AND (T-1)
  * and feat[l][s][f] = sum_b w_b table[tile][l][idx_b][f] with
  * w_b = prod_a (b_a ? w_a : 1 - w_a).
- * table [K][L][T][F] float (1 <= K <= 256), pos [.][3] float, tile_id (NULL =
- * tile 0 for all; an id >= K gives zero features and SNAKE_DEVERR_TILE_ID),
- * feat [L][n][F] written.  idx_dbg (NULL or [n][L][8] uint32) receives the
- * corner slots.
+ * table [K][L][T][F] float (1 <= K <= 256), or with SNAKE_GRID_TABLE_BF16 in
+ * g->flags its bfloat16 mirror of the same layout (the FP32 table rounded by
+ * snake_convert_bf16; the blend stays FP32), 16-byte aligned; pos [.][3]
+ * float, tile_id (NULL = tile 0 for all; an id >= K gives zero features and
+ * SNAKE_DEVERR_TILE_ID), feat [L][n][F] written.  idx_dbg (NULL or
+ * [n][L][8] uint32) receives the corner slots.  The adjoint ignores the flag
+ * (its dtable is always FP32).
  */
-int snake_hashgrid_fwd(const snake_grid_desc *g, int32_t K, const float *table,
+int snake_hashgrid_fwd(const snake_grid_desc *g, int32_t K, const void *table,
                        const float *pos, const uint8_t *tile_id, const int32_t *sample_idx,
                        int64_t n, const int64_t *n_dev, void *feat, uint32_t *idx_dbg,
                        snake_stream_t stream);
+
+/* dst[i] = src[i] rounded to bfloat16 (nearest, ties to even; NaN stays NaN)
+ * for n floats (n a multiple of 4; src 16-byte, dst 8-byte aligned): the
+ * half-precision parameter copy that mixed-precision NGP training gathers
+ * from, refreshed from the FP32 master table before each forward. */
+int snake_convert_bf16(const float *src, int64_t n, void *dst, snake_stream_t stream);
 
 /* Adjoint: dtable[tile][l][idx_b][f] += w_b * dfeat[l][s][f] for the K tiles
  * of dtable [K][L][T][F] float; dfeat [L][n][F] float (compact, indexed by j).

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsnake.so")
 
 SNAKE_F32, SNAKE_BF16 = 0, 1
 SNAKE_GRID_ALWAYS_HASH = 1
+SNAKE_GRID_TABLE_BF16 = 2
 SNAKE_ADAM_ZERO_GRAD = 1
 SNAKE_OCC_MEAN_CAP = 1
 SNAKE_DEVERR_CAPACITY = 1
@@ -36,7 +37,7 @@ EXPORTS = (
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
     "snake_occupancy_cells", "snake_occupancy_workspace_bytes", "snake_occupancy_update",
     "snake_cull_workspace_bytes", "snake_cull_samples",
-    "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
+    "snake_convert_bf16", "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_weight_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
     "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step", "snake_counter_add",
@@ -102,6 +103,7 @@ _SIGS = {
     "snake_cull_samples": ([_I32, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
                             _SZ, _P], ctypes.c_int),
     "snake_tile_partition": ([_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "snake_convert_bf16": ([_P, _I64, _P, _P], ctypes.c_int),
     "snake_hashgrid_fwd": ([_P, _I32, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "snake_hashgrid_bwd": ([_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_hashgrid_bwd_workspace_bytes": ([_P, _I32, _I64, _I32], _SZ),
@@ -265,6 +267,10 @@ def snake_cull_samples(G, bits, K, R, packed_info, t0, t1, pos, ray_id, tile_id,
                                   _ptr(n_out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                                   _stream(stream))
     _check("snake_cull_samples", rc)
+
+
+def snake_convert_bf16(src, n, dst, stream=None):
+    _check("snake_convert_bf16", lib().snake_convert_bf16(_ptr(src), int(n), _ptr(dst), _stream(stream)))
 
 
 def snake_hashgrid_fwd(g: GridDesc, K, table, pos, tile_id, sample_idx, n, n_dev, feat, idx_dbg=None,

@@ -80,11 +80,64 @@ struct Vec<4> {
     __device__ static float get(const T &v, int f) { return f == 0 ? v.x : f == 1 ? v.y : f == 2 ? v.z : v.w; }
 };
 
+// Table entries: FP32, or the BF16 mirror of the forward (one 16-bit word
+// per feature; widening to FP32 is a shift).  Pair loads fetch the slots
+// (2m, 2m+1) of the x-neighbour pairing in one access.
+template <int F, typename TabT>
+struct Entry;
+template <int F>
+struct Entry<F, float> {
+    typedef typename Vec<F>::T VT;
+    __device__ static VT one(const float *lev, uint32_t i) { return reinterpret_cast<const VT *>(lev)[i]; }
+};
+__device__ __forceinline__ float bf16_bits(uint32_t h) { return __uint_as_float(h << 16); }
+template <>
+struct Entry<1, __hip_bfloat16> {
+    __device__ static float one(const __hip_bfloat16 *lev, uint32_t i)
+    {
+        return bf16_bits(reinterpret_cast<const uint16_t *>(lev)[i]);
+    }
+};
+template <>
+struct Entry<2, __hip_bfloat16> {
+    __device__ static float2 one(const __hip_bfloat16 *lev, uint32_t i)
+    {
+        const uint32_t w = reinterpret_cast<const uint32_t *>(lev)[i];
+        return make_float2(bf16_bits(w & 0xffffu), bf16_bits(w >> 16));
+    }
+    // slots 2m and 2m+1 in one 8-byte load
+    __device__ static void pair(const __hip_bfloat16 *lev, uint32_t m, float2 &lo, float2 &hi)
+    {
+        const uint2 w = reinterpret_cast<const uint2 *>(lev)[m];
+        lo = make_float2(bf16_bits(w.x & 0xffffu), bf16_bits(w.x >> 16));
+        hi = make_float2(bf16_bits(w.y & 0xffffu), bf16_bits(w.y >> 16));
+    }
+};
+template <>
+struct Entry<4, __hip_bfloat16> {
+    __device__ static float4 one(const __hip_bfloat16 *lev, uint32_t i)
+    {
+        const uint2 w = reinterpret_cast<const uint2 *>(lev)[i];
+        return make_float4(bf16_bits(w.x & 0xffffu), bf16_bits(w.x >> 16), bf16_bits(w.y & 0xffffu),
+                           bf16_bits(w.y >> 16));
+    }
+};
+template <>
+struct Entry<2, float> {
+    __device__ static float2 one(const float *lev, uint32_t i) { return reinterpret_cast<const float2 *>(lev)[i]; }
+    __device__ static void pair(const float *lev, uint32_t m, float2 &lo, float2 &hi)
+    {
+        const float4 w = reinterpret_cast<const float4 *>(lev)[m];
+        lo = make_float2(w.x, w.y);
+        hi = make_float2(w.z, w.w);
+    }
+};
+
 __device__ __forceinline__ void store_feat(float *p, float v) { *p = v; }
 __device__ __forceinline__ void store_feat(__hip_bfloat16 *p, float v) { *p = __float2bfloat16(v); }
 
-template <int F, typename OutT>
-__global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const float *__restrict__ table,
+template <int F, typename OutT, typename TabT>
+__global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *__restrict__ table,
                                                            const float *__restrict__ pos,
                                                            const uint8_t *__restrict__ tile_id,
                                                            const int32_t *__restrict__ sidx, int64_t n,
@@ -111,29 +164,28 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const float *
         uint32_t idx[8];
         float wt[8];
         corners(g, l, x, idx, wt);
-        const VT *lev = reinterpret_cast<const VT *>(table + ((tile * g.L + l) << g.log2T) * F);
+        const TabT *lev = table + ((tile * g.L + l) << g.log2T) * F;
         VT v[8];
         if constexpr (F == 2) {
             // corners q and q^1 differ only in x; when their slots are an
             // aligned pair (2m, 2m+1) -- half of all pairs, dense or hashed --
-            // one 16-byte load fetches both: one cache-line request, not two
-            const float4 *lev4 = reinterpret_cast<const float4 *>(lev);
+            // one load fetches both: one cache-line request, not two
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const uint32_t a = idx[2 * p], b = idx[2 * p + 1];
                 if ((a ^ b) == 1u) {
-                    const float4 w4 = lev4[a >> 1];
-                    const float2 lo = make_float2(w4.x, w4.y), hi = make_float2(w4.z, w4.w);
+                    float2 lo, hi;
+                    Entry<F, TabT>::pair(lev, a >> 1, lo, hi);
                     v[2 * p] = (a & 1u) ? hi : lo;
                     v[2 * p + 1] = (a & 1u) ? lo : hi;
                 } else {
-                    v[2 * p] = lev[a];
-                    v[2 * p + 1] = lev[b];
+                    v[2 * p] = Entry<F, TabT>::one(lev, a);
+                    v[2 * p + 1] = Entry<F, TabT>::one(lev, b);
                 }
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = lev[idx[q]];
+            for (int q = 0; q < 8; ++q) v[q] = Entry<F, TabT>::one(lev, idx[q]);
         }
 #pragma unroll
         for (int f = 0; f < F; ++f) {
@@ -588,6 +640,24 @@ __global__ __launch_bounds__(256) void level_absmax_kernel(const float *__restri
     }
 }
 
+// dst = src rounded to BF16 (nearest, ties to even; NaN stays NaN).
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float4 *__restrict__ src, int64_t n4,
+                                                      uint2 *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 v = src[i];
+        const float f[4] = {v.x, v.y, v.z, v.w};
+        uint32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t u = __float_as_uint(f[k]);
+            h[k] = (u & 0x7fffffffu) > 0x7f800000u ? ((u >> 16) | 0x40u)
+                                                   : ((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+        }
+        dst[i] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+}
+
 __global__ void zero_u32_kernel(uint32_t *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -721,6 +791,8 @@ static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
 int make_grid(const snake_grid_desc *d, int K, Grid &g, const char *fn)
 {
     SNAKE_REQUIRE(d != nullptr, SNAKE_ERR_NULL, "%s: grid descriptor is NULL", fn);
+    SNAKE_REQUIRE((d->flags & ~(SNAKE_GRID_ALWAYS_HASH | SNAKE_GRID_TABLE_BF16)) == 0u, SNAKE_ERR_INVALID_ARG,
+                  "%s: unknown grid flags 0x%x", fn, d->flags);
     SNAKE_REQUIRE(d->n_levels >= 1 && d->n_levels <= SNAKE_MAX_LEVELS, SNAKE_ERR_INVALID_ARG,
                   "%s: n_levels = %d not in [1, %d]", fn, d->n_levels, SNAKE_MAX_LEVELS);
     SNAKE_REQUIRE(d->n_features == 1 || d->n_features == 2 || d->n_features == 4, SNAKE_ERR_UNSUPPORTED,
@@ -756,7 +828,21 @@ using namespace snake;
 
 extern "C" {
 
-int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const float *table, const float *pos,
+int snake_convert_bf16(const float *src, int64_t n, void *dst, snake_stream_t stream)
+{
+    SNAKE_REQUIRE(n >= 0 && n % 4 == 0, SNAKE_ERR_INVALID_ARG, "snake_convert_bf16: n = %lld not a multiple of 4",
+                  (long long)n);
+    if (n == 0) return SNAKE_OK;
+    SNAKE_NOT_NULL(src);
+    SNAKE_NOT_NULL(dst);
+    SNAKE_ALIGNED(src, 16);
+    SNAKE_ALIGNED(dst, 8);
+    to_bf16_kernel<<<grid_for(n / 4, 256, 8), 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+        reinterpret_cast<const float4 *>(src), n / 4, static_cast<uint2 *>(dst));
+    return launch_status(__func__);
+}
+
+int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const void *table, const float *pos,
                        const uint8_t *tile_id, const int32_t *sample_idx, int64_t n,
                        const int64_t *n_dev, void *feat, uint32_t *idx_dbg, snake_stream_t stream)
 {
@@ -773,13 +859,25 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const float *table,
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const unsigned grid = grid_for(n * g.L, 256, tune(SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU));
     const bool bf = gd->feat_dtype == SNAKE_BF16;
-#define SNAKE_HG_FWD(FF)                                                                              \
-    if (bf)                                                                                           \
-        hashgrid_fwd_kernel<FF, __hip_bfloat16><<<grid, 256, 0, st>>>(                                \
-            g, table, pos, tile_id, sample_idx, n, n_dev, static_cast<__hip_bfloat16 *>(feat), idx_dbg); \
-    else                                                                                              \
-        hashgrid_fwd_kernel<FF, float><<<grid, 256, 0, st>>>(g, table, pos, tile_id, sample_idx, n,   \
-                                                             n_dev, static_cast<float *>(feat), idx_dbg)
+    const bool tb = (gd->flags & SNAKE_GRID_TABLE_BF16) != 0;
+    const float *tf = static_cast<const float *>(table);
+    const __hip_bfloat16 *th = static_cast<const __hip_bfloat16 *>(table);
+    __hip_bfloat16 *fh = static_cast<__hip_bfloat16 *>(feat);
+    float *ff = static_cast<float *>(feat);
+#define SNAKE_HG_FWD(FF)                                                                                        \
+    if (tb && bf)                                                                                               \
+        hashgrid_fwd_kernel<FF, __hip_bfloat16, __hip_bfloat16><<<grid, 256, 0, st>>>(g, th, pos, tile_id,      \
+                                                                                    sample_idx, n, n_dev, fh,   \
+                                                                                    idx_dbg);                   \
+    else if (tb)                                                                                                \
+        hashgrid_fwd_kernel<FF, float, __hip_bfloat16><<<grid, 256, 0, st>>>(g, th, pos, tile_id, sample_idx, n, \
+                                                                           n_dev, ff, idx_dbg);                 \
+    else if (bf)                                                                                                \
+        hashgrid_fwd_kernel<FF, __hip_bfloat16, float><<<grid, 256, 0, st>>>(g, tf, pos, tile_id, sample_idx, n, \
+                                                                           n_dev, fh, idx_dbg);                 \
+    else                                                                                                        \
+        hashgrid_fwd_kernel<FF, float, float><<<grid, 256, 0, st>>>(g, tf, pos, tile_id, sample_idx, n, n_dev,  \
+                                                                  ff, idx_dbg)
     if (F == 1) {
         SNAKE_HG_FWD(1);
     } else if (F == 2) {

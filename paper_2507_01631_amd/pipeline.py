@@ -50,7 +50,7 @@ class TileNeRF:
                  boxes, zband=None, samples=64, early_stop=0.0, precision="fp32",
                  table=None, mlp_params=None, max_rays=4096, lr=1e-2, betas=(0.9, 0.99),
                  eps=1e-15, hash_bwd="binned", hash_ws_gib=24.0, recompute=True, occ_grid=0,
-                 occ_decay=0.95, occ_threshold=0.01, occ_mean_cap=True, device="cuda"):
+                 occ_decay=0.95, occ_threshold=0.01, occ_mean_cap=True, table_bf16=None, device="cuda"):
         self.device = torch.device(device)
         self.res = [int(r) for r in res]
         self.F = int(n_features)
@@ -78,6 +78,14 @@ class TileNeRF:
         self.m_t = torch.zeros_like(self.table)
         self.v_t = torch.zeros_like(self.table)
         self.g_t = torch.zeros_like(self.table)
+        # table_bf16 (default: the BF16 form): the forward gathers from a BF16
+        # copy of the table, refreshed from the FP32 master before each forward
+        # (mixed-precision NGP parameters); adjoint and Adam stay FP32
+        self.table_bf16 = bf if table_bf16 is None else bool(table_bf16)
+        self.grid_fwd = self.grid
+        if self.table_bf16:
+            self.table_h = torch.empty(shape, dtype=torch.bfloat16, device=dev)
+            self.grid_fwd = L.grid_desc(self.res, self.F, self.log2T, self.feat_dtype, L.SNAKE_GRID_TABLE_BF16)
         self.m_w = torch.zeros_like(self.params)
         self.v_w = torch.zeros_like(self.params)
         self.g_w = torch.zeros_like(self.params)
@@ -225,8 +233,13 @@ class TileNeRF:
         return float(bits.reshape(-1)[:nc].sum().item()) / nc
 
     def field_fwd(self, sun=None, stream=None):
-        L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.pos, self.tile_id, None, self.cap,
-                             self.n_out, self.feat, None, stream)
+        if self.table_bf16:
+            L.snake_convert_bf16(self.table, self.table.numel(), self.table_h, stream)
+            L.snake_hashgrid_fwd(self.grid_fwd, self.K, self.table_h, self.pos, self.tile_id, None, self.cap,
+                                 self.n_out, self.feat, None, stream)
+        else:
+            L.snake_hashgrid_fwd(self.grid, self.K, self.table, self.pos, self.tile_id, None, self.cap,
+                                 self.n_out, self.feat, None, stream)
         L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, sun, self.ray_id, self.R_cur, None,
                         self.cap, self.n_out, self.sigma, self.rgb, act=self.act, stream=stream)
 

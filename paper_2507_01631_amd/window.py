@@ -34,7 +34,7 @@ class WindowNeRF:
     def __init__(self, *, boxes, zband, res, n_features, log2_table, n_dir, colour_layers, colour_out,
                  precision="bf16", tables=None, mlp_params=None, max_rays=1 << 16, max_samples=None,
                  samples=128, early_stop=0.0, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, hash_ws_gib=16.0,
-                 shared_colour=False, lr_colour=None, device="cuda"):
+                 shared_colour=False, lr_colour=None, table_bf16=None, device="cuda"):
         self.device = torch.device(device)
         self.boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 6)
         self.K = self.boxes.shape[0]
@@ -48,6 +48,11 @@ class WindowNeRF:
         self.precision = precision
         self.feat_dtype = L.SNAKE_BF16 if bf else L.SNAKE_F32
         self.grid = L.grid_desc(self.res, self.F, self.log2T, self.feat_dtype)
+        # table_bf16 (default: the BF16 form): the forward gathers from a BF16
+        # copy of the tables, refreshed from the FP32 masters at each step
+        self.table_bf16 = bf if table_bf16 is None else bool(table_bf16)
+        self.grid_fwd = (L.grid_desc(self.res, self.F, self.log2T, self.feat_dtype, L.SNAKE_GRID_TABLE_BF16)
+                         if self.table_bf16 else self.grid)
         # shared_colour: density nets per tile, one global colour net (Sec. 4.1)
         # with its own optimiser; weights are [K][Pd] then the colour set
         self.shared_colour = bool(shared_colour)
@@ -65,6 +70,7 @@ class WindowNeRF:
                        torch.as_tensor(np.ascontiguousarray(mlp_params, dtype=np.float32)).to(dev)
                        .reshape(self.n_w))
         self.m_t, self.v_t, self.g_t = (torch.zeros_like(self.table) for _ in range(3))
+        self.table_h = torch.empty(tshape, dtype=torch.bfloat16, device=dev) if self.table_bf16 else None
         self.m_w, self.v_w, self.g_w = (torch.zeros_like(self.params) for _ in range(3))
         self.lr, (self.b1, self.b2), self.eps = float(lr), betas, float(eps)
         self.lr_colour = self.lr if lr_colour is None else float(lr_colour)
@@ -157,8 +163,10 @@ class WindowNeRF:
                                  self.view, cap, self.n_out, self.ws_sample, stream)
         L.snake_tile_partition(self.tile_id, self.pos, self.ray_id, cap, self.n_out, K, self.perm, self.inv,
                                self.tile_start, self.pos_s, self.tile_s, self.ray_s, self.ws_part, stream)
-        L.snake_hashgrid_fwd(self.grid, K, self.table, self.pos_s, self.tile_s, None, cap, self.n_out, self.feat,
-                             None, stream)
+        if self.table_bf16:
+            L.snake_convert_bf16(self.table, self.table.numel(), self.table_h, stream)
+        L.snake_hashgrid_fwd(self.grid_fwd, K, self.table_h if self.table_bf16 else self.table, self.pos_s,
+                             self.tile_s, None, cap, self.n_out, self.feat, None, stream)
         L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, sun, self.ray_s, R, None, cap, self.n_out,
                         self.sigma, self.rgb, K=K, tile_start=self.tile_start, stream=stream)
         L.snake_composite_fwd(self.sigma, self.rgb, self.t0, self.t1, self.packed_info, R, self.early_stop,

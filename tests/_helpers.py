@@ -29,6 +29,13 @@ def sync():
     torch.cuda.synchronize()
 
 
+def bf16_round(a):
+    """FP32 values rounded to bfloat16 (nearest, ties to even) by torch's CPU
+    conversion, returned as FP32."""
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    return t.to(torch.bfloat16).to(torch.float32).numpy()
+
+
 def assert_values(got, ref, rel=1e-5, abs_=1e-7, what=""):
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import synth
-from _helpers import DEV, assert_grad, assert_values, dev, host, sync
+from _helpers import DEV, assert_grad, assert_values, bf16_round, dev, host, sync
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +64,56 @@ def test_hashgrid_fwd(L, orc, name, bf16):
         assert_values(got, ref[:, :W], rel=2 ** -8, abs_=1e-6, what="feat bf16")
     else:
         assert_values(got, ref[:, :W], rel=1e-5, abs_=1e-6, what="feat")
+
+
+def test_convert_bf16_matches_torch(L):
+    """The table mirror: round to nearest even, bit for bit against torch's
+    conversion, over random values, ties, subnormals, infinities and NaN."""
+    rng = np.random.default_rng(12)
+    with np.errstate(over="ignore", under="ignore"):
+        x = (rng.standard_normal(40000) * 10.0 ** rng.integers(-42, 39, 40000)).astype(np.float32)
+    bits = rng.integers(0, 2 ** 32, size=4000, dtype=np.uint64).astype(np.uint32)
+    ties = (rng.integers(0, 2 ** 16, size=4000).astype(np.uint32) << 16) | np.uint32(0x8000)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0, 3.4e38, -3.4e38, 1e-40, -1e-40, 1e-45],
+                       np.float32)
+    x = np.concatenate([x, bits.view(np.float32), ties.view(np.float32), special])
+    x = x[: x.size // 4 * 4]
+    out = torch.empty(x.size, dtype=torch.bfloat16, device=DEV)
+    L.snake_convert_bf16(dev(x), x.size, out)
+    sync()
+    got = out.cpu().view(torch.int16).numpy().view(np.uint16)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    nan = np.isnan(x)
+    assert np.array_equal(got[~nan], ref[~nan])
+    assert np.all((got[nan] & 0x7f80) == 0x7f80) and np.all((got[nan] & 0x7f) != 0)
+
+
+@pytest.mark.parametrize("name", ["tiny", "full", "f1", "f4"])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_hashgrid_fwd_bf16_table(L, orc, name, bf16):
+    """Gathers from the BF16 mirror: the same corner slots, and features equal
+    the oracle's on the BF16-rounded table (the blend itself stays FP32)."""
+    rng = np.random.default_rng(13)
+    n = 20011
+    K = 2 if name == "tiny" else 1
+    c, res, table = _grid_setup(L, orc, name, rng, K)
+    pos = _positions(rng, n)
+    tid = rng.integers(0, K, size=n).astype(np.uint8) if K > 1 else None
+    g = L.grid_desc(res, c["F"], c["log2T"], L.SNAKE_BF16 if bf16 else L.SNAKE_F32, L.SNAKE_GRID_TABLE_BF16)
+    th = torch.empty(table.shape, dtype=torch.bfloat16, device=DEV)
+    L.snake_convert_bf16(dev(table), table.size, th)
+    feat = torch.zeros((c["L"], n, c["F"]), dtype=torch.bfloat16 if bf16 else torch.float32, device=DEV)
+    idx = torch.zeros((n, c["L"], 8), dtype=torch.int32, device=DEV)
+    L.snake_hashgrid_fwd(g, K, th, dev(pos), None if tid is None else dev(tid), None, n, None, feat, idx)
+    sync()
+    ref, ridx = orc.hashgrid_fwd(res, c["log2T"], bf16_round(table), pos, tid, 32, return_index=True)
+    assert np.array_equal(host(idx).astype(np.uint32), ridx)
+    got = host(feat).transpose(1, 0, 2).reshape(n, -1)
+    W = c["L"] * c["F"]
+    if bf16:
+        assert_values(got, ref[:, :W], rel=2 ** -8, abs_=1e-6, what="feat bf16 (bf16 table)")
+    else:
+        assert_values(got, ref[:, :W], rel=1e-5, abs_=1e-6, what="feat (bf16 table)")
 
 
 def test_hashgrid_fwd_indexed_and_device_count(L, orc):

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import synth
-from _helpers import DEV, assert_grad, assert_values, dev, host, sync
+from _helpers import DEV, assert_grad, assert_values, bf16_round, dev, host, sync
 
 pytestmark = pytest.mark.gpu
 
@@ -218,7 +218,9 @@ def test_full_size_sampled(orc, prec):
     assert np.array_equal(host(nerf.pos[sd]), o["pos"])
     assert np.array_equal(rays[o["ray_id"]], host(nerf.ray_id[sd]))
     # field on those samples
-    feat = orc.hashgrid_fwd(nerf.res, w.grid.log2_table, w.table, o["pos"], None, 32)
+    # the BF16 form gathers from the BF16 mirror of the table
+    tref = bf16_round(w.table) if nerf.table_bf16 else w.table
+    feat = orc.hashgrid_fwd(nerf.res, w.grid.log2_table, tref, o["pos"], None, 32)
     gf = host(nerf.feat[:, sd, :]).transpose(1, 0, 2).reshape(sel.size, -1)
     vt = 1e-2 if prec == "bf16" else 1e-5
     assert_values(gf, feat, 2 ** -8 if prec == "bf16" else 1e-5, 1e-7, "feat")
