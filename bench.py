@@ -103,6 +103,9 @@ def run_form(wl, precision, args, pool):
             cnt[0] += 1
         tuned, ms, _ = autotune.tune(one, reps=3, warmup=1)
         log("  %s: tuned launch shapes %s (%.2f ms)" % (precision, tuned, ms))
+    else:
+        from paper_2507_01631_amd import autotune
+        tuned = autotune.current()
 
     K = args.steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)] for _ in range(K)]
@@ -472,6 +475,8 @@ def main():
     ap.add_argument("--precision", choices=["bf16", "fp32", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", type=int, default=1, help="autotune launch shapes before timing (1) or not (0)")
+    ap.add_argument("--shape", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a launch-shape tunable before timing (with --tune 0: fixed shapes for profiling)")
     ap.add_argument("--cpu-rays", type=int, default=1 << 17)
     ap.add_argument("--recompute-rays", type=int, default=1 << 16)
     ap.add_argument("--no-recompute-check", action="store_true")
@@ -499,6 +504,9 @@ def main():
     import synth
     from paper_2507_01631_amd import _lib
     _lib.lib()
+    for kv in args.shape:
+        name, val = kv.split("=", 1)
+        _lib.snake_tune_set(name, int(val))
     t = time.perf_counter()
     wl = synth.full_tile(seed=0, n_rays=args.rays * args.batches)
     log("workload generated in %.1f s (%d rays)" % (time.perf_counter() - t, wl.n_rays))
