@@ -339,13 +339,19 @@ __device__ __forceinline__ bool merge_runs(uint32_t key, bool act, int32_t (&v)[
     const unsigned long long le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
     const unsigned long long hb = heads & le;
     const int rs = hb ? 63 - __clzll((long long)hb) : lane;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
+    // Scan steps d = 1, 2, 4, ... complete every run of up to 2d lanes, so a
+    // step is needed only while some run is longer: c holds the lanes that
+    // end d consecutive continuation lanes (active lanes that are not a run's
+    // head), and is zero once no run exceeds the steps taken.  The count is
+    // the same on every lane (it comes from ballots).
+    unsigned long long c = acts & ~heads;
+    for (int d = 1; d < 64 && c != 0ull; d <<= 1) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             const int32_t u = __shfl_up(v[f], d, 64);
             if (lane - d >= rs) v[f] += u;
         }
+        c &= c >> d;
     }
     return tail;
 }
@@ -604,9 +610,15 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
 
 // lmax[l] = largest |dfeat[l][s][f]| over s < ne, as float bits (non-negative
 // floats order as unsigned integers).  Grid: (chunks, L).  A non-finite value
-// raises SNAKE_DEVERR_NONFINITE and its level contributes nothing.
+// raises SNAKE_DEVERR_NONFINITE and its level contributes nothing.  Each
+// thread keeps four 16-byte loads in flight when every level's row is 16-byte
+// aligned (vec: dfeat 16-byte aligned and n F a multiple of 4), else eight
+// scalar loads.
+__device__ __forceinline__ uint32_t absbits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
 __global__ __launch_bounds__(256) void level_absmax_kernel(const float *__restrict__ dfeat, int64_t n,
-                                                           const int64_t *__restrict__ n_dev, int F,
+                                                           const int64_t *__restrict__ n_dev, int F, int vec,
                                                            uint32_t *__restrict__ lmax, unsigned int *err)
 {
     __shared__ uint32_t red[4];
@@ -614,27 +626,41 @@ __global__ __launch_bounds__(256) void level_absmax_kernel(const float *__restri
     const int64_t cnt = effective_n(n, n_dev) * F;
     const float *src = dfeat + (int64_t)l * n * F;
     uint32_t m = 0u;
-    // eight independent loads in flight per thread
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < cnt; i0 += 8 * stride) {
-        uint32_t b[8];
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vec) {
+        const float4 *src4 = reinterpret_cast<const float4 *>(src);
+        const int64_t c4 = cnt / 4;
+        for (int64_t i0 = t0; i0 < c4; i0 += 4 * stride) {
+            float4 b[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t i = i0 + u * stride;
-            b[u] = i < cnt ? (__float_as_uint(src[i]) & 0x7fffffffu) : 0u;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = i0 + u * stride;
+                b[u] = i < c4 ? src4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                m = umax(m, umax(umax(absbits(b[u].x), absbits(b[u].y)), umax(absbits(b[u].z), absbits(b[u].w))));
         }
+        for (int64_t i = c4 * 4 + t0; i < cnt; i += stride) m = umax(m, absbits(src[i]));   // tail
+    } else {
+        for (int64_t i0 = t0; i0 < cnt; i0 += 8 * stride) {
+            uint32_t b[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) m = b[u] > m ? b[u] : m;
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + u * stride;
+                b[u] = i < cnt ? absbits(src[i]) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m = umax(m, b[u]);
+        }
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t o = __shfl_xor(m, d, 64);
-        m = o > m ? o : m;
-    }
+    for (int d = 32; d >= 1; d >>= 1) m = umax(m, __shfl_xor(m, d, 64));
     if (lane_id() == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;
+        for (int w = 1; w < 4; ++w) m = umax(m, red[w]);
         if (m >= 0x7f800000u && err) atomicOr(err, (unsigned)SNAKE_DEVERR_NONFINITE);
         if (m) atomicMax(&lmax[l], m);
     }
@@ -965,7 +991,8 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         unsigned gx = (unsigned)((vals + 256 * 8 - 1) / (256 * 8));
         const unsigned cap_x = (unsigned)(num_cus() * 16 / g.L + 1);
         gx = gx < 1 ? 1 : (gx > cap_x ? cap_x : gx);
-        level_absmax_kernel<<<dim3(gx, g.L), 256, 0, st>>>(dfeat, n, n_dev, F, lmax, err);
+        const int vec = (vals % 4 == 0 && (reinterpret_cast<uintptr_t>(dfeat) & 15u) == 0) ? 1 : 0;
+        level_absmax_kernel<<<dim3(gx, g.L), 256, 0, st>>>(dfeat, n, n_dev, F, vec, lmax, err);
     }
     for (int l0 = 0; l0 < g.L; l0 += lg) {
         const int lgp = l0 + lg <= g.L ? lg : g.L - l0;
