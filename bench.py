@@ -482,7 +482,7 @@ def main():
     ap.add_argument("--no-recompute-check", action="store_true")
     ap.add_argument("--no-window", action="store_true", help="skip the 2x2 window (graph vs separate) run")
     ap.add_argument("--no-sweep", action="store_true", help="skip the snake sweep run")
-    ap.add_argument("--sweep-grids", type=int, nargs="+", default=[3, 4])
+    ap.add_argument("--sweep-grids", type=int, nargs="+", default=[3, 4, 8])
     ap.add_argument("--sweep-steps", type=int, default=5)
     ap.add_argument("--sweep-rays", type=int, default=1 << 16)
     ap.add_argument("--render-px", type=int, default=2048)
