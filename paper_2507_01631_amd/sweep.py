@@ -74,22 +74,25 @@ class SnakeSweep:
         self.per_t = w.Lv * (1 << w.log2T) * w.F
         self.per_w = w.P
         n = self.nx * self.ny
-        # host store (pinned): tables U(-1e-4, 1e-4) and network weights from the seed
+        # host store: one pinned buffer per tile and field (many moderate
+        # pinned allocations rather than a few of several GB each); tables
+        # U(-1e-4, 1e-4) and network weights from the seed
         rng = np.random.default_rng(seed)
         self.h = {}
         for f in self.FIELDS_T:
-            self.h[f] = torch.zeros((n, self.per_t), dtype=torch.float32).pin_memory()
+            self.h[f] = [torch.zeros(self.per_t, dtype=torch.float32).pin_memory() for _ in range(n)]
         for f in self.FIELDS_W:
-            self.h[f] = torch.zeros((n, self.per_w), dtype=torch.float32).pin_memory()
-        self.h["step"] = torch.zeros((n, 1), dtype=torch.int32).pin_memory()
-        self.h["table"].copy_(torch.from_numpy(
-            rng.uniform(-1e-4, 1e-4, size=(n, self.per_t)).astype(np.float32)))
+            self.h[f] = [torch.zeros(self.per_w, dtype=torch.float32).pin_memory() for _ in range(n)]
+        self.h["step"] = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(n)]
+        for t in range(n):
+            self.h["table"][t].copy_(torch.from_numpy(rng.uniform(-1e-4, 1e-4, size=self.per_t).astype(np.float32)))
         from synth import MlpConfig, init_mlp      # weight init recipe (seeded)
         m = MlpConfig(feat_real=min(32, w.Lv * w.F), n_dir=n_dir, colour_layers=colour_layers,
                       colour_out=colour_out)
-        w0 = np.stack([init_mlp(rng, m) for _ in range(n)])
-        assert w0.shape[1] == self.per_w
-        self.h["params"].copy_(torch.from_numpy(w0))
+        for t in range(n):
+            w0 = init_mlp(rng, m)
+            assert w0.shape[0] == self.per_w
+            self.h["params"][t].copy_(torch.from_numpy(np.ascontiguousarray(w0, dtype=np.float32)))
         # device staging: two slots in, two out
         mk = lambda k: torch.empty((2, k), dtype=torch.float32, device=dev)   # noqa: E731
         self.st_in = {f: mk(self.per_t) for f in self.FIELDS_T}
@@ -241,4 +244,4 @@ class SnakeSweep:
 
     def trained_steps(self):
         """Adam steps each tile has taken (1, 2 or 4 windows' worth)."""
-        return self.h["step"].view(self.nx, self.ny).clone()
+        return torch.cat(self.h["step"]).view(self.nx, self.ny).clone()

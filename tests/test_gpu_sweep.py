@@ -41,7 +41,7 @@ def test_sweep_equals_window_by_window(graph):
     kw, _ = _cfg()
     batches = _batches()
     sw = SnakeSweep(NX, NY, precision="fp32", max_rays=R, samples=48, seed=3, device=DEV, **kw)
-    init = {f: sw.h[f].clone() for f in sw.h}
+    init = {f: torch.stack(sw.h[f]).clone() for f in sw.h}       # host store: one pinned buffer per tile
     times = sw.run(STEPS, batches, graph=graph)
     assert len(times) == len(snake_path(NX, NY))
     # reference: a plain store on the device, one fresh window per position
@@ -75,7 +75,7 @@ def test_sweep_equals_window_by_window(graph):
         del w
     sync()
     for f in ("table", "m_t", "v_t", "params", "m_w", "v_w", "step"):
-        assert torch.equal(sw.h[f], ref[f].cpu()), f
+        assert torch.equal(torch.stack(sw.h[f]), ref[f].cpu()), f
     # corners were trained in 1 window, edges in 2, the centre in 4
     steps = host(sw.trained_steps()).reshape(NX, NY)
     extra = 1 if graph else 0
