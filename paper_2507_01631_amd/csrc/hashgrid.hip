@@ -13,6 +13,8 @@
 // blend's fused multiply-adds are written out explicitly.
 #pragma clang fp contract(off)
 
+#include <type_traits>
+
 #include "common.h"
 #include "scan.h"
 
@@ -166,7 +168,26 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
         corners(g, l, x, idx, wt);
         const TabT *lev = table + ((tile * g.L + l) << g.log2T) * F;
         VT v[8];
-        if constexpr (F == 2) {
+        if constexpr (F == 2 && std::is_same<TabT, __hip_bfloat16>::value) {
+            // BF16 entries are 4 bytes: one 16-byte load covers an aligned
+            // quad of slots, which holds both x-neighbours for three pairs in four
+            const uint4 *lev4 = reinterpret_cast<const uint4 *>(lev);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t a = idx[2 * p], b = idx[2 * p + 1];
+                if ((a >> 2) == (b >> 2)) {
+                    const uint4 w4 = lev4[a >> 2];
+                    const uint32_t ka = a & 3u, kb = b & 3u;
+                    const uint32_t wa = (ka & 2u) ? ((ka & 1u) ? w4.w : w4.z) : ((ka & 1u) ? w4.y : w4.x);
+                    const uint32_t wb = (kb & 2u) ? ((kb & 1u) ? w4.w : w4.z) : ((kb & 1u) ? w4.y : w4.x);
+                    v[2 * p] = make_float2(bf16_bits(wa & 0xffffu), bf16_bits(wa >> 16));
+                    v[2 * p + 1] = make_float2(bf16_bits(wb & 0xffffu), bf16_bits(wb >> 16));
+                } else {
+                    v[2 * p] = Entry<F, TabT>::one(lev, a);
+                    v[2 * p + 1] = Entry<F, TabT>::one(lev, b);
+                }
+            }
+        } else if constexpr (F == 2) {
             // corners q and q^1 differ only in x; when their slots are an
             // aligned pair (2m, 2m+1) -- half of all pairs, dense or hashed --
             // one load fetches both: one cache-line request, not two
