@@ -359,12 +359,19 @@ def sweep_bench(args):
         npath = len(snake_path(n, n))
         # the first window also pays for the graph capture and the initial load
         steady = t[1:] if len(t) > 1 else t
+        cm = sw.copy_ms()
         out["grids"].append({"tiles": n * n, "windows": npath, "total_s": round(sum(t), 4),
                              "ms_per_window_step": round(1e3 * float(np.mean(steady)) / steps, 4),
+                             "host_copy_ms_per_move": round(float(np.mean(cm)), 3) if cm else None,
                              "window_ms": [round(1e3 * x, 2) for x in t]})
         log("  sweep %dx%d: %s" % (n, n, json.dumps(out["grids"][-1])))
         win = sw.win
         del sw
+        # hand the grid's pinned host store back (torch caches pinned blocks), so
+        # the next grid's store is allocated afresh
+        torch.cuda.synchronize()
+        if hasattr(torch._C, "_host_emptyCache"):
+            torch._C._host_emptyCache()
     # depth render of one tile, 2048 x 2048 rays, forward only
     nr = args.render_px ** 2
     o, d, _, _ = synth.window_rays(7, nr, margin=0.0)

@@ -192,11 +192,15 @@ class SnakeSweep:
         self.out_tiles = [t for t, _ in leave]
         self.pos = b
         # overlap with the next window: write the leavers back, prefetch the next entering pair
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(self.copy)
         self._writeback()
         if next_b is not None:
             self._prefetch([t for t, _ in self._move_plan(b, next_b)[2]])
         else:
             self.in_tiles = None
+        c1.record(self.copy)
+        self._copy_events.append((c0, c1))
 
     # -- the sweep -----------------------------------------------------------
     def run(self, steps_per_window, batches, graph=True, log=None):
@@ -205,6 +209,7 @@ class SnakeSweep:
         window-local rays for step k at window position pos (device tensors
         of one fixed shape).  Returns per-window times (s)."""
         path = snake_path(self.nx, self.ny)
+        self._copy_events = []
         self._load_window(path[0])
         if len(path) > 1:
             self._prefetch([t for t, _ in self._move_plan(path[0], path[1])[2]])
@@ -241,6 +246,11 @@ class SnakeSweep:
                     self.h[f][t].copy_(self._wview(f)[s])
         torch.cuda.synchronize()
         return times
+
+    def copy_ms(self):
+        """Copy-stream time of each move's host transfers (write-back of the two
+        leaving tiles, prefetch of the next two), in ms, after run()."""
+        return [a.elapsed_time(b) for a, b in self._copy_events]
 
     def trained_steps(self):
         """Adam steps each tile has taken (1, 2 or 4 windows' worth)."""
