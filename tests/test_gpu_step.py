@@ -50,7 +50,8 @@ def gpu_step(w, precision="fp32", occupancy=None):
     # dfeat is compact over the samples kept by early stop: scatter back to [n][32]
     idx = host(nerf.alive_idx)[:nb] if w.early_stop > 0 else np.arange(nb)
     df = np.zeros((n, 32))
-    df[idx, :len(nerf.res) * nerf.F] = host(nerf.dfeat)[:, :nb, :].transpose(1, 0, 2).reshape(nb, -1)
+    W = len(nerf.res) * nerf.F
+    df[idx, :W] = host(nerf.dfeat)[:, :nb, :].transpose(1, 0, 2).reshape(nb, W)
     out["dfeat"] = df
     nerf.adam()
     sync()
@@ -278,3 +279,24 @@ def test_occupancy_update_from_the_field(orc):
     frac = nerf.occupied_fraction()
     mean_occ = (ref > min(0.01, ref.mean())).mean()
     assert abs(frac - mean_occ) < 0.01, (frac, mean_occ)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_step_with_no_samples(orc, prec):
+    """Every ray misses the tile: no samples anywhere in the step.  The
+    composite is the background 0, the loss is the targets' mean square, all
+    gradients are zero and Adam leaves the table and the networks unchanged
+    (the full-tile shapes and launch configuration, early stop on)."""
+    w = synth.full_tile(seed=0, n_rays=2048, render_targets=False)
+    w.rays_o = np.tile([5.0, 5.0, 2.0], (w.n_rays, 1))
+    w.rays_d = np.tile([0.0, 0.0, -1.0], (w.n_rays, 1))
+    nerf = make_nerf(w, prec)
+    g = gpu_step(w, prec)
+    assert g["n"] == 0 and g["n_bwd"] == 0
+    assert np.all(g["rgb_out"] == 0.0) and np.all(g["opacity"] == 0.0)
+    ref_loss = float(np.sum(w.target.astype(np.float64) ** 2) / (3.0 * w.n_rays))
+    assert_values(g["loss"], ref_loss, 1e-5, 0.0, "loss")
+    assert not np.any(g["dtable"]) and not np.any(g["dW"])
+    assert np.array_equal(g["table_new"], host(nerf.table)) and np.array_equal(g["mlp_new"], host(nerf.params))
+    from paper_2507_01631_amd import _lib as L
+    assert L.snake_check_device_error() == 0
