@@ -292,8 +292,10 @@ int snake_convert_bf16(const float *src, int64_t n, void *dst, snake_stream_t st
  * of dtable [K][L][T][F] float; dfeat [L][n][F] float (compact, indexed by j).
  * With a workspace the corner contributions are binned by table slot (count,
  * scan, scatter) and summed exactly in 64-bit fixed point: each contribution
- * is rounded once to an integer multiple of 2^-E_l, where E_l = 24 - e and
- * 2^(e-1) <= max|dfeat of level l| < 2^e, then every table entry receives its
+ * is rounded once to an integer multiple of 2^-E_l, where E_l = 23 - e and
+ * 2^(e-1) <= max|dfeat of level l| < 2^e (consecutive samples of a ray that
+ * share a slot are first summed in pieces of at most three, so every stored
+ * partial sum fits 26 bits), then every table entry receives its
  * sum, rounded once to FP32.  The result is deterministic (the same bits for
  * any grid or scheduling).  A level whose dfeat holds a non-finite value adds
  * nothing and raises SNAKE_DEVERR_NONFINITE.  The workspace size decides how

@@ -322,14 +322,14 @@ __device__ __forceinline__ bool grad_nonzero(const typename Vec<F>::T &gv)
 
 // Fixed-point exponent of a level from the bit pattern of its largest
 // |dfeat| (m < 2^e): a contribution w g (w <= 1) becomes the integer
-// rint(w g 2^(24-e)), |q| <= 2^24, and a merged run of at most 64 of them
-// stays below 2^30.
+// rint(w g 2^(23-e)), |q| <= 2^23, and a merged piece of at most kRunCap = 3
+// of them stays below 2^25, inside the 26-bit fields of an item.
 __device__ __forceinline__ int level_exponent(uint32_t maxbits)
 {
     if (maxbits == 0u || maxbits >= 0x7f800000u) return 0;
     int e;
     frexpf(__uint_as_float(maxbits), &e);
-    return 24 - e;
+    return 23 - e;
 }
 
 // A level takes part when it has a nonzero, finite largest gradient.
@@ -338,53 +338,122 @@ __device__ __forceinline__ bool level_ok(uint32_t maxbits) { return maxbits != 0
 __device__ __forceinline__ int32_t quantise(float v, int E) { return (int32_t)rintf(ldexpf(v, E)); }
 
 // Consecutive lanes (consecutive samples of a ray) often hit the same slot on
-// coarse levels.  Sum each run of equal keys across the wavefront (segmented
-// inclusive scan) so only the run's last lane emits an item.  Returns whether
-// this lane emits; v holds the run total there.  The values are already
-// integers (fixed point), so merging only regroups exact sums and the result
-// does not depend on which lanes happened to share a wavefront.
-template <int F>
-__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, int32_t (&v)[F])
+// coarse levels.  Each run of equal keys across the wavefront is cut into
+// pieces of at most kRunCap lanes counted from the run's first lane; a
+// piece's last lane emits one item holding the piece's sum.  run_pieces
+// gives this lane's piece start ps, whether it emits (ptail), and the
+// wave's active lanes and piece heads; when no run is longer than one lane
+// it reports exactly that (pheads == acts) without the rest.
+constexpr int kRunCap = 3;
+
+__device__ __forceinline__ void run_pieces(uint32_t key, bool act, unsigned long long &acts,
+                                           unsigned long long &pheads, int &ps, bool &ptail)
 {
     const int lane = lane_id();
     const uint32_t pk = __shfl_up(key, 1, 64);
     const bool pa = __shfl_up(act ? 1 : 0, 1, 64) != 0;
     const bool head = act && (lane == 0 || !pa || pk != key);
     const unsigned long long heads = __ballot(head);
-    const unsigned long long acts = __ballot(act);
-    if (heads == acts) return act;                 // no run longer than one lane
+    acts = __ballot(act);
+    if (heads == acts) {
+        pheads = heads;
+        ps = lane;
+        ptail = act;
+        return;
+    }
     const uint32_t nk = __shfl_down(key, 1, 64);
     const bool na = __shfl_down(act ? 1 : 0, 1, 64) != 0;
-    const bool tail = act && (lane == 63 || !na || nk != key);
+    const bool rtail = act && (lane == 63 || !na || nk != key);
     // start of this lane's run: highest head at or below this lane
     const unsigned long long le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
     const unsigned long long hb = heads & le;
     const int rs = hb ? 63 - __clzll((long long)hb) : lane;
-    // Scan steps d = 1, 2, 4, ... complete every run of up to 2d lanes, so a
-    // step is needed only while some run is longer: c holds the lanes that
-    // end d consecutive continuation lanes (active lanes that are not a run's
-    // head), and is zero once no run exceeds the steps taken.  The count is
-    // the same on every lane (it comes from ballots).
-    unsigned long long c = acts & ~heads;
+    const int off = lane - rs;
+    ps = rs + (off / kRunCap) * kRunCap;
+    pheads = __ballot(act && off % kRunCap == 0);
+    ptail = act && (rtail || off % kRunCap == kRunCap - 1);
+}
+
+// Sum each piece across the wavefront (segmented inclusive scan); returns
+// whether this lane emits, with v the piece total there.  The values are
+// integers (fixed point), so merging only regroups exact sums and the
+// result does not depend on which lanes happened to share a wavefront.
+template <int F>
+__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, int32_t (&v)[F])
+{
+    const int lane = lane_id();
+    unsigned long long acts, pheads;
+    int ps;
+    bool ptail;
+    run_pieces(key, act, acts, pheads, ps, ptail);
+    if (pheads == acts) return act;                // no piece longer than one lane
+    // Scan steps d = 1, 2, ... complete every piece of up to 2d lanes; c holds
+    // the lanes that end d consecutive continuation lanes (active lanes that
+    // are not a piece's head) and is zero once no piece exceeds the steps
+    // taken.  The count is the same on every lane (it comes from ballots).
+    unsigned long long c = acts & ~pheads;
     for (int d = 1; d < 64 && c != 0ull; d <<= 1) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             const int32_t u = __shfl_up(v[f], d, 64);
-            if (lane - d >= rs) v[f] += u;
+            if (lane - d >= ps) v[f] += u;
         }
         c &= c >> d;
     }
-    return tail;
+    return ptail;
 }
 
-// The lane that emits a run's item (its last lane); the same decision as
-// merge_runs, without the sums (the count pass needs only how many items).
+// The lane that emits a piece's item; the same decision as merge_runs,
+// without the sums (the count pass needs only how many items).
 __device__ __forceinline__ bool run_tail(uint32_t key, bool act)
 {
-    const int lane = lane_id();
-    const uint32_t nk = __shfl_down(key, 1, 64);
-    const bool na = __shfl_down(act ? 1 : 0, 1, 64) != 0;
-    return act && (lane == 63 || !na || nk != key);
+    unsigned long long acts, pheads;
+    int ps;
+    bool ptail;
+    run_pieces(key, act, acts, pheads, ps, ptail);
+    return ptail;
+}
+
+// An item is one 64-bit word (F = 1, 2) or two (F = 4): the slot within its
+// bin in the low binshift bits (at most 13), then F fixed-point values of 26
+// bits each (two's complement), the fourth feature's pair in the second word.
+constexpr int kValBits = 26;
+constexpr uint64_t kValMask = (1ull << kValBits) - 1ull;
+
+template <int F>
+struct ItemFmt {
+    static constexpr int NW = F == 4 ? 2 : 1;
+};
+
+__device__ __forceinline__ int32_t val26(uint64_t field)
+{
+    return (int32_t)((uint32_t)(field & kValMask) << (32 - kValBits)) >> (32 - kValBits);
+}
+
+template <int F>
+__device__ __forceinline__ void item_pack(unsigned long long *dst, uint32_t slot, int sb, const int32_t *v)
+{
+    uint64_t w0 = (uint64_t)slot;
+    w0 |= ((uint64_t)(uint32_t)v[0] & kValMask) << sb;
+    if constexpr (F >= 2) w0 |= ((uint64_t)(uint32_t)v[1] & kValMask) << (sb + kValBits);
+    dst[0] = w0;
+    if constexpr (F == 4)
+        dst[1] = ((uint64_t)(uint32_t)v[2] & kValMask) | (((uint64_t)(uint32_t)v[3] & kValMask) << kValBits);
+}
+
+template <int F>
+__device__ __forceinline__ void item_unpack(const unsigned long long *src, uint32_t smask, int sb, uint32_t &slot,
+                                            int32_t (&v)[F])
+{
+    const uint64_t w0 = src[0];
+    slot = (uint32_t)w0 & smask;
+    v[0] = val26(w0 >> sb);
+    if constexpr (F >= 2) v[1] = val26(w0 >> (sb + kValBits));
+    if constexpr (F == 4) {
+        const uint64_t w1 = src[1];
+        v[2] = val26(w1);
+        v[3] = val26(w1 >> kValBits);
+    }
 }
 
 // Runs of equal slots along a ray are worth merging only where cells are
@@ -509,7 +578,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                                                           const int32_t *__restrict__ offsets,
                                                           const int32_t *__restrict__ counts,
                                                           const uint32_t *__restrict__ lmax,
-                                                          uint32_t *__restrict__ items)
+                                                          unsigned long long *__restrict__ items)
 {
     typedef typename Vec<F>::T VT;
     extern __shared__ int sm[];
@@ -611,16 +680,14 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 }
             __syncthreads();
             // 4. write out: consecutive threads, consecutive slots of a bin
-            const uint32_t lbase = (uint32_t)lr << bp.kt2_log2;
+            const uint32_t smask = (1u << bp.binshift) - 1u;
             for (int j = threadIdx.x; j < total; j += blockDim.x) {
                 const uint32_t k = skey[j];
                 const int bl = (int)(k >> bp.binshift);
                 const int gb = gbase[bl];
                 if (gb < 0) continue;
-                uint32_t *it = items + (int64_t)(gb + (j - hoff[bl])) * (1 + F);
-                it[0] = lbase + k;
-#pragma unroll
-                for (int f = 0; f < F; ++f) it[1 + f] = (uint32_t)sval[j * F + f];
+                item_pack<F>(items + (int64_t)(gb + (j - hoff[bl])) * ItemFmt<F>::NW, k & smask, bp.binshift,
+                             sval + j * F);
             }
             __syncthreads();
         }
@@ -717,10 +784,25 @@ __global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long *__res
         p[i] = 0ull;
 }
 
+// Largest bin b (in [0, nb)) whose first item index offsets[b nblk] is at
+// most i: the bin holding item i (empty bins before it share its start).
+__device__ __forceinline__ int bin_of_item(const int32_t *offsets, int nblk, int nb, int64_t i)
+{
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)offsets[(int64_t)mid * nblk] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int F>
 __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32_t *__restrict__ offsets,
                                                          int nblk, const int64_t *__restrict__ n_items,
-                                                         const uint32_t *__restrict__ items,
+                                                         const unsigned long long *__restrict__ items,
                                                          const uint32_t *__restrict__ lmax,
                                                          unsigned long long *__restrict__ acc64)
 {
@@ -728,12 +810,13 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32
     const int64_t total = *n_items;
     const int slots = 1 << bp.binshift;
     const uint32_t smask = (uint32_t)slots - 1;
+    constexpr int NW = ItemFmt<F>::NW;
     for (int64_t c0 = (int64_t)blockIdx.x * kReduceChunk; c0 < total; c0 += (int64_t)gridDim.x * kReduceChunk) {
         const int64_t c1 = c0 + kReduceChunk < total ? c0 + kReduceChunk : total;
-        int bfirst = (int)(items[c0 * (1 + F)] >> bp.binshift);
-        int blast = (int)(items[(c1 - 1) * (1 + F)] >> bp.binshift);
-        bfirst = bfirst < 0 ? 0 : (bfirst >= bp.nb ? bp.nb - 1 : bfirst);
-        blast = blast < bfirst ? bfirst : (blast >= bp.nb ? bp.nb - 1 : blast);
+        // the bins holding the chunk's first and last items (items carry only
+        // their slot within the bin)
+        const int bfirst = bin_of_item(offsets, nblk, bp.nb, c0);
+        const int blast = bin_of_item(offsets, nblk, bp.nb, c1 - 1);
         for (int b = bfirst; b <= blast; ++b) {
             const int64_t bs = offsets[(int64_t)b * nblk];
             const int64_t be = b + 1 < bp.nb ? (int64_t)offsets[(int64_t)(b + 1) * nblk] : total;
@@ -747,22 +830,24 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32
             __syncthreads();
             // kRU items per thread per round keep enough loads in flight
             for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kRU * blockDim.x) {
-                uint32_t w[kRU][1 + F];
+                unsigned long long w[kRU][NW];
 #pragma unroll
                 for (int u = 0; u < kRU; ++u) {
                     const int64_t i = i0 + (int64_t)u * blockDim.x;
                     if (i < hi) {
 #pragma unroll
-                        for (int k = 0; k <= F; ++k) w[u][k] = items[i * (1 + F) + k];
+                        for (int k = 0; k < NW; ++k) w[u][k] = items[i * NW + k];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kRU; ++u) {
                     if (i0 + (int64_t)u * blockDim.x < hi) {
+                        uint32_t slot;
+                        int32_t v[F];
+                        item_unpack<F>(w[u], smask, bp.binshift, slot, v);
 #pragma unroll
                         for (int f = 0; f < F; ++f)
-                            atomicAdd(&acc[(w[u][0] & smask) * F + f],
-                                      (unsigned long long)(long long)(int32_t)w[u][1 + f]);
+                            atomicAdd(&acc[slot * F + f], (unsigned long long)(long long)v[f]);
                     }
                 }
             }
@@ -802,7 +887,7 @@ struct BinWs {
     int64_t *bsum, *n_items;
     uint32_t *lmax;
     unsigned long long *acc64;
-    uint32_t *items;
+    unsigned long long *items;
     int64_t item_cap;
 };
 
@@ -816,7 +901,7 @@ static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F, int kt2_log2)
     const int64_t ncnt = (int64_t)nb * kBinBlocks;
     return align256((size_t)SNAKE_MAX_LEVELS * 4) + 2 * align256((size_t)ncnt * 4) +
            align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 + align256(((size_t)lg << kt2_log2) * F * 8) +
-           align256((size_t)n * lg * 8 * (1 + F) * 4);
+           align256((size_t)n * lg * 8 * (F == 4 ? 2 : 1) * 8);
 }
 
 static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
@@ -1033,7 +1118,7 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         const int64_t n_acc = ((int64_t)lgp << bp.kt2_log2) * F;
         w.acc64 = reinterpret_cast<unsigned long long *>(p);
         p += align256((size_t)n_acc * 8);
-        w.items = reinterpret_cast<uint32_t *>(p);
+        w.items = reinterpret_cast<unsigned long long *>(p);
         w.item_cap = n * lgp * 8;
         const int64_t chunks = (w.item_cap + kReduceChunk - 1) / kReduceChunk;
         const unsigned rgrid = (unsigned)(chunks < 4096 ? (chunks > 0 ? chunks : 1) : 4096);
