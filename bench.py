@@ -393,7 +393,8 @@ def convergence(args):
     train from the same initial table and networks on the same cycle of ray
     batches; the held-out ninth view (256^2 rays) is then rendered and its
     PSNR against the scene's own rendering compared (both with early stop
-    only).  With the occupancy grid on, a third BF16 run trains with culling
+    only), as means over --conv-orders orders of the batch cycle.  With the
+    occupancy grid on, one more BF16 run trains with culling
     (grid refreshed every 16 steps from step --conv-occ-start) and gives
     culling's effect on PSNR and on the step time."""
     import torch
@@ -413,9 +414,12 @@ def convergence(args):
                         if G else "off")}
     from paper_2507_01631_amd import TileNeRF, level_resolutions
     g, m = wl.grid, wl.mlp
-    runs = [("fp32", 0), ("bf16", 0)] + ([("bf16", G)] if G else [])
-    for prec, grid in runs:
-        name = prec if grid == 0 else prec + "_grid"
+    # the FP32 trajectory is sensitive to last-bit changes, so the two forms
+    # are compared over several orders of the batches (offsets of the cycle)
+    offsets = [0, 1, 3, 5, 2, 4, 6, 7][:max(1, args.conv_orders)]
+    runs = [(p, 0, o) for o in offsets for p in ("fp32", "bf16")] + ([("bf16", G, 0)] if G else [])
+    for prec, grid, off in runs:
+        name = (prec if grid == 0 else prec + "_grid") + ("" if off == 0 else "_order%d" % off)
         nerf = TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
                         log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
                         colour_out=m.colour_out, boxes=wl.boxes, zband=wl.zband, samples=wl.samples_per_ray,
@@ -425,7 +429,7 @@ def convergence(args):
         t0 = time.perf_counter()
         kept = 0
         for k in range(steps):
-            b = k % nb
+            b = (k + off) % nb
             sl = slice(b * R, (b + 1) * R)
             if nerf.G and k >= args.conv_occ_start and k % 16 == 0:
                 nerf.update_occupancy()
@@ -450,7 +454,13 @@ def convergence(args):
             out[name]["occupied_fraction"] = round(nerf.occupied_fraction(), 4)
         log("  convergence %s: %s" % (name, json.dumps(out[name])))
         del nerf
-    out["psnr_gap_db"] = round(out["bf16"]["psnr_db"] - out["fp32"]["psnr_db"], 3)
+
+    def mean_psnr(p):
+        return float(np.mean([out[p + ("" if o == 0 else "_order%d" % o)]["psnr_db"] for o in offsets]))
+    out["orders"] = offsets
+    out["psnr_fp32_mean_db"] = round(mean_psnr("fp32"), 3)
+    out["psnr_bf16_mean_db"] = round(mean_psnr("bf16"), 3)
+    out["psnr_gap_db"] = round(out["psnr_bf16_mean_db"] - out["psnr_fp32_mean_db"], 3)
     if G:
         out["culling_psnr_delta_db"] = round(out["bf16_grid"]["psnr_db"] - out["bf16"]["psnr_db"], 3)
         out["culling_speedup"] = round(out["bf16"]["ms_per_step"] / out["bf16_grid"]["ms_per_step"], 3)
@@ -496,6 +506,8 @@ def main():
     ap.add_argument("--convergence-steps", type=int, default=0,
                     help="also train FP32 and BF16 this many steps and compare held-out PSNR")
     ap.add_argument("--conv-rays", type=int, default=1 << 17)
+    ap.add_argument("--conv-orders", type=int, default=2,
+                    help="batch orders each form trains on in the convergence leg (PSNR means compared)")
     ap.add_argument("--conv-occupancy", type=int, default=1,
                     help="add a BF16 convergence run with a 128^3 occupancy grid")
     ap.add_argument("--conv-occ-start", type=int, default=256, help="first step that updates the grid")
