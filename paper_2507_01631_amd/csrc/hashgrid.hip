@@ -268,7 +268,8 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 // the footprint, far below the rate at which the samples produce corner
 // gradients (L*8*F per sample).  The binned adjoint therefore sorts the
 // corner contributions by table slot before adding them:
-//   count   per (bin, block) how many (slot, w*g) items a block's samples make
+//   count   per (bin, block) how many (slot, w*g) items a block's samples
+//           make, and each level's largest |dfeat|
 //   scan    exclusive offsets, bin-major, so each bin's items are contiguous
 //   scatter write the items to their bin (LDS cursors per block)
 //   reduce  per chunk of items: add into a 64 KB LDS copy of the bin's slots,
@@ -279,13 +280,14 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 //
 // LDS float atomics are slow on this chip (about 2e11/s) while LDS integer
 // atomics are about 20x faster, so the sums are taken in fixed point: every
-// contribution v becomes the int32 rint(v 2^E_l), with E_l fixed per level
-// from the level's largest |dfeat| (a merged item is at most 64 of them, each
-// times a weight <= 1, so |q| < 2^30), and is added into 64-bit sums.
-// Integer sums do not depend on the order of addition, so the result is the
-// same bits whatever the chunking, the scheduling or the grid.  Consecutive
-// samples of a ray that share a corner are first merged across the
-// wavefront, which shortens the item list on the coarse levels.
+// contribution v becomes the integer rint(v 2^E_l), with E_l fixed per level
+// from the level's largest |dfeat| (|q| <= 2^23), and is added into 64-bit
+// sums.  Integer sums do not depend on the order of addition, so the result
+// is the same bits whatever the chunking, the scheduling or the grid.
+// Consecutive samples of a ray that share a corner are first merged across
+// the wavefront in pieces of up to three (each stored sum fits 26 bits),
+// which shortens the item list on the coarse levels; an item is one 64-bit
+// word for F <= 2.
 
 constexpr int kBinBlocks = 1024;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
@@ -319,6 +321,10 @@ __device__ __forceinline__ bool grad_nonzero(const typename Vec<F>::T &gv)
     for (int f = 0; f < F; ++f) any |= Vec<F>::get(gv, f) != 0.0f;
     return any;
 }
+
+// |x| as float bits (non-negative floats order as unsigned integers).
+__device__ __forceinline__ uint32_t absbits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
 // Fixed-point exponent of a level from the bit pattern of its largest
 // |dfeat| (m < 2^e): a contribution w g (w <= 1) becomes the integer
@@ -466,12 +472,14 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
                                                         const int32_t *__restrict__ sidx, int64_t n,
                                                         const int64_t *__restrict__ n_dev,
                                                         const float *__restrict__ dfeat,
-                                                        const uint32_t *__restrict__ lmax,
+                                                        uint32_t *__restrict__ lmax,
                                                         int32_t *__restrict__ counts)
 {
     typedef typename Vec<F>::T VT;
     __shared__ int hist[kMaxBins];
+    __shared__ uint32_t hmax[SNAKE_MAX_LEVELS];
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) hist[b] = 0;
+    if (threadIdx.x < SNAKE_MAX_LEVELS) hmax[threadIdx.x] = 0u;
     __syncthreads();
     const int64_t ne = effective_n(n, n_dev);
     const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
@@ -494,8 +502,21 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
             const int l = bp.l0 + lr;
             const bool dense_l = (g.dense_bits >> l) & 1u;
             const bool merge_l = g.res[l] <= kMergeMaxRes;
-            bool act = valid && tile_ok && level_ok(lmax[l]);
-            if (act) act = grad_nonzero<F>(*reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F));
+            // whether the sample contributes does not depend on its level's
+            // largest |dfeat| (the scatter emits the same items, with zero
+            // values for a level that holds a non-finite value); that maximum
+            // is taken here, for the scatter's fixed-point scale
+            bool act = false;
+            uint32_t gm = 0u;
+            if (valid && tile_ok) {
+                const VT gv = *reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F);
+                act = grad_nonzero<F>(gv);
+#pragma unroll
+                for (int f = 0; f < F; ++f) gm = umax(gm, absbits(Vec<F>::get(gv, f)));
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) gm = umax(gm, (uint32_t)__shfl_xor((int)gm, d, 64));
+            if (lane == 0 && gm) atomicMax(&hmax[lr], gm);
             uint32_t idx[8];
             float wt[8];
             corners(g, l, x, idx, wt);
@@ -520,6 +541,11 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
     }
     __syncthreads();
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) counts[(int64_t)b * gridDim.x + blockIdx.x] = hist[b];
+    if (threadIdx.x < bp.lg && hmax[threadIdx.x]) {
+        const uint32_t m = hmax[threadIdx.x];
+        if (m >= 0x7f800000u && g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_NONFINITE);
+        atomicMax(&lmax[bp.l0 + threadIdx.x], m);
+    }
 }
 
 // Exclusive prefix sum of cnt[0..m) into off[0..m) by the 256 threads of a
@@ -620,11 +646,15 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             const bool merge_l = g.res[l] <= kMergeMaxRes;
             const uint32_t lm = lmax[l];
             const int E = level_exponent(lm);
-            bool act = valid && tile_ok && level_ok(lm);
+            const bool lok = level_ok(lm);
+            // the same decision as the count pass; a level without a finite,
+            // nonzero maximum emits its items with zero values
+            bool act = false;
             VT gv = {};
-            if (act) {
+            if (valid && tile_ok) {
                 gv = *reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F);
                 act = grad_nonzero<F>(gv);
+                if (!lok) gv = VT{};
             }
             uint32_t idx[8];
             float wt[8];
@@ -695,64 +725,6 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
 }
 
 
-
-// lmax[l] = largest |dfeat[l][s][f]| over s < ne, as float bits (non-negative
-// floats order as unsigned integers).  Grid: (chunks, L).  A non-finite value
-// raises SNAKE_DEVERR_NONFINITE and its level contributes nothing.  Each
-// thread keeps four 16-byte loads in flight when every level's row is 16-byte
-// aligned (vec: dfeat 16-byte aligned and n F a multiple of 4), else eight
-// scalar loads.
-__device__ __forceinline__ uint32_t absbits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
-__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
-
-__global__ __launch_bounds__(256) void level_absmax_kernel(const float *__restrict__ dfeat, int64_t n,
-                                                           const int64_t *__restrict__ n_dev, int F, int vec,
-                                                           uint32_t *__restrict__ lmax, unsigned int *err)
-{
-    __shared__ uint32_t red[4];
-    const int l = blockIdx.y;
-    const int64_t cnt = effective_n(n, n_dev) * F;
-    const float *src = dfeat + (int64_t)l * n * F;
-    uint32_t m = 0u;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (vec) {
-        const float4 *src4 = reinterpret_cast<const float4 *>(src);
-        const int64_t c4 = cnt / 4;
-        for (int64_t i0 = t0; i0 < c4; i0 += 4 * stride) {
-            float4 b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t i = i0 + u * stride;
-                b[u] = i < c4 ? src4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                m = umax(m, umax(umax(absbits(b[u].x), absbits(b[u].y)), umax(absbits(b[u].z), absbits(b[u].w))));
-        }
-        for (int64_t i = c4 * 4 + t0; i < cnt; i += stride) m = umax(m, absbits(src[i]));   // tail
-    } else {
-        for (int64_t i0 = t0; i0 < cnt; i0 += 8 * stride) {
-            uint32_t b[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t i = i0 + u * stride;
-                b[u] = i < cnt ? absbits(src[i]) : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) m = umax(m, b[u]);
-        }
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) m = umax(m, __shfl_xor(m, d, 64));
-    if (lane_id() == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < 4; ++w) m = umax(m, red[w]);
-        if (m >= 0x7f800000u && err) atomicOr(err, (unsigned)SNAKE_DEVERR_NONFINITE);
-        if (m) atomicMax(&lmax[l], m);
-    }
-}
 
 // dst = src rounded to BF16 (nearest, ties to even; NaN stays NaN).
 __global__ __launch_bounds__(256) void to_bf16_kernel(const float4 *__restrict__ src, int64_t n4,
@@ -1091,15 +1063,8 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     // per-level scale of the fixed-point sums, from the largest |dfeat|
     uint32_t *lmax = static_cast<uint32_t *>(workspace);
     unsigned int *err = device_error_word();
+    // the per-level maxima are taken by each pass's count kernel
     zero_u32_kernel<<<1, 64, 0, st>>>(lmax, g.L);
-    {
-        const int64_t vals = n * F;
-        unsigned gx = (unsigned)((vals + 256 * 8 - 1) / (256 * 8));
-        const unsigned cap_x = (unsigned)(num_cus() * 16 / g.L + 1);
-        gx = gx < 1 ? 1 : (gx > cap_x ? cap_x : gx);
-        const int vec = (vals % 4 == 0 && (reinterpret_cast<uintptr_t>(dfeat) & 15u) == 0) ? 1 : 0;
-        level_absmax_kernel<<<dim3(gx, g.L), 256, 0, st>>>(dfeat, n, n_dev, F, vec, lmax, err);
-    }
     for (int l0 = 0; l0 < g.L; l0 += lg) {
         const int lgp = l0 + lg <= g.L ? lg : g.L - l0;
         const BinPlan bp = make_plan(g.L, F, gd->log2_table, K, l0, lgp);

@@ -459,3 +459,38 @@ def test_hashgrid_bwd_binned_is_deterministic(L, orc):
         assert torch.equal(o, outs[0])
     ref = orc.hashgrid_bwd(res, c["log2T"], table.shape, pos, dfeat.astype(np.float64))
     assert_grad(host(outs[0]), ref, 1e-4, "dtable")
+
+
+@pytest.mark.parametrize("lg", [1, 3, 0])
+def test_hashgrid_bwd_binned_nonfinite_level_adds_nothing(L, orc, lg):
+    """A level whose feature gradient holds an inf or a NaN leaves its table
+    gradient untouched and raises the non-finite flag; the other levels are
+    summed as usual, in every split of the levels into passes."""
+    rng = np.random.default_rng(23)
+    n = 20011
+    c, res, table = _grid_setup(L, orc, "tiny", rng)
+    pos = _positions(rng, n)
+    dfeat = rng.normal(size=(n, c["L"] * c["F"]))
+    bad = 3
+    dfeat[17, bad * 2] = np.inf
+    dfeat[9001, bad * 2 + 1] = np.nan
+    g = L.grid_desc(res, c["F"], c["log2T"])
+    dfd = dev(dfeat.reshape(n, c["L"], c["F"]).transpose(1, 0, 2).astype(np.float32))
+    ws = torch.empty(L.snake_hashgrid_bwd_workspace_bytes(g, 1, n, c["L"]), dtype=torch.uint8, device=DEV)
+    saved = L.snake_tune_get("bin_levels_per_pass")
+    try:
+        L.snake_tune_set("bin_levels_per_pass", lg)
+        dtab = torch.zeros(table.shape, device=DEV)
+        L.snake_hashgrid_bwd(g, 1, dev(pos), None, None, n, None, dfd, dtab, ws)
+        sync()
+    finally:
+        L.snake_tune_set("bin_levels_per_pass", saved)
+    assert L.snake_check_device_error() == L.SNAKE_DEVERR_NONFINITE
+    got = host(dtab)
+    assert np.all(got[:, bad] == 0.0)
+    clean = dfeat.astype(np.float32).astype(np.float64)
+    clean[:, bad * 2:bad * 2 + 2] = 0.0
+    dpad = np.zeros((n, 32))
+    dpad[:, :clean.shape[1]] = clean
+    ref = orc.hashgrid_bwd(res, c["log2T"], table.shape, pos, dpad)
+    assert_grad(got, ref, 1e-4, "dtable")
