@@ -13,9 +13,11 @@
 // accumulation; inputs, weights and hidden activations rounded RNE to bf16.
 //
 // The adjoint recomputes activations from the features (or reads them back
-// when the forward stored them), runs the transposed chain, and accumulates weight gradients with
-// MFMA over samples (K = samples) after a per-wave LDS transpose.  Per-block
-// partial sums are reduced in a fixed order by a second kernel.
+// when the forward stored them), runs the transposed chain, and accumulates
+// weight gradients with MFMA over samples (K = samples) after an LDS
+// transpose: per wavefront in the FP32 form, split across the block's four
+// wavefronts in the BF16 form (which then fits two wavefronts per SIMD).
+// Per-block partial sums are reduced in a fixed order by a second kernel.
 #include "common.h"
 
 namespace snake {
@@ -27,8 +29,6 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;   // 4 wavefronts
-constexpr int kStageStride = 20;  // floats per staged row (16 samples + pad)
-constexpr int kStageRows = 128;
 constexpr int kMaxBwdBlocks = 512;
 
 enum Prec { P_F32 = 0, P_BF16 = 1 };
@@ -256,13 +256,15 @@ __device__ __forceinline__ void load_features(const FT *feat, int64_t ld, int64_
 {
     const int q = lane_id() >> 4;
     if (a.F == 2) {             // rows 2m, 2m+1 are the two features of level m: one load
+        // level 8t + 2q + h: a per-lane base and uniform level offsets
+        const FT *base = feat + ((int64_t)(2 * q) * ld + s) * 2;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int p = 16 * t + 4 * q + 2 * h;
                 float2 v = make_float2(0.0f, 0.0f);
-                if (valid && p < a.n_feat) v = load_pair(feat + ((int64_t)(p >> 1) * ld + s) * 2);
+                if (valid && p < a.n_feat) v = load_pair(base + (int64_t)(8 * t + h) * ld * 2);
                 x[t][2 * h] = v.x;
                 x[t][2 * h + 1] = v.y;
             }
@@ -498,93 +500,6 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
 
 // ---- adjoint ----------------------------------------------------------------
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Stage rows row0 + (0..16T-1) of a D-layout tile set as [row][sample].
-template <int T>
-__device__ __forceinline__ void stage(float *st, int row0, const float (&v)[T][4])
-{
-    const int lane = lane_id(), i = lane & 15, q = lane >> 4;
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) st[(row0 + 16 * t + 4 * q + r) * kStageStride + i] = v[t][r];
-}
-
-// acc[to][ti] += dy[16to.. ][samples] . x[16ti.. ][samples]^T over the 16 staged samples.
-template <int PREC, int TO, int TI>
-__device__ __forceinline__ void dw_accumulate(const float *st, int dy0, int x0, f4 (&acc)[TO][TI])
-{
-    const int lane = lane_id(), i = lane & 15, q = lane >> 4;
-    f4 av[TO], bv[TI];
-#pragma unroll
-    for (int to = 0; to < TO; ++to)
-        av[to] = *reinterpret_cast<const f4 *>(st + (dy0 + 16 * to + i) * kStageStride + 4 * q);
-#pragma unroll
-    for (int ti = 0; ti < TI; ++ti)
-        bv[ti] = *reinterpret_cast<const f4 *>(st + (x0 + 16 * ti + i) * kStageStride + 4 * q);
-    if constexpr (PREC == P_F32) {
-#pragma unroll
-        for (int to = 0; to < TO; ++to)
-#pragma unroll
-            for (int ti = 0; ti < TI; ++ti)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    acc[to][ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[to][k], bv[ti][k], acc[to][ti], 0, 0, 0);
-    } else {
-        s4 ab[TO], bb[TI];
-#pragma unroll
-        for (int to = 0; to < TO; ++to) {
-            bf4 t4;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) t4[k] = (__bf16)av[to][k];
-            ab[to] = __builtin_bit_cast(s4, t4);
-        }
-#pragma unroll
-        for (int ti = 0; ti < TI; ++ti) {
-            bf4 t4;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) t4[k] = (__bf16)bv[ti][k];
-            bb[ti] = __builtin_bit_cast(s4, t4);
-        }
-#pragma unroll
-        for (int to = 0; to < TO; ++to)
-#pragma unroll
-            for (int ti = 0; ti < TI; ++ti)
-                acc[to][ti] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab[to], bb[ti], acc[to][ti], 0, 0, 0);
-    }
-}
-
-template <int TO, int TI>
-__device__ __forceinline__ void zero(f4 (&acc)[TO][TI])
-{
-#pragma unroll
-    for (int a = 0; a < TO; ++a)
-#pragma unroll
-        for (int b = 0; b < TI; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-}
-
-// Add a dW tile set into the padded block buffer R (row-major, `cols` wide).
-template <int TO, int TI>
-__device__ __forceinline__ void flush(float *R, int base, int cols, const f4 (&acc)[TO][TI], bool first)
-{
-    const int lane = lane_id(), j = lane & 15, q = lane >> 4;
-#pragma unroll
-    for (int to = 0; to < TO; ++to)
-#pragma unroll
-        for (int ti = 0; ti < TI; ++ti)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float *p = R + base + (16 * to + 4 * q + r) * cols + 16 * ti + j;
-                *p = first ? acc[to][ti][r] : *p + acc[to][ti][r];
-            }
-}
-
 // Padded weight-gradient row of one block and weight set: D1 [64][32] | D2
 // [16][64] | C1 [64][32] | C2 [64][64] (two colour layers) | CO [16][64].
 template <int CL>
@@ -608,30 +523,346 @@ __device__ __forceinline__ int padded_index(const MlpArgs &a, int p)
     return CO + (p - a.off[4]);
 }
 
-// Sum the four wavefronts' weight-gradient tiles in a fixed order into LDS,
-// then copy the padded row out.  Block-uniform: every thread calls it.
-template <int PREC, int CL>
-__device__ void flush_partial(float *R, float *out, const f4 (&acc_d1)[4][2], const f4 (&acc_d2)[1][4],
-                              const f4 (&acc_c1)[4][2], const f4 (&acc_c2)[4][4], const f4 (&acc_co)[1][4])
+// Weight gradients sum over samples, so both factors need samples along K,
+// while the chain leaves lane (i, q) holding rows 4q..4q+3 of sample i: each
+// layer's (dy, x) pair is transposed through LDS before its MFMA.  Two ways
+// to hold the sums:
+//  - per wavefront (FP32 form): a wavefront stages its own 16 samples and
+//    holds the whole of every layer's accumulators; at the end the four
+//    wavefronts' sums are added in a fixed order.  The FP32 fragments fill
+//    half the LDS, so one block runs per CU and block barriers would only
+//    cost.
+//  - split across the block (BF16 form): the four wavefronts stage their
+//    samples side by side ([row][64 samples], BF16 values) and after one
+//    barrier each accumulates a quarter of the layer's 16x16 tiles over all
+//    64 samples, so it holds a quarter of the accumulators.  That brings the
+//    kernel under 256 registers: two wavefronts per SIMD, which hide each
+//    other's latencies.  Two staging buffers alternate, one barrier a layer.
+
+// Tile shape of a layer's weight gradient: TO x TI tiles of 16x16, dy has
+// 16 TO rows and x 16 TI rows; `cols` = 16 TI is the row length in PadRow.
+template <int M>
+struct LayerShape;
+template <>
+struct LayerShape<M_D1> {
+    static constexpr int TO = 4, TI = 2;
+};
+template <>
+struct LayerShape<M_D2> {
+    static constexpr int TO = 1, TI = 4;
+};
+template <>
+struct LayerShape<M_C1> {
+    static constexpr int TO = 4, TI = 2;
+};
+template <>
+struct LayerShape<M_C2> {
+    static constexpr int TO = 4, TI = 4;
+};
+template <>
+struct LayerShape<M_CO> {
+    static constexpr int TO = 1, TI = 4;
+};
+
+template <int CL, int M>
+__device__ constexpr int pad_offset()
 {
     typedef PadRow<CL> PR;
-    static_assert(PR::W <= 4 * kStageRows * kStageStride, "reduction buffer");
-    const int wv = threadIdx.x >> 6;
-    __syncthreads();
-    for (int w = 0; w < kBlock / 64; ++w) {
-        if (wv == w) {
-            flush(R, PR::D1, 32, acc_d1, w == 0);
-            flush(R, PR::D2, 64, acc_d2, w == 0);
-            flush(R, PR::C1, 32, acc_c1, w == 0);
-            if (CL == 2) flush(R, PR::C2, 64, acc_c2, w == 0);
-            flush(R, PR::CO, 64, acc_co, w == 0);
+    return M == M_D1 ? PR::D1 : M == M_D2 ? PR::D2 : M == M_C1 ? PR::C1 : M == M_C2 ? PR::C2 : PR::CO;
+}
+
+template <int N>
+__device__ __forceinline__ void zero(f4 (&acc)[N])
+{
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+template <int PREC, int CL, bool SPLIT>
+struct WGrad;
+
+// ---- per wavefront ----
+constexpr int kWaveStride = 20;  // floats per staged row (16 samples + pad)
+constexpr int kWaveRows = 128;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int PREC, int CL>
+struct WGrad<PREC, CL, false> {
+    static constexpr int kLdsBytes = 4 * kWaveRows * kWaveStride * (int)sizeof(float);
+    static_assert(PadRow<CL>::W * (int)sizeof(float) <= kLdsBytes, "reduction buffer");
+    f4 d1[4 * 2], d2[1 * 4], c1[4 * 2], c2[4 * 4], co[1 * 4];   // tile (to, ti) at to TI + ti
+    float *R, *st;
+
+    __device__ explicit WGrad(void *lds)
+        : R(static_cast<float *>(lds)), st(static_cast<float *>(lds) + (threadIdx.x >> 6) * kWaveRows * kWaveStride)
+    {
+    }
+
+    template <int M>
+    __device__ __forceinline__ auto &acc()
+    {
+        if constexpr (M == M_D1) return d1;
+        else if constexpr (M == M_D2) return d2;
+        else if constexpr (M == M_C1) return c1;
+        else if constexpr (M == M_C2) return c2;
+        else return co;
+    }
+
+    __device__ __forceinline__ void zero_all()
+    {
+        zero(d1);
+        zero(d2);
+        zero(c1);
+        zero(c2);
+        zero(co);
+    }
+
+    // rows row0 + (0..16T-1) of the wavefront's 16 samples as [row][sample]
+    template <int T>
+    __device__ __forceinline__ void stage(int row0, const float (&v)[T][4])
+    {
+        const int lane = lane_id(), i = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) st[(row0 + 16 * t + 4 * q + r) * kWaveStride + i] = v[t][r];
+    }
+
+    // acc += dy . x^T over the wavefront's 16 samples
+    template <int M>
+    __device__ __forceinline__ void layer(const float (&dy)[LayerShape<M>::TO][4],
+                                          const float (&x)[LayerShape<M>::TI][4])
+    {
+        constexpr int TO = LayerShape<M>::TO, TI = LayerShape<M>::TI;
+        f4(&a)[TO * TI] = acc<M>();
+        stage<TO>(0, dy);
+        stage<TI>(16 * TO, x);
+        wave_sync();
+        const int lane = lane_id(), i = lane & 15, q = lane >> 4;
+        f4 av[TO], bv[TI];
+#pragma unroll
+        for (int to = 0; to < TO; ++to) av[to] = *reinterpret_cast<const f4 *>(st + (16 * to + i) * kWaveStride + 4 * q);
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+            bv[ti] = *reinterpret_cast<const f4 *>(st + (16 * TO + 16 * ti + i) * kWaveStride + 4 * q);
+        if constexpr (PREC == P_F32) {
+#pragma unroll
+            for (int to = 0; to < TO; ++to)
+#pragma unroll
+                for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        a[to * TI + ti] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(av[to][k], bv[ti][k], a[to * TI + ti], 0, 0, 0);
+        } else {
+            s4 ab[TO], bb[TI];
+#pragma unroll
+            for (int to = 0; to < TO; ++to) {
+                bf4 t4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) t4[k] = (__bf16)av[to][k];
+                ab[to] = __builtin_bit_cast(s4, t4);
+            }
+#pragma unroll
+            for (int ti = 0; ti < TI; ++ti) {
+                bf4 t4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) t4[k] = (__bf16)bv[ti][k];
+                bb[ti] = __builtin_bit_cast(s4, t4);
+            }
+#pragma unroll
+            for (int to = 0; to < TO; ++to)
+#pragma unroll
+                for (int ti = 0; ti < TI; ++ti)
+                    a[to * TI + ti] =
+                        __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab[to], bb[ti], a[to * TI + ti], 0, 0, 0);
         }
+        wave_sync();
+    }
+
+    // one layer's tiles into the row buffer: the first wavefront stores, the
+    // others add
+    template <int M>
+    __device__ __forceinline__ void add_layer(bool first)
+    {
+        constexpr int TO = LayerShape<M>::TO, TI = LayerShape<M>::TI, cols = 16 * TI;
+        const f4(&a)[TO * TI] = acc<M>();
+        const int lane = lane_id(), j = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int to = 0; to < TO; ++to)
+#pragma unroll
+            for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float *p = R + pad_offset<CL, M>() + (16 * to + 4 * q + r) * cols + 16 * ti + j;
+                    *p = first ? a[to * TI + ti][r] : *p + a[to * TI + ti][r];
+                }
+    }
+
+    // the four wavefronts' sums added in a fixed order, then the padded row
+    // out.  Block-uniform: every thread calls it.
+    __device__ void flush(float *out)
+    {
+        const int wv = threadIdx.x >> 6;
+        __syncthreads();
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (wv == w) {
+                add_layer<M_D1>(w == 0);
+                add_layer<M_D2>(w == 0);
+                add_layer<M_C1>(w == 0);
+                if (CL == 2) add_layer<M_C2>(w == 0);
+                add_layer<M_CO>(w == 0);
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < PadRow<CL>::W / 4; e += kBlock)
+            reinterpret_cast<f4 *>(out)[e] = reinterpret_cast<const f4 *>(R)[e];
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < PR::W / 4; e += kBlock)
-        reinterpret_cast<f4 *>(out)[e] = reinterpret_cast<const f4 *>(R)[e];
-    __syncthreads();
-}
+};
+
+// ---- split across the block ----
+template <int PREC>
+struct StageT {
+    typedef float T;
+    static constexpr int stride = 68;   // 64 samples + pad, rows 16-byte aligned
+};
+template <>
+struct StageT<P_BF16> {
+    typedef __bf16 T;
+    static constexpr int stride = 72;
+};
+constexpr int kStageRows = 128;         // the largest pair: 64 dy rows + 64 x rows
+
+// A wavefront's tiles of a TO x TI tile layer: e = wv NT + j, all in dy row
+// block `to`, x column blocks ti0 + j.
+template <int TO, int TI>
+struct TileSplit {
+    static constexpr int NT = TO * TI / 4;
+    static_assert(NT >= 1 && TI % NT == 0, "a wavefront's tiles share one row block");
+    __device__ static int to(int wv) { return wv * NT / TI; }
+    __device__ static int ti0(int wv) { return wv * NT % TI; }
+};
+
+template <int PREC, int CL>
+struct WGrad<PREC, CL, true> {
+    typedef typename StageT<PREC>::T ST;
+    static constexpr int S = StageT<PREC>::stride, kElems = kStageRows * S;
+    static constexpr int kLdsBytes = 2 * kElems * (int)sizeof(ST);
+    f4 d1[TileSplit<4, 2>::NT], d2[TileSplit<1, 4>::NT], c1[TileSplit<4, 2>::NT], c2[TileSplit<4, 4>::NT],
+        co[TileSplit<1, 4>::NT];
+    ST *buf;
+    int pb;                     // buffer of the next layer (block-uniform)
+
+    __device__ explicit WGrad(void *lds) : buf(static_cast<ST *>(lds)), pb(0) {}
+
+    template <int M>
+    __device__ __forceinline__ auto &acc()
+    {
+        if constexpr (M == M_D1) return d1;
+        else if constexpr (M == M_D2) return d2;
+        else if constexpr (M == M_C1) return c1;
+        else if constexpr (M == M_C2) return c2;
+        else return co;
+    }
+
+    __device__ __forceinline__ void zero_all()
+    {
+        zero(d1);
+        zero(d2);
+        zero(c1);
+        zero(c2);
+        zero(co);
+    }
+
+    // rows row0 + (0..16T-1) of the wavefront's 16 samples into columns 16 wv + i
+    template <int T>
+    __device__ __forceinline__ void stage(ST *b, int row0, const float (&v)[T][4])
+    {
+        const int lane = lane_id(), i = lane & 15, q = lane >> 4, col = 16 * (int)(threadIdx.x >> 6) + i;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) b[(row0 + 16 * t + 4 * q + r) * S + col] = (ST)v[t][r];
+    }
+
+    // acc[j] += dy[16 to.. ] . x[16 (ti0 + j).. ]^T over the block's 64
+    // samples; lane (i, q) supplies samples 16q..16q+15 of row i to both
+    // operands
+    template <int M>
+    __device__ __forceinline__ void layer(const float (&dy)[LayerShape<M>::TO][4],
+                                          const float (&x)[LayerShape<M>::TI][4])
+    {
+        constexpr int TO = LayerShape<M>::TO, TI = LayerShape<M>::TI;
+        typedef TileSplit<TO, TI> TS;
+        f4(&a)[TS::NT] = acc<M>();
+        ST *b = buf + pb * kElems;
+        pb ^= 1;
+        stage<TO>(b, 0, dy);
+        stage<TI>(b, 16 * TO, x);
+        __syncthreads();
+        const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+        const ST *pa = b + (16 * TS::to(wv) + i) * S + 16 * q;
+        const ST *pbx = b + (16 * TO + 16 * TS::ti0(wv) + i) * S + 16 * q;
+        if constexpr (PREC == P_F32) {
+            f4 av[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) av[h] = *reinterpret_cast<const f4 *>(pa + 4 * h);
+#pragma unroll
+            for (int j = 0; j < TS::NT; ++j)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const f4 bv = *reinterpret_cast<const f4 *>(pbx + 16 * j * S + 4 * h);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        a[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h][k], bv[k], a[j], 0, 0, 0);
+                }
+        } else {
+            bf8 av[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) av[h] = *reinterpret_cast<const bf8 *>(pa + 8 * h);
+#pragma unroll
+            for (int j = 0; j < TS::NT; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf8 bv = *reinterpret_cast<const bf8 *>(pbx + 16 * j * S + 8 * h);
+                    a[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[h], bv, a[j], 0, 0, 0);
+                }
+        }
+    }
+
+    // this wavefront's tiles of a layer into the padded row; the four
+    // wavefronts' tiles cover it
+    template <int M>
+    __device__ __forceinline__ void store_layer(float *out)
+    {
+        constexpr int TO = LayerShape<M>::TO, TI = LayerShape<M>::TI, cols = 16 * TI;
+        typedef TileSplit<TO, TI> TS;
+        const f4(&a)[TS::NT] = acc<M>();
+        const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+        const int to = TS::to(wv), ti0 = TS::ti0(wv);
+        float *o = out + pad_offset<CL, M>();
+#pragma unroll
+        for (int j = 0; j < TS::NT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[(16 * to + 4 * q + r) * cols + 16 * (ti0 + j) + i] = a[j][r];
+    }
+
+    __device__ void flush(float *out)
+    {
+        store_layer<M_D1>(out);
+        store_layer<M_D2>(out);
+        store_layer<M_C1>(out);
+        if constexpr (CL == 2) store_layer<M_C2>(out);
+        store_layer<M_CO>(out);
+    }
+};
 
 template <typename FT>
 __device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s, bool valid, const MlpArgs &a,
@@ -640,13 +871,14 @@ __device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s,
     const int q = lane_id() >> 4;
     if (!valid) return;
     if (a.F == 2) {
+        float *base = dfeat + ((int64_t)(2 * q) * ld + s) * 2;     // level 8t + 2q + h
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int p = 16 * t + 4 * q + 2 * h;
                 if (p < a.n_feat)
-                    *reinterpret_cast<float2 *>(dfeat + ((int64_t)(p >> 1) * ld + s) * 2) =
+                    *reinterpret_cast<float2 *>(base + (int64_t)(8 * t + h) * ld * 2) =
                         make_float2(dx[t][2 * h], dx[t][2 * h + 1]);
             }
         return;
@@ -664,7 +896,7 @@ __device__ __forceinline__ void store_dfeat(float *dfeat, int64_t ld, int64_t s,
 }
 
 template <int PREC, int CL, typename FT, bool LOAD>
-__global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
+__global__ __launch_bounds__(kBlock, PREC == P_BF16 ? 2 : 1) void mlp_bwd_kernel(
     MlpArgs a, const float *__restrict__ w, const FT *__restrict__ feat, int64_t feat_ld,
     const float *__restrict__ view, const float *__restrict__ sun, const int32_t *__restrict__ ray_id,
     const int32_t *__restrict__ sidx, int64_t n, const int64_t *__restrict__ n_dev,
@@ -672,22 +904,14 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
     float *__restrict__ dfeat, float *__restrict__ partial, const typename FragT<PREC>::T *__restrict__ frag)
 {
     typedef Layout<PREC, CL> Lt;
+    typedef WGrad<PREC, CL, PREC == P_BF16> WG;
     __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::ALL];
-    __shared__ __attribute__((aligned(16))) float stage_buf[4 * kStageRows * kStageStride];
+    __shared__ __attribute__((aligned(16))) unsigned char wg_lds[WG::kLdsBytes];
     __shared__ UnitTable U;
     const int64_t ne = effective_n(n, n_dev);
     setup_units(U, a, ne);
     const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
-    float *st = stage_buf + wv * kStageRows * kStageStride;
-
-    f4 acc_d1[4][2], acc_d2[1][4], acc_c1[4][2], acc_c2[4][4], acc_co[1][4];
-    auto zero_all = [&]() {
-        zero(acc_d1);
-        zero(acc_d2);
-        zero(acc_c1);
-        zero(acc_c2);
-        zero(acc_co);
-    };
+    WG wg(wg_lds);
 
     // inputs of the next unit are loaded while the current one is computed
     int64_t g1 = 0, gbase = 0;   // end of the current group; sample of unit 0 in its numbering
@@ -738,7 +962,7 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
             for (int e = threadIdx.x; e < n16; e += kBlock) dst[e] = src[e];
             __syncthreads();
         }
-        zero_all();
+        wg.zero_all();
         BwdIdx ix;
         load_idx(u, ix);
         for (; u < ue; u += G) {
@@ -792,53 +1016,32 @@ __global__ __launch_bounds__(kBlock, 1) void mlp_bwd_kernel(
                     dout[0][3] = dvis * vis * (1.0f - vis);
                 }
             }
+            // adjoint chain; each layer's weight gradient as soon as both of
+            // its factors are known
             float dg2[4][4], dg1[4][4], dob[1][4], dh1[4][4], dx[2][4];
             if constexpr (CL == 2) {
                 apply<PREC, 64, 16>(lds + Lt::COT, dout, dg2);
                 relu_mask(dg2, A.g2);
+                wg.template layer<M_CO>(dout, A.g2);
                 apply<PREC, 64, 64>(lds + Lt::C2T, dg2, dg1);
+                relu_mask(dg1, A.g1);
+                wg.template layer<M_C2>(dg2, A.g1);
             } else {
                 apply<PREC, 64, 16>(lds + Lt::COT, dout, dg1);
+                relu_mask(dg1, A.g1);
+                wg.template layer<M_CO>(dout, A.g1);
             }
-            relu_mask(dg1, A.g1);
             apply<PREC, 16, 64>(lds + Lt::C1T, dg1, dob);
             if (q == 0) dob[0][0] = dsig * expf(A.o[0][0]);   // sigma = exp(o_0)
+            wg.template layer<M_C1>(dg1, A.cin);
             apply<PREC, 64, 16>(lds + Lt::D2T, dob, dh1);
             relu_mask(dh1, A.h1);
+            wg.template layer<M_D2>(dob, A.h1);
             apply<PREC, 32, 64>(lds + Lt::D1T, dh1, dx);
             store_dfeat<FT>(dfeat, n, s, in_range, a, dx);       // dropped samples store zeros
-
-            // weight gradients: stage (dy, x) pairs as [row][sample], MFMA over samples
-            stage<1>(st, 0, dout);
-            stage<4>(st, 16, CL == 2 ? A.g2 : A.g1);
-            wave_sync();
-            dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_co);
-            wave_sync();
-            if constexpr (CL == 2) {
-                stage<4>(st, 0, dg2);
-                stage<4>(st, 64, A.g1);
-                wave_sync();
-                dw_accumulate<PREC, 4, 4>(st, 0, 64, acc_c2);
-                wave_sync();
-            }
-            stage<4>(st, 0, dg1);
-            stage<2>(st, 64, A.cin);
-            wave_sync();
-            dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_c1);
-            wave_sync();
-            stage<1>(st, 0, dob);
-            stage<4>(st, 16, A.h1);
-            wave_sync();
-            dw_accumulate<PREC, 1, 4>(st, 0, 16, acc_d2);
-            wave_sync();
-            stage<4>(st, 0, dh1);
-            stage<2>(st, 64, A.x);
-            wave_sync();
-            dw_accumulate<PREC, 4, 2>(st, 0, 64, acc_d1);
-            wave_sync();
+            wg.template layer<M_D1>(dh1, A.x);
         }
-        flush_partial<PREC, CL>(stage_buf, partial + ((int64_t)blockIdx.x * a.K + k) * PadRow<CL>::W, acc_d1,
-                                acc_d2, acc_c1, acc_c2, acc_co);
+        wg.flush(partial + ((int64_t)blockIdx.x * a.K + k) * PadRow<CL>::W);
     }
 }
 
