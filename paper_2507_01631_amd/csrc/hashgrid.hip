@@ -464,7 +464,7 @@ __device__ __forceinline__ void item_unpack(const unsigned long long *src, uint3
 
 // Runs of equal slots along a ray are worth merging only where cells are
 // large against the sample spacing; on finer levels every item is emitted.
-constexpr int kMergeMaxRes = 512;
+constexpr int kMergeMaxRes = 256;
 
 template <int F>
 __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
@@ -817,17 +817,20 @@ __global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32
                         uint32_t slot;
                         int32_t v[F];
                         item_unpack<F>(w[u], smask, bp.binshift, slot, v);
+                        // feature-major: random slots spread over twice the banks
 #pragma unroll
                         for (int f = 0; f < F; ++f)
-                            atomicAdd(&acc[slot * F + f], (unsigned long long)(long long)v[f]);
+                            atomicAdd(&acc[f * slots + slot], (unsigned long long)(long long)v[f]);
                     }
                 }
             }
             __syncthreads();
             // exact: integer partial sums of several chunks add in any order
             unsigned long long *dst = acc64 + ((int64_t)lr << bp.kt2_log2) * F + (int64_t)(kbase & ((1u << bp.kt2_log2) - 1u)) * F;
-            for (int e = threadIdx.x; e < slots * F; e += blockDim.x)
-                if (acc[e]) atomicAdd(dst + e, acc[e]);
+            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) {
+                const unsigned long long a = acc[(e % F) * slots + e / F];
+                if (a) atomicAdd(dst + e, a);
+            }
             __syncthreads();
         }
     }
