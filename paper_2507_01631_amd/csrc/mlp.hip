@@ -1063,46 +1063,65 @@ __global__ __launch_bounds__(kBlock) void mlp_frag_kernel(MlpArgs a, const float
     build_frag<PREC, 32, 64>(dst + Lt::D1T, wd, a, M_D1, true);
 }
 
-// dW += the sums, over the blocks that processed units of each weight set (in
-// block order), of their padded rows.  Which blocks those are follows from
-// the same unit table the adjoint used (block b takes units u = b mod grid).
-// Per-tile sets: dW[k][p] sums set k's rows.  Shared colour net: dW[k][p] for
-// the density part of set k, then one colour part summed over all sets (in
-// set order, then block order).
-__global__ __launch_bounds__(256) void reduce_partials_kernel(MlpArgs a, const float *__restrict__ partial, int nb,
-                                                              int W, int64_t n, const int64_t *__restrict__ n_dev,
-                                                              float *__restrict__ dW)
+// dW += the sums, over the blocks that processed units of each weight set, of
+// their padded rows.  Which blocks those are follows from the same unit table
+// the adjoint used (block b takes units u = b mod grid).  Per-tile sets:
+// dW[k][p] sums set k's rows.  Shared colour net: dW[k][p] for the density
+// part of set k, then one colour part summed over all sets.  A block handles
+// 64 parameters (one per lane); its kRedGroups wavefronts each sum every
+// kRedGroups-th block row (sets in order, blocks ascending), and the groups'
+// sums are added in group order: a fixed order, so the result is the same
+// every run.
+constexpr int kRedGroups = 16;
+
+__global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(MlpArgs a, const float *__restrict__ partial,
+                                                                          int nb, int W, int64_t n,
+                                                                          const int64_t *__restrict__ n_dev,
+                                                                          float *__restrict__ dW)
 {
     __shared__ UnitTable U;
+    __shared__ float part[kRedGroups][64];
     setup_units(U, a, effective_n(n, n_dev));
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
     const int Pc = a.P - a.Pd;
     const int64_t total = a.shared_colour ? (int64_t)a.K * a.Pd + Pc : (int64_t)a.K * a.P;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        int k0, k1, p;
-        if (!a.shared_colour) {
-            k0 = (int)(e / a.P);
-            p = (int)(e - (int64_t)k0 * a.P);
-            k1 = k0 + 1;
-        } else if (e < (int64_t)a.K * a.Pd) {
-            k0 = (int)(e / a.Pd);
-            p = (int)(e - (int64_t)k0 * a.Pd);
-            k1 = k0 + 1;
-        } else {
-            k0 = 0;
-            k1 = a.K;
-            p = a.Pd + (int)(e - (int64_t)a.K * a.Pd);
-        }
-        const int pi = padded_index(a, p);
+    for (int64_t e0 = (int64_t)blockIdx.x * 64; e0 < total; e0 += (int64_t)gridDim.x * 64) {   // block-uniform
+        const int64_t e = e0 + lane;
         float s = 0.0f;
-        for (int k = k0; k < k1; ++k) {
-            const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
-            const float *src = partial + (int64_t)k * W + pi;
-            for (int b = 0; b < nb; ++b) {
-                const int u = ua + ((b - ua) % nb + nb) % nb;   // block b's first unit of set k
-                if (u < ue) s += src[(int64_t)b * a.K * W];
+        if (e < total) {
+            int k0, k1, p;
+            if (!a.shared_colour) {
+                k0 = (int)(e / a.P);
+                p = (int)(e - (int64_t)k0 * a.P);
+                k1 = k0 + 1;
+            } else if (e < (int64_t)a.K * a.Pd) {
+                k0 = (int)(e / a.Pd);
+                p = (int)(e - (int64_t)k0 * a.Pd);
+                k1 = k0 + 1;
+            } else {
+                k0 = 0;
+                k1 = a.K;
+                p = a.Pd + (int)(e - (int64_t)a.K * a.Pd);
+            }
+            const int pi = padded_index(a, p);
+            for (int k = k0; k < k1; ++k) {
+                const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
+                const float *src = partial + (int64_t)k * W + pi;
+                for (int b = grp; b < nb; b += kRedGroups) {
+                    const int u = ua + ((b - ua) % nb + nb) % nb;   // block b's first unit of set k
+                    if (u < ue) s += src[(int64_t)b * a.K * W];
+                }
             }
         }
-        dW[e] += s;
+        part[grp][lane] = s;
+        __syncthreads();
+        if (grp == 0 && e < total) {
+            float t = 0.0f;
+#pragma unroll
+            for (int g = 0; g < kRedGroups; ++g) t += part[g][lane];
+            dW[e] += t;
+        }
+        __syncthreads();
     }
 }
 
@@ -1207,8 +1226,8 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
                                                                      view, sun, ray_id, sidx, n, n_dev, dsigma, drgb,
                                                                      act, dfeat, partial, frag);
     const int64_t kp = a.shared_colour ? (int64_t)a.K * a.Pd + (a.P - a.Pd) : (int64_t)a.K * a.P;
-    reduce_partials_kernel<<<(unsigned)((kp + 255) / 256), 256, 0, st>>>(a, partial, (int)grid, PadRow<CL>::W, n,
-                                                                         n_dev, dW);
+    reduce_partials_kernel<<<(unsigned)((kp + 63) / 64), 64 * kRedGroups, 0, st>>>(a, partial, (int)grid,
+                                                                                    PadRow<CL>::W, n, n_dev, dW);
 }
 
 }  // namespace
