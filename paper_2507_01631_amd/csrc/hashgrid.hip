@@ -309,7 +309,7 @@ __device__ __forceinline__ bool wave_uniform(int b, bool active, int &b0)
     const unsigned long long act = __ballot(active);
     if (!act) return false;
     const int first = __ffsll((long long)act) - 1;
-    b0 = __shfl(b, first, 64);
+    b0 = __builtin_amdgcn_readlane(b, first);
     return __all(!active || b == b0);
 }
 
@@ -520,6 +520,16 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
             uint32_t idx[8];
             float wt[8];
             corners(g, l, x, idx, wt);
+            if (!merge_l && !dense_l) {
+                // every corner of an active lane emits: one branch for all eight
+                if (act) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        atomicAdd(&hist[lr * bp.nbpl + (int)((((uint32_t)tile << bp.T_log2) + idx[q]) >> bp.binshift)],
+                                  1);
+                }
+                continue;
+            }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
@@ -668,18 +678,30 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 key[q] = ((uint32_t)tile << bp.T_log2) + idx[q];
 #pragma unroll
                 for (int f = 0; f < F; ++f) v[q][f] = quantise(wt[q] * Vec<F>::get(gv, f), E);
-                const bool emit = merge_l ? merge_runs<F>(key[q], act, v[q]) : act;
-                const int bl = (int)(key[q] >> bp.binshift);
-                int b0;
-                if (dense_l && wave_uniform(bl, emit, b0)) {
-                    const unsigned long long am = __ballot(emit);
-                    const int leader = __ffsll((long long)am) - 1;
-                    int r0 = 0;
-                    if (lane == leader) r0 = atomicAdd(&hcnt[b0], __popcll(am));
-                    r0 = __shfl(r0, leader, 64);
-                    rank[q] = emit ? r0 + __popcll(am & lt_mask) : -1;
-                } else {
-                    rank[q] = emit ? atomicAdd(&hcnt[bl], 1) : -1;
+                rank[q] = -1;
+            }
+            if (!merge_l && !dense_l) {
+                // every corner of an active lane emits: one branch for all eight
+                if (act) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) rank[q] = atomicAdd(&hcnt[key[q] >> bp.binshift], 1);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool emit = merge_l ? merge_runs<F>(key[q], act, v[q]) : act;
+                    const int bl = (int)(key[q] >> bp.binshift);
+                    int b0;
+                    if (dense_l && wave_uniform(bl, emit, b0)) {
+                        const unsigned long long am = __ballot(emit);
+                        const int leader = __ffsll((long long)am) - 1;
+                        int r0 = 0;
+                        if (lane == leader) r0 = atomicAdd(&hcnt[b0], __popcll(am));
+                        r0 = __builtin_amdgcn_readlane(r0, leader);
+                        rank[q] = emit ? r0 + __popcll(am & lt_mask) : -1;
+                    } else if (emit) {
+                        rank[q] = atomicAdd(&hcnt[bl], 1);
+                    }
                 }
             }
             __syncthreads();
