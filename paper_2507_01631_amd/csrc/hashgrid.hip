@@ -341,8 +341,6 @@ __device__ __forceinline__ int level_exponent(uint32_t maxbits)
 // A level takes part when it has a nonzero, finite largest gradient.
 __device__ __forceinline__ bool level_ok(uint32_t maxbits) { return maxbits != 0u && maxbits < 0x7f800000u; }
 
-__device__ __forceinline__ int32_t quantise(float v, int E) { return (int32_t)rintf(ldexpf(v, E)); }
-
 // Consecutive lanes (consecutive samples of a ray) often hit the same slot on
 // coarse levels.  Each run of equal keys across the wavefront is cut into
 // pieces of at most kRunCap lanes counted from the run's first lane; a
@@ -673,11 +671,15 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             uint32_t key[8];
             int rank[8];
             int32_t v[8][F];
+            // w (g 2^E) is (w g) 2^E: scaling by a power of two is exact
+            float gs[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) gs[f] = ldexpf(Vec<F>::get(gv, f), E);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 key[q] = ((uint32_t)tile << bp.T_log2) + idx[q];
 #pragma unroll
-                for (int f = 0; f < F; ++f) v[q][f] = quantise(wt[q] * Vec<F>::get(gv, f), E);
+                for (int f = 0; f < F; ++f) v[q][f] = (int32_t)rintf(wt[q] * gs[f]);
                 rank[q] = -1;
             }
             if (!merge_l && !dense_l) {
@@ -722,14 +724,22 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 }
             }
             // 3. counting-sort the batch into the staging area
+            auto stage_item = [&](int q) {
+                const int at = hoff[key[q] >> bp.binshift] + rank[q];
+                skey[at] = key[q];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (rank[q] >= 0) {
-                    const int at = hoff[key[q] >> bp.binshift] + rank[q];
-                    skey[at] = key[q];
+                for (int f = 0; f < F; ++f) sval[at * F + f] = v[q][f];
+            };
+            if (!merge_l && !dense_l) {
+                if (act) {
 #pragma unroll
-                    for (int f = 0; f < F; ++f) sval[at * F + f] = v[q][f];
+                    for (int q = 0; q < 8; ++q) stage_item(q);
                 }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (rank[q] >= 0) stage_item(q);
+            }
             __syncthreads();
             // 4. write out: consecutive threads, consecutive slots of a bin
             const uint32_t smask = (1u << bp.binshift) - 1u;
