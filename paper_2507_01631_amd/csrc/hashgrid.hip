@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 //           make, and each level's largest |dfeat|
 //   scan    exclusive offsets, bin-major, so each bin's items are contiguous
 //   scatter write the items to their bin (LDS cursors per block)
-//   reduce  per chunk of items: add into a 64 KB LDS copy of the bin's slots,
+//   reduce  per equal share of the items: add into a 64 KB LDS copy of the bin's slots,
 //           then flush the bin once with one 64-bit integer atomic per touched
 //           slot into a pass-wide integer accumulator
 //   convert every accumulator slot of the pass, scaled back, into dtable
@@ -292,7 +292,8 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 constexpr int kBinBlocks = 1024;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
 constexpr int kAccWords = 8192;         // LDS accumulator: 8192 int64 = 64 KB
-constexpr int64_t kReduceChunk = 1 << 21;
+constexpr int kReduceThreads = 1024;    // reduce block: many loads in flight per CU
+constexpr int kReducePerCU = 2;         // reduce blocks resident per CU (64 KB of LDS each)
 constexpr int kRU = 8;                  // items in flight per thread in the reduce
 
 struct BinPlan {
@@ -804,20 +805,23 @@ __device__ __forceinline__ int bin_of_item(const int32_t *offsets, int nblk, int
 }
 
 template <int F>
-__global__ __launch_bounds__(256) void bin_reduce_kernel(BinPlan bp, const int32_t *__restrict__ offsets,
-                                                         int nblk, const int64_t *__restrict__ n_items,
-                                                         const unsigned long long *__restrict__ items,
-                                                         const uint32_t *__restrict__ lmax,
-                                                         unsigned long long *__restrict__ acc64)
+__global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, const int32_t *__restrict__ offsets,
+                                                                    int nblk, const int64_t *__restrict__ n_items,
+                                                                    const unsigned long long *__restrict__ items,
+                                                                    const uint32_t *__restrict__ lmax,
+                                                                    unsigned long long *__restrict__ acc64)
 {
     __shared__ unsigned long long acc[kAccWords];
     const int64_t total = *n_items;
     const int slots = 1 << bp.binshift;
     const uint32_t smask = (uint32_t)slots - 1;
     constexpr int NW = ItemFmt<F>::NW;
-    for (int64_t c0 = (int64_t)blockIdx.x * kReduceChunk; c0 < total; c0 += (int64_t)gridDim.x * kReduceChunk) {
-        const int64_t c1 = c0 + kReduceChunk < total ? c0 + kReduceChunk : total;
-        // the bins holding the chunk's first and last items (items carry only
+    // one contiguous, equal share of the pass's items per block (the grid is
+    // what the chip holds at once, so there is no tail of late blocks)
+    {
+        const int64_t c0 = total * blockIdx.x / gridDim.x, c1 = total * (blockIdx.x + 1) / gridDim.x;
+        if (c0 >= c1) return;
+        // the bins holding the share's first and last items (items carry only
         // their slot within the bin)
         const int bfirst = bin_of_item(offsets, nblk, bp.nb, c0);
         const int blast = bin_of_item(offsets, nblk, bp.nb, c1 - 1);
@@ -1120,8 +1124,7 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         p += align256((size_t)n_acc * 8);
         w.items = reinterpret_cast<unsigned long long *>(p);
         w.item_cap = n * lgp * 8;
-        const int64_t chunks = (w.item_cap + kReduceChunk - 1) / kReduceChunk;
-        const unsigned rgrid = (unsigned)(chunks < 4096 ? (chunks > 0 ? chunks : 1) : 4096);
+        const unsigned rgrid = (unsigned)(kReducePerCU * num_cus());
         const unsigned zgrid = grid_for(n_acc, 256, 8);
         const unsigned cgrid = grid_for(((int64_t)lgp * K << gd->log2_table) * F, 256, 8);
 #define SNAKE_BIN_PASS(FF)                                                                                 \
@@ -1131,7 +1134,7 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items, err, st);   \
     bin_scatter_kernel<FF><<<nblk, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(                     \
         g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.lmax, w.items);            \
-    bin_reduce_kernel<FF><<<rgrid, 256, 0, st>>>(bp, w.offsets, nblk, w.n_items, w.items, w.lmax, w.acc64); \
+    bin_reduce_kernel<FF><<<rgrid, kReduceThreads, 0, st>>>(bp, w.offsets, nblk, w.n_items, w.items, w.lmax, w.acc64); \
     bin_convert_kernel<FF><<<cgrid, 256, 0, st>>>(bp, g.L, w.acc64, w.lmax, K, dtable)
         if (F == 1) {
             SNAKE_BIN_PASS(1);
