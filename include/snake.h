@@ -104,7 +104,7 @@ typedef enum {
                                                1 for FP32); changes the dW summation order */
     SNAKE_TUNE_COMPOSITE_BLOCKS_PER_CU = 3, /* rendering grid, 1..64 (8) */
     SNAKE_TUNE_BIN_BLOCKS = 4,              /* binned table adjoint: count/scatter blocks,
-                                               64..1024 (1024) */
+                                               64..2048 (2048) */
     SNAKE_TUNE_BIN_LEVELS_PER_PASS = 5,     /* binned table adjoint: most levels per pass,
                                                0..32 (0: as many as the workspace holds) */
     SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU = 6,   /* sampler fill grid, 1..64 (16) */

@@ -28,7 +28,7 @@ CANDIDATES = {
     "mlp_fwd_blocks_per_cu": [2, 3, 4, 8],
     "mlp_bwd_blocks_per_cu": [1, 2],
     "composite_blocks_per_cu": [4, 8, 16],
-    "bin_blocks": [256, 512, 1024],
+    "bin_blocks": [512, 1024, 2048],
     "bin_levels_per_pass": [0, 2, 4],
     "sampler_blocks_per_cu": [8, 16, 32],
 }

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 // which shortens the item list on the coarse levels; an item is one 64-bit
 // word for F <= 2.
 
-constexpr int kBinBlocks = 1024;        // most count/scatter blocks (the workspace holds this many)
+constexpr int kBinBlocks = 2048;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
 constexpr int kAccWords = 8192;         // LDS accumulator: 8192 int64 = 64 KB
 constexpr int kReduceThreads = 1024;    // reduce block: many loads in flight per CU

@@ -186,12 +186,12 @@ def test_tunables_table(L):
     assert len(ids) == 7 and sorted(ids.values()) == list(range(7))
     saved = {k: L.snake_tune_get(k) for k in ids}
     try:
-        assert saved["hash_fwd_blocks_per_cu"] == 16 and saved["bin_blocks"] == 1024
+        assert saved["hash_fwd_blocks_per_cu"] == 16 and saved["bin_blocks"] == 2048
         L.snake_tune_set("bin_blocks", 256)
         assert L.snake_tune_get("bin_blocks") == 256
         L.snake_tune_set("bin_blocks", 0)                      # 0 restores the default
-        assert L.snake_tune_get("bin_blocks") == 1024
-        for which, bad in (("bin_blocks", 2048), ("mlp_bwd_blocks_per_cu", 3), ("hash_fwd_blocks_per_cu", -1)):
+        assert L.snake_tune_get("bin_blocks") == 2048
+        for which, bad in (("bin_blocks", 4096), ("mlp_bwd_blocks_per_cu", 3), ("hash_fwd_blocks_per_cu", -1)):
             with pytest.raises(L.SnakeError):
                 L.snake_tune_set(which, bad)
         with pytest.raises(L.SnakeError):
