@@ -445,7 +445,7 @@ def test_hashgrid_bwd_binned_is_deterministic(L, orc):
     saved = {k: L.snake_tune_get(k) for k in ("bin_blocks", "bin_levels_per_pass")}
     outs = []
     try:
-        for blocks, lg in ((1024, 0), (256, 0), (512, 3), (64, 1)):
+        for blocks, lg in ((2048, 0), (1024, 0), (256, 0), (512, 3), (64, 1)):
             L.snake_tune_set("bin_blocks", blocks)
             L.snake_tune_set("bin_levels_per_pass", lg)
             dtab = torch.zeros(table.shape, device=DEV)
