@@ -18,7 +18,7 @@
 namespace snake {
 namespace {
 
-constexpr int kPartBlocks = 512;
+constexpr int kPartBlocks = 2048;
 constexpr int kMaxPartTiles = 16;
 
 __global__ __launch_bounds__(256) void part_count_kernel(const uint8_t *__restrict__ tile_id, int64_t n,
