@@ -6,7 +6,7 @@ reported value) beside the FP32 form, with the dominant kernel's fraction of
 its roofline.  A "step" is one pass of the whole path over one batch of rays:
 segmented sampling -> hash encoding -> density/colour MLP -> volume rendering
 + MSE loss -> composite adjoint -> MLP adjoint (recomputed activations) ->
-binned fixed-point hash-table adjoint -> Adam on the table and the MLP.
+binned exact-sum hash-table adjoint -> Adam on the table and the MLP.
 
 Workload (full-size single tile): hash grid L=16, F=2, T=2^19, resolutions
 16 -> 2048; density MLP 32->64->16, colour MLP 21->64->64->4; 2^18 rays per

@@ -291,21 +291,25 @@ int snake_convert_bf16(const float *src, int64_t n, void *dst, snake_stream_t st
 /* Adjoint: dtable[tile][l][idx_b][f] += w_b * dfeat[l][s][f] for the K tiles
  * of dtable [K][L][T][F] float; dfeat [L][n][F] float (compact, indexed by j).
  * With a workspace the corner contributions are binned by table slot (count,
- * scan, scatter) and summed exactly in 64-bit fixed point: each contribution
- * is rounded once to an integer multiple of 2^-E_l, where E_l = 23 - e and
- * 2^(e-1) <= max|dfeat of level l| < 2^e (consecutive samples of a ray that
- * share a slot are first summed in pieces of at most three, so every stored
- * partial sum fits 26 bits), then every table entry receives its
- * sum, rounded once to FP32.  The result is deterministic (the same bits for
- * any grid or scheduling).  A level whose dfeat holds a non-finite value adds
- * nothing and raises SNAKE_DEVERR_NONFINITE.  The workspace size decides how
- * many levels share a pass (snake_hashgrid_bwd_workspace_bytes(g, K, n,
- * levels_per_pass); one level per pass is the minimum).  With workspace ==
- * NULL every contribution is a direct FP32 atomic add, whose order, hence
- * last bits, is not deterministic.  A tile_id >= K contributes nothing and
- * raises SNAKE_DEVERR_TILE_ID.  Limits: 1 <= K <= 256, K*T <= 2^28; the
- * binned form needs 8 n < 2^31 and puts at most (2^31 - 1) / (8 n) levels in
- * a pass. */
+ * scan, scatter) and summed exactly in integers: each stored value -- one
+ * corner's w_b * dfeat in FP32, or the FP32 sum of a run of consecutive
+ * samples of a ray sharing the slot -- is rounded once to 20 significant bits
+ * (relative error <= 2^-20) with an exponent at most 63 binades below the
+ * level's largest |dfeat| (smaller values count as 0; values more than 37
+ * binades below it are rounded to a multiple of 2^-56 times it), the values
+ * are added exactly into 128-bit integer sums, and every table entry receives
+ * its sum rounded once to FP32.  So each entry keeps its own relative
+ * precision whatever the gradients' spread: |error| <= about 2^-20 times the
+ * sum of |w_b * dfeat| over its contributions, plus the final FP32 rounding.
+ * The result is deterministic (the same bits for any grid or scheduling).  A
+ * level whose dfeat holds a non-finite value adds nothing and raises
+ * SNAKE_DEVERR_NONFINITE.  The workspace size decides how many levels share a
+ * pass (snake_hashgrid_bwd_workspace_bytes(g, K, n, levels_per_pass); one
+ * level per pass is the minimum).  With workspace == NULL every contribution
+ * is a direct FP32 atomic add, whose order, hence last bits, is not
+ * deterministic.  A tile_id >= K contributes nothing and raises
+ * SNAKE_DEVERR_TILE_ID.  Limits: 1 <= K <= 256, K*T <= 2^28; the binned form
+ * needs 8 n < 2^31 and puts at most (2^31 - 1) / (8 n) levels in a pass. */
 size_t snake_hashgrid_bwd_workspace_bytes(const snake_grid_desc *g, int32_t K, int64_t n,
                                           int32_t levels_per_pass);
 int snake_hashgrid_bwd(const snake_grid_desc *g, int32_t K, const float *pos, const uint8_t *tile_id,

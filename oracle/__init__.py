@@ -59,6 +59,8 @@ def lib():
         L.orc_mlp_bwd.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
         L.orc_mlp_margin.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P]
         L.orc_mlp_fwd_bf16emu.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P]
+        L.orc_mlp_bwd_q.argtypes = [_I] * 6 + [_P, _I64, _P, _P, _P, _P, _P, _P, _I, _P, _P]
+        L.orc_bf16_round.argtypes = [_I64, _P, _P]
         L.orc_composite_fwd.argtypes = [_I, _P, _P, _P, _P, _P, _D, _P, _P, _D,
                                         _P, _P, _P, _P, _P]
         L.orc_composite_bwd.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _D, _P, _P]
@@ -188,6 +190,31 @@ def mlp_bwd(m, weights, feat, view, ray_id, dsigma, drgb, sun=None):
                       _ptr(_c(dsigma, np.float64)), _ptr(_c(drgb, np.float64)),
                       _ptr(dW), _ptr(dfeat))
     return dW, dfeat
+
+
+def mlp_bwd_q(m, weights, feat, view, ray_id, dsigma, drgb, sun=None, round16=1):
+    """Adjoint of the 16-bit form: mlp_bwd with every matrix-core operand
+    rounded to bfloat16 (weights, inputs, post-ReLU activations, colour inputs,
+    the output gradient before each transposed product, and both factors of
+    each weight-gradient product); round16=0 is mlp_bwd itself, bit for bit."""
+    weights = _c(weights, np.float32)
+    feat = _c(feat, np.float64)
+    n = feat.shape[0]
+    dW = np.zeros(weights.shape[0])
+    dfeat = np.zeros_like(feat)
+    lib().orc_mlp_bwd_q(*_mlp_args(m), _ptr(weights), n, _ptr(feat), _ptr(_c(view, np.float32)),
+                        _ptr(_c(sun, np.float32)), _ptr(_c(ray_id, np.int32)),
+                        _ptr(_c(dsigma, np.float64)), _ptr(_c(drgb, np.float64)), int(round16),
+                        _ptr(dW), _ptr(dfeat))
+    return dW, dfeat
+
+
+def bf16_round(x):
+    """x rounded to the nearest bfloat16 (ties to even), as float64."""
+    x = _c(x, np.float64)
+    out = np.empty_like(x)
+    lib().orc_bf16_round(x.size, _ptr(x), _ptr(out))
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -338,15 +365,19 @@ def adam_step(p, g, m, v, lr, step, b1=0.9, b2=0.99, eps=1e-15, l2=0.0):
 # one training step, composed in the paper's order
 # ---------------------------------------------------------------------------
 def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=1,
-               alive=None, rays=None, timings=None, occupancy=None):
+               alive=None, rays=None, timings=None, occupancy=None, bf16=False):
     """One step of the tile-NeRF: segmented sampling -> hash encoding -> density
     and colour nets -> volume rendering + MSE loss -> adjoints -> Adam.
 
     ``wl`` supplies the rays, boxes, band, targets and configs (any object with
     the attributes of ``synth.Workload``).  ``alive`` optionally fixes the
     per-ray early-stop counts (to follow another implementation's decision
-    where floating point rounding makes it ambiguous).  Returns a dict of every
-    intermediate, the gradients and the updated FP64 parameters."""
+    where floating point rounding makes it ambiguous).  ``bf16`` emulates the
+    16-bit form: the encoding gathers from the table rounded to bfloat16 (its
+    half-precision copy) and both networks round every matrix-core operand to
+    bfloat16 (mlp_fwd_bf16emu, mlp_bwd_q); everything else stays FP64.
+    Returns a dict of every intermediate, the gradients and the updated FP64
+    parameters."""
     t_start = time.perf_counter()
     g, m = wl.grid, wl.mlp
     if res is None:
@@ -368,7 +399,9 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
         out["sample_raw"] = smp
         smp = cull_samples(smp, occupancy[1], occupancy[0])
     out["sample"] = smp
-    feat = hashgrid_fwd(res, g.log2_table, table, smp["pos"], smp["tile_id"], g.out_width)
+    table_fwd = bf16_round(table).astype(np.float32).reshape(table.shape) if bf16 else table
+    feat = hashgrid_fwd(res, g.log2_table, table_fwd, smp["pos"], smp["tile_id"], g.out_width)
+    fwd = mlp_fwd_bf16emu if bf16 else mlp_fwd
     # one weight set ([P]) shared by the tiles, one per tile ([K][P]), or
     # per-tile density nets with one shared colour net ({"density": [K][Pd],
     # "colour": [P-Pd]}): each sample goes through the networks of its tile
@@ -387,7 +420,7 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
     sigma, rgb = np.zeros(smp["n"]), np.zeros((smp["n"], 3))
     for sel, w in groups:
         if sel.any():
-            sigma[sel], rgb[sel] = mlp_fwd(m, w, feat[sel], smp["view"], smp["ray_id"][sel], sun=sun)
+            sigma[sel], rgb[sel] = fwd(m, w, feat[sel], smp["view"], smp["ray_id"][sel], sun=sun)
     loss_scale = 1.0 / (3.0 * R)
     comp = composite_fwd(smp["packed_info"], sigma, rgb, smp["t0"], smp["t1"], target,
                          loss_scale, early_stop=wl.early_stop, alive=alive)
@@ -398,8 +431,8 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
     dfeat = np.zeros((smp["n"], feat.shape[1]))
     for k, (sel, w) in enumerate(groups):
         if sel.any():
-            dWk, dfeat[sel] = mlp_bwd(m, w, feat[sel], smp["view"], smp["ray_id"][sel], dsigma[sel], drgb[sel],
-                                      sun=sun)
+            dWk, dfeat[sel] = mlp_bwd_q(m, w, feat[sel], smp["view"], smp["ray_id"][sel], dsigma[sel], drgb[sel],
+                                        sun=sun, round16=int(bf16))
             if per_tile:
                 dW[k] += dWk
             else:

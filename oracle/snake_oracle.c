@@ -547,6 +547,12 @@ static double bf16r(double x)
     return (double)f;
 }
 
+/* out[i] = in[i] rounded to the nearest bfloat16 (ties to even, via float32). */
+void orc_bf16_round(int64_t n, const double *in, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bf16r(in[i]);
+}
+
 void orc_mlp_fwd_bf16emu(int feat_width, int hidden, int dens_out, int n_dir, int colour_layers,
                          int colour_out, const float *weights, int64_t n, const double *feat,
                          const float *view, const float *sun, const int32_t *ray_id,
@@ -688,6 +694,141 @@ static void mlp_adjoint_one(const orc_mlp *m, const double *w, const int64_t *of
     }
 }
 
+/* q16(x, on): x rounded to the nearest bfloat16 when `on`, else x. */
+static double q16(double x, int on) { return on ? bf16r(x) : x; }
+
+/* Adjoint of one sample with every matrix-core operand of a 16-bit
+ * implementation rounded to bfloat16 (when q): the weights, the network
+ * inputs, the post-ReLU activations and colour inputs (as in the forward
+ * emulation above), and in the adjoint the output gradient fed to each
+ * transposed product and both factors of every weight-gradient outer product.
+ * ReLU masks, sigmoid and exp use the unrounded values; sums are FP64.  With
+ * q == 0 it is the plain FP64 adjoint, term for term in the same order as
+ * mlp_adjoint_one (w must already hold rounded weights when q != 0). */
+static void mlp_adjoint_one_q(const orc_mlp *m, const double *w, const int64_t *off,
+                              const double *feat, const float *view, const float *sun,
+                              double dsigma, const double drgb[3], double *dw, double *dfeat, int q)
+{
+    int H = m->hidden, cin = m->dens_out - 1 + m->n_dir, CL = m->colour_layers;
+    int FW = m->feat_width, DO = m->dens_out, CO = m->colour_out;
+    /* forward with the operands rounded where a 16-bit matrix core takes them */
+    double x[ORC_MAXW], h1[ORC_MAXW], o[ORC_MAXW], ci[ORC_MAXW], g[ORC_MAX_COLOUR_LAYERS][ORC_MAXW];
+    double out[8];
+    for (int i = 0; i < FW; ++i) x[i] = q16(feat[i], q);
+    matvec(w + off[0], H, FW, x, h1);
+    for (int i = 0; i < H; ++i) h1[i] = h1[i] > 0.0 ? h1[i] : 0.0;
+    double h1q[ORC_MAXW];
+    for (int i = 0; i < H; ++i) h1q[i] = q16(h1[i], q);
+    matvec(w + off[1], DO, H, h1q, o);
+    for (int i = 0; i < DO - 1; ++i) ci[i] = q16(o[1 + i], q);
+    for (int i = 0; i < 3; ++i) ci[DO - 1 + i] = q16(view[i], q);
+    if (m->n_dir == 6)
+        for (int i = 0; i < 3; ++i) ci[DO + 2 + i] = q16(sun[i], q);
+    double gq[ORC_MAX_COLOUR_LAYERS][ORC_MAXW];
+    matvec(w + off[2], H, cin, ci, g[0]);
+    for (int i = 0; i < H; ++i) {
+        g[0][i] = g[0][i] > 0.0 ? g[0][i] : 0.0;
+        gq[0][i] = q16(g[0][i], q);
+    }
+    for (int c = 1; c < CL; ++c) {
+        matvec(w + off[2 + c], H, H, gq[c - 1], g[c]);
+        for (int i = 0; i < H; ++i) {
+            g[c][i] = g[c][i] > 0.0 ? g[c][i] : 0.0;
+            gq[c][i] = q16(g[c][i], q);
+        }
+    }
+    matvec(w + off[2 + CL], CO, H, gq[CL - 1], out);
+
+    /* output activation */
+    double dout[8];
+    if (CO == 3) {
+        for (int c = 0; c < 3; ++c) {
+            double y = sigmoid(out[c]);
+            dout[c] = drgb[c] * y * (1.0 - y);
+        }
+    } else {
+        double vis = sigmoid(out[3]), dvis = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double alb = sigmoid(out[c]);
+            dout[c] = drgb[c] * vis * alb * (1.0 - alb);
+            dvis += drgb[c] * alb;
+        }
+        dout[3] = dvis * vis * (1.0 - vis);
+    }
+    for (int c = 0; c < CO; ++c) dout[c] = q16(dout[c], q);
+
+    /* colour output layer */
+    double dg[ORC_MAXW], tmp[ORC_MAXW];
+    {
+        const double *W = w + off[2 + CL];
+        double *dW = dw + off[2 + CL];
+        const double *xi = gq[CL - 1];
+        for (int oo = 0; oo < CO; ++oo)
+            for (int i = 0; i < H; ++i) dW[(int64_t)oo * H + i] += dout[oo] * xi[i];
+        for (int i = 0; i < H; ++i) {
+            double acc = 0.0;
+            for (int oo = 0; oo < CO; ++oo) acc += W[(int64_t)oo * H + i] * dout[oo];
+            dg[i] = g[CL - 1][i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < H; ++i) dg[i] = q16(dg[i], q);
+    }
+    /* colour hidden layers */
+    for (int c = CL - 1; c >= 1; --c) {
+        const double *W = w + off[2 + c];
+        double *dW = dw + off[2 + c];
+        const double *xi = gq[c - 1];
+        for (int oo = 0; oo < H; ++oo)
+            for (int i = 0; i < H; ++i) dW[(int64_t)oo * H + i] += dg[oo] * xi[i];
+        for (int i = 0; i < H; ++i) {
+            double acc = 0.0;
+            for (int oo = 0; oo < H; ++oo) acc += W[(int64_t)oo * H + i] * dg[oo];
+            tmp[i] = g[c - 1][i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < H; ++i) dg[i] = q16(tmp[i], q);
+    }
+    /* colour first layer */
+    double dos[ORC_MAXW];
+    {
+        const double *W = w + off[2];
+        double *dW = dw + off[2];
+        for (int oo = 0; oo < H; ++oo)
+            for (int i = 0; i < cin; ++i) dW[(int64_t)oo * cin + i] += dg[oo] * ci[i];
+        dos[0] = dsigma * exp(o[0]);
+        for (int e = 0; e < DO - 1; ++e) {
+            double acc = 0.0;
+            for (int oo = 0; oo < H; ++oo) acc += W[(int64_t)oo * cin + e] * dg[oo];
+            dos[1 + e] = acc;
+        }
+        for (int e = 0; e < DO; ++e) dos[e] = q16(dos[e], q);
+    }
+    /* density second layer */
+    double dh[ORC_MAXW];
+    {
+        const double *W = w + off[1];
+        double *dW = dw + off[1];
+        for (int oo = 0; oo < DO; ++oo)
+            for (int i = 0; i < H; ++i) dW[(int64_t)oo * H + i] += dos[oo] * h1q[i];
+        for (int i = 0; i < H; ++i) {
+            double acc = 0.0;
+            for (int oo = 0; oo < DO; ++oo) acc += W[(int64_t)oo * H + i] * dos[oo];
+            dh[i] = h1[i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < H; ++i) dh[i] = q16(dh[i], q);
+    }
+    /* density first layer */
+    {
+        const double *W = w + off[0];
+        double *dW = dw + off[0];
+        for (int oo = 0; oo < H; ++oo)
+            for (int i = 0; i < FW; ++i) dW[(int64_t)oo * FW + i] += dh[oo] * x[i];
+        for (int i = 0; i < FW; ++i) {
+            double acc = 0.0;
+            for (int oo = 0; oo < H; ++oo) acc += W[(int64_t)oo * FW + i] * dh[oo];
+            dfeat[i] = acc;
+        }
+    }
+}
+
 #define ORC_CHUNKS 64
 
 /* Adjoint of orc_mlp_fwd.  dW (packed like the weights) is ADDED TO; dfeat
@@ -712,6 +853,37 @@ void orc_mlp_bwd(int feat_width, int hidden, int dens_out, int n_dir, int colour
             mlp_adjoint_one(&m, w, off, feat + s * feat_width, view + 3 * r,
                             sun ? sun + 3 * r : NULL, dsigma[s], drgb + 3 * s,
                             part + (int64_t)ch * P, dfeat + s * feat_width);
+        }
+    }
+    for (int ch = 0; ch < ORC_CHUNKS; ++ch)
+        for (int64_t i = 0; i < P; ++i) dW[i] += part[(int64_t)ch * P + i];
+    free(part);
+    free(w);
+}
+
+/* Adjoint of the 16-bit form: orc_mlp_bwd with every matrix-core operand
+ * rounded to bfloat16 (mlp_adjoint_one_q, q = round16); round16 == 0 gives
+ * the plain FP64 adjoint again, bit for bit equal to orc_mlp_bwd.  Same
+ * chunked, thread-count independent summation of dW. */
+void orc_mlp_bwd_q(int feat_width, int hidden, int dens_out, int n_dir, int colour_layers,
+                   int colour_out, const float *weights, int64_t n, const double *feat,
+                   const float *view, const float *sun, const int32_t *ray_id,
+                   const double *dsigma, const double *drgb, int round16, double *dW, double *dfeat)
+{
+    orc_mlp m = {feat_width, hidden, dens_out, n_dir, colour_layers, colour_out};
+    int64_t off[8];
+    int64_t P = mlp_offsets(&m, off);
+    double *w = weights_f64(weights, P);
+    for (int64_t i = 0; i < P; ++i) w[i] = q16(w[i], round16);
+    double *part = (double *)calloc((size_t)ORC_CHUNKS * (size_t)P, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ch = 0; ch < ORC_CHUNKS; ++ch) {
+        int64_t s0 = n * ch / ORC_CHUNKS, s1 = n * (ch + 1) / ORC_CHUNKS;
+        for (int64_t s = s0; s < s1; ++s) {
+            int64_t r = ray_id[s];
+            mlp_adjoint_one_q(&m, w, off, feat + s * feat_width, view + 3 * r,
+                              sun ? sun + 3 * r : NULL, dsigma[s], drgb + 3 * s,
+                              part + (int64_t)ch * P, dfeat + s * feat_width, round16);
         }
     }
     for (int ch = 0; ch < ORC_CHUNKS; ++ch)

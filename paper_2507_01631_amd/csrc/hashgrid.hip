@@ -272,29 +272,47 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 //           make, and each level's largest |dfeat|
 //   scan    exclusive offsets, bin-major, so each bin's items are contiguous
 //   scatter write the items to their bin (LDS cursors per block)
-//   reduce  per equal share of the items: add into a 64 KB LDS copy of the bin's slots,
-//           then flush the bin once with one 64-bit integer atomic per touched
-//           slot into a pass-wide integer accumulator
-//   convert every accumulator slot of the pass, scaled back, into dtable
+//   reduce  per equal share of the items: add into an LDS copy of the bin's
+//           slots, then flush the bin once per touched slot into a pass-wide
+//           integer accumulator of two 64-bit words (hi 2^52 + lo)
+//   convert every accumulator slot of the pass, rounded once, into dtable
 // A pass covers `lg` levels; bins never straddle levels.
 //
-// LDS float atomics are slow on this chip (about 2e11/s) while LDS integer
-// atomics are about 20x faster, so the sums are taken in fixed point: every
-// contribution v becomes the integer rint(v 2^E_l), with E_l fixed per level
-// from the level's largest |dfeat| (|q| <= 2^23), and is added into 64-bit
-// sums.  Integer sums do not depend on the order of addition, so the result
-// is the same bits whatever the chunking, the scheduling or the grid.
+// Item values.  Each stored value (one corner's w*g, or the FP32 sum of a run
+// of consecutive samples of a ray sharing the slot) is rounded once to a
+// 26-bit float: a sign, a 6-bit exponent k counted down from the level's top
+// exponent Et = e + 7 (2^(e-1) <= max|dfeat of the level| < 2^e, so every
+// value is below 2^(Et-1) even for a run of 64 lanes), and 19 stored mantissa
+// bits, i.e. |v| = 1.m * 2^(Et-k) with 20 significant bits (relative error
+// at most 2^-20).  Values below 2^(Et-63) = 2^(e-56) are stored as zero.
+//
+// Exact sums.  LDS float atomics are slow on this chip (about 2e11/s) while
+// LDS integer atomics are about 20x faster, so the values are summed as
+// integers: a value with k <= 22 adds (2^19+m) << (22-k) into a "big"
+// accumulator with unit 2^(Et-41); one with 22 < k <= 44 adds
+// (2^19+m) << (44-k) into a "small" one with unit 2^(Et-63); smaller ones
+// (k > 44, below 2^(e-37)) are rounded to that unit.  Each term is below 2^41
+// and a block adds at most 2^21 items into one copy before flushing it, so
+// the 64-bit LDS sums cannot overflow.  Integer sums do not depend on the
+// order of addition, and the items do not depend on the grid (block ranges
+// are whole 64-sample wavefronts), so the result is the same bits whatever
+// the chunking, the scheduling or the grid.  The only roundings are the
+// value's (2^-20 relative, or 2^(e-57) absolute below 2^(e-37)) and the
+// final one to FP32, so every table entry keeps its own relative precision
+// however small it is against the level's largest gradient.
+//
 // Consecutive samples of a ray that share a corner are first merged across
-// the wavefront in pieces of up to three (each stored sum fits 26 bits),
-// which shortens the item list on the coarse levels; an item is one 64-bit
-// word for F <= 2.
+// the wavefront (whole runs), which shortens the item list on the coarse
+// levels; an item is one 64-bit word for F <= 2.
 
 constexpr int kBinBlocks = 2048;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
-constexpr int kAccWords = 8192;         // LDS accumulator: 8192 int64 = 64 KB
+constexpr int kAccWords = 8192;         // LDS accumulators: 2 x 8192 int64 = 128 KB
 constexpr int kReduceThreads = 1024;    // reduce block: many loads in flight per CU
-constexpr int kReducePerCU = 2;         // reduce blocks resident per CU (64 KB of LDS each)
-constexpr int kRU = 8;                  // items in flight per thread in the reduce
+constexpr int kReducePerCU = 1;         // reduce blocks resident per CU (128 KB of LDS each)
+constexpr int kRU = 8;                  // items in flight per thread in the reduce (more: the F = 4
+                                        // kernel reaches 128 registers, and then gave wrong sums)
+constexpr int64_t kFlushItems = 1 << 21;  // most items a block adds into its LDS copy between flushes
 
 struct BinPlan {
     int l0, lg;            // levels [l0, l0 + lg) in this pass
@@ -327,101 +345,109 @@ __device__ __forceinline__ bool grad_nonzero(const typename Vec<F>::T &gv)
 __device__ __forceinline__ uint32_t absbits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
-// Fixed-point exponent of a level from the bit pattern of its largest
-// |dfeat| (m < 2^e): a contribution w g (w <= 1) becomes the integer
-// rint(w g 2^(23-e)), |q| <= 2^23, and a merged piece of at most kRunCap = 3
-// of them stays below 2^25, inside the 26-bit fields of an item.
-__device__ __forceinline__ int level_exponent(uint32_t maxbits)
+// Top exponent Et = e + 7 of a level's item values, from the bit pattern of
+// its largest |dfeat| (2^(e-1) <= m < 2^e): a corner value w g (w <= 1) is
+// below 2^e, a run of at most 64 of them below 2^(e+6) = 2^(Et-1).
+__device__ __forceinline__ int level_top(uint32_t maxbits)
 {
     if (maxbits == 0u || maxbits >= 0x7f800000u) return 0;
     int e;
     frexpf(__uint_as_float(maxbits), &e);
-    return 23 - e;
+    return e + 7;
 }
 
 // A level takes part when it has a nonzero, finite largest gradient.
 __device__ __forceinline__ bool level_ok(uint32_t maxbits) { return maxbits != 0u && maxbits < 0x7f800000u; }
 
 // Consecutive lanes (consecutive samples of a ray) often hit the same slot on
-// coarse levels.  Each run of equal keys across the wavefront is cut into
-// pieces of at most kRunCap lanes counted from the run's first lane; a
-// piece's last lane emits one item holding the piece's sum.  run_pieces
-// gives this lane's piece start ps, whether it emits (ptail), and the
-// wave's active lanes and piece heads; when no run is longer than one lane
-// it reports exactly that (pheads == acts) without the rest.
-constexpr int kRunCap = 3;
-
-__device__ __forceinline__ void run_pieces(uint32_t key, bool act, unsigned long long &acts,
-                                           unsigned long long &pheads, int &ps, bool &ptail)
+// coarse levels.  Each run of equal keys across the wavefront emits one item,
+// from its last lane, holding the run's sum.  run_bounds gives this lane's
+// run start rs, whether it emits (rtail), and the wave's active lanes and run
+// heads; when no run is longer than one lane it reports exactly that
+// (heads == acts) without the rest.
+__device__ __forceinline__ void run_bounds(uint32_t key, bool act, unsigned long long &acts,
+                                           unsigned long long &heads, int &rs, bool &rtail)
 {
     const int lane = lane_id();
     const uint32_t pk = __shfl_up(key, 1, 64);
     const bool pa = __shfl_up(act ? 1 : 0, 1, 64) != 0;
     const bool head = act && (lane == 0 || !pa || pk != key);
-    const unsigned long long heads = __ballot(head);
+    heads = __ballot(head);
     acts = __ballot(act);
     if (heads == acts) {
-        pheads = heads;
-        ps = lane;
-        ptail = act;
+        rs = lane;
+        rtail = act;
         return;
     }
     const uint32_t nk = __shfl_down(key, 1, 64);
     const bool na = __shfl_down(act ? 1 : 0, 1, 64) != 0;
-    const bool rtail = act && (lane == 63 || !na || nk != key);
+    rtail = act && (lane == 63 || !na || nk != key);
     // start of this lane's run: highest head at or below this lane
     const unsigned long long le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
     const unsigned long long hb = heads & le;
-    const int rs = hb ? 63 - __clzll((long long)hb) : lane;
-    const int off = lane - rs;
-    ps = rs + (off / kRunCap) * kRunCap;
-    pheads = __ballot(act && off % kRunCap == 0);
-    ptail = act && (rtail || off % kRunCap == kRunCap - 1);
+    rs = hb ? 63 - __clzll((long long)hb) : lane;
 }
 
-// Sum each piece across the wavefront (segmented inclusive scan); returns
-// whether this lane emits, with v the piece total there.  The values are
-// integers (fixed point), so merging only regroups exact sums and the
-// result does not depend on which lanes happened to share a wavefront.
+// Sum each run across the wavefront (segmented inclusive scan, FP32); returns
+// whether this lane emits, with v the run total there.  The additions follow
+// the lanes' positions in the wavefront only, and wavefronts always cover the
+// same 64 samples, so the sums are the same bits for any grid.
 template <int F>
-__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, int32_t (&v)[F])
+__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, float (&v)[F])
 {
     const int lane = lane_id();
-    unsigned long long acts, pheads;
-    int ps;
-    bool ptail;
-    run_pieces(key, act, acts, pheads, ps, ptail);
-    if (pheads == acts) return act;                // no piece longer than one lane
-    // Scan steps d = 1, 2, ... complete every piece of up to 2d lanes; c holds
+    unsigned long long acts, heads;
+    int rs;
+    bool rtail;
+    run_bounds(key, act, acts, heads, rs, rtail);
+    if (heads == acts) return act;                 // no run longer than one lane
+    // Scan steps d = 1, 2, ... complete every run of up to 2d lanes; c holds
     // the lanes that end d consecutive continuation lanes (active lanes that
-    // are not a piece's head) and is zero once no piece exceeds the steps
-    // taken.  The count is the same on every lane (it comes from ballots).
-    unsigned long long c = acts & ~pheads;
+    // are not a run's head) and is zero once no run exceeds the steps taken.
+    // The count is the same on every lane (it comes from ballots).
+    unsigned long long c = acts & ~heads;
     for (int d = 1; d < 64 && c != 0ull; d <<= 1) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            const int32_t u = __shfl_up(v[f], d, 64);
-            if (lane - d >= ps) v[f] += u;
+            const float u = __shfl_up(v[f], d, 64);
+            if (lane - d >= rs) v[f] += u;
         }
         c &= c >> d;
     }
-    return ptail;
+    return rtail;
 }
 
-// The lane that emits a piece's item; the same decision as merge_runs,
-// without the sums (the count pass needs only how many items).
+// The lane that emits a run's item; the same decision as merge_runs, without
+// the sums (the count pass needs only how many items).
 __device__ __forceinline__ bool run_tail(uint32_t key, bool act)
 {
-    unsigned long long acts, pheads;
-    int ps;
-    bool ptail;
-    run_pieces(key, act, acts, pheads, ps, ptail);
-    return ptail;
+    unsigned long long acts, heads;
+    int rs;
+    bool rtail;
+    run_bounds(key, act, acts, heads, rs, rtail);
+    return rtail;
+}
+
+// 26-bit item value of v for a level of top exponent Et (see above): sign in
+// bit 25, k = Et - exponent in bits 19..24 (1..63; 0 only for the value 0),
+// mantissa rounded to 19 bits (nearest, ties to even) in bits 0..18.
+// Zeros, subnormals and values below 2^(Et-63) are stored as 0.
+__device__ __forceinline__ uint32_t val_encode(float v, int Et)
+{
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t a = u & 0x7fffffffu;
+    // exponent and mantissa rounded to 19 bits at once: a carry out of the
+    // mantissa moves into the exponent field, as it should
+    const uint32_t r = (a + 0x7u + ((a >> 4) & 1u)) >> 4;
+    const int k = Et + 127 - (int)(r >> 19);
+    // every value is below 2^(Et-1), so k >= 1 unless v is not finite (a level
+    // with a non-finite gradient stores zeros before this point)
+    return (a >= 0x00800000u && k <= 63) ? (((u >> 31) << 25) | ((uint32_t)k << 19) | (r & 0x7ffffu)) : 0u;
 }
 
 // An item is one 64-bit word (F = 1, 2) or two (F = 4): the slot within its
-// bin in the low binshift bits (at most 13), then F fixed-point values of 26
-// bits each (two's complement), the fourth feature's pair in the second word.
+// bin in the low binshift bits (at most 13), then F 26-bit values, the
+// fourth feature's pair in the second word.
 constexpr int kValBits = 26;
 constexpr uint64_t kValMask = (1ull << kValBits) - 1ull;
 
@@ -430,35 +456,57 @@ struct ItemFmt {
     static constexpr int NW = F == 4 ? 2 : 1;
 };
 
-__device__ __forceinline__ int32_t val26(uint64_t field)
-{
-    return (int32_t)((uint32_t)(field & kValMask) << (32 - kValBits)) >> (32 - kValBits);
-}
-
 template <int F>
-__device__ __forceinline__ void item_pack(unsigned long long *dst, uint32_t slot, int sb, const int32_t *v)
+__device__ __forceinline__ void item_pack(unsigned long long *dst, uint32_t slot, int sb, const uint32_t *v)
 {
     uint64_t w0 = (uint64_t)slot;
-    w0 |= ((uint64_t)(uint32_t)v[0] & kValMask) << sb;
-    if constexpr (F >= 2) w0 |= ((uint64_t)(uint32_t)v[1] & kValMask) << (sb + kValBits);
+    w0 |= ((uint64_t)v[0] & kValMask) << sb;
+    if constexpr (F >= 2) w0 |= ((uint64_t)v[1] & kValMask) << (sb + kValBits);
     dst[0] = w0;
-    if constexpr (F == 4)
-        dst[1] = ((uint64_t)(uint32_t)v[2] & kValMask) | (((uint64_t)(uint32_t)v[3] & kValMask) << kValBits);
+    if constexpr (F == 4) dst[1] = ((uint64_t)v[2] & kValMask) | (((uint64_t)v[3] & kValMask) << kValBits);
 }
 
 template <int F>
 __device__ __forceinline__ void item_unpack(const unsigned long long *src, uint32_t smask, int sb, uint32_t &slot,
-                                            int32_t (&v)[F])
+                                            uint32_t (&v)[F])
 {
     const uint64_t w0 = src[0];
     slot = (uint32_t)w0 & smask;
-    v[0] = val26(w0 >> sb);
-    if constexpr (F >= 2) v[1] = val26(w0 >> (sb + kValBits));
+    v[0] = (uint32_t)(w0 >> sb) & (uint32_t)kValMask;
+    if constexpr (F >= 2) v[1] = (uint32_t)(w0 >> (sb + kValBits)) & (uint32_t)kValMask;
     if constexpr (F == 4) {
         const uint64_t w1 = src[1];
-        v[2] = val26(w1);
-        v[3] = val26(w1 >> kValBits);
+        v[2] = (uint32_t)w1 & (uint32_t)kValMask;
+        v[3] = (uint32_t)(w1 >> kValBits) & (uint32_t)kValMask;
     }
+}
+
+// Adds a 26-bit value into the big (unit 2^(Et-41)) or the small (unit
+// 2^(Et-63)) LDS accumulator, without branches (a zero value adds 0).
+__device__ __forceinline__ void val_accumulate(uint32_t code, unsigned long long *big, unsigned long long *small)
+{
+    const int k = (int)((code >> 19) & 63u);
+    const uint32_t m = code ? ((code & 0x7ffffu) | 0x80000u) : 0u;
+    const bool isbig = k <= 22;
+    const int sh = (isbig ? 22 : 44) - k;        // -19 .. 21 (k = 0 only for the value 0)
+    const int shl = sh > 0 ? sh : 0, shr = sh < 0 ? -sh : 0;
+    // below 2^(Et-44) (shr > 0): rounded to the unit, halves away from 0
+    const uint32_t mr = (m + ((1u << shr) >> 1)) >> shr;
+    const uint64_t t = (uint64_t)mr << shl;
+    const uint64_t sgn = (uint64_t)(int64_t)((int32_t)(code << 6) >> 31);   // all ones when negative
+    atomicAdd(isbig ? big : small, (unsigned long long)((t ^ sgn) - sgn));
+}
+
+// Samples of this count/scatter block: a contiguous range of whole 64-sample
+// wavefronts, so that every wavefront covers the same samples (and merges the
+// same runs) whatever the grid.
+__device__ __forceinline__ void block_range(int64_t ne, int64_t &s0, int64_t &s1)
+{
+    const int64_t nw = (ne + 63) >> 6;
+    s0 = (nw * blockIdx.x / gridDim.x) << 6;
+    s1 = (nw * (blockIdx.x + 1) / gridDim.x) << 6;
+    s0 = s0 < ne ? s0 : ne;
+    s1 = s1 < ne ? s1 : ne;
 }
 
 // Runs of equal slots along a ray are worth merging only where cells are
@@ -480,8 +528,8 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) hist[b] = 0;
     if (threadIdx.x < SNAKE_MAX_LEVELS) hmax[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t ne = effective_n(n, n_dev);
-    const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
+    int64_t s0, s1;
+    block_range(effective_n(n, n_dev), s0, s1);
     const int lane = lane_id();
     for (int64_t base = s0; base < s1; base += blockDim.x) {
         const int64_t s = base + threadIdx.x;
@@ -624,7 +672,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
     int *gbase = hoff + bp.nbpl;                        // [nbpl] their first global slot (-1: dropped)
     int *wtot = gbase + bp.nbpl;                        // [8]
     uint32_t *skey = reinterpret_cast<uint32_t *>(wtot + 8);        // [batch]
-    int32_t *sval = reinterpret_cast<int32_t *>(skey + kScatterBatch);  // [batch][F]
+    float *sval = reinterpret_cast<float *>(skey + kScatterBatch);  // [batch][F] item values
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) {
         const int64_t i = (int64_t)b * gridDim.x + blockIdx.x;
         cursor[b] = offsets[i];
@@ -632,8 +680,8 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
     }
     for (int b = threadIdx.x; b < bp.nbpl; b += blockDim.x) hcnt[b] = 0;
     __syncthreads();
-    const int64_t ne = effective_n(n, n_dev);
-    const int64_t s0 = ne * blockIdx.x / gridDim.x, s1 = ne * (blockIdx.x + 1) / gridDim.x;
+    int64_t s0, s1;
+    block_range(effective_n(n, n_dev), s0, s1);
     const int lane = lane_id();
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int64_t base = s0; base < s1; base += blockDim.x) {
@@ -654,7 +702,7 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             const bool dense_l = (g.dense_bits >> l) & 1u;
             const bool merge_l = g.res[l] <= kMergeMaxRes;
             const uint32_t lm = lmax[l];
-            const int E = level_exponent(lm);
+            const int Et = level_top(lm);
             const bool lok = level_ok(lm);
             // the same decision as the count pass; a level without a finite,
             // nonzero maximum emits its items with zero values
@@ -671,16 +719,12 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             // 1. rank every emitted item within its bin for this batch
             uint32_t key[8];
             int rank[8];
-            int32_t v[8][F];
-            // w (g 2^E) is (w g) 2^E: scaling by a power of two is exact
-            float gs[F];
-#pragma unroll
-            for (int f = 0; f < F; ++f) gs[f] = ldexpf(Vec<F>::get(gv, f), E);
+            float v[8][F];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 key[q] = ((uint32_t)tile << bp.T_log2) + idx[q];
 #pragma unroll
-                for (int f = 0; f < F; ++f) v[q][f] = (int32_t)rintf(wt[q] * gs[f]);
+                for (int f = 0; f < F; ++f) v[q][f] = wt[q] * Vec<F>::get(gv, f);
                 rank[q] = -1;
             }
             if (!merge_l && !dense_l) {
@@ -749,8 +793,10 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                 const int bl = (int)(k >> bp.binshift);
                 const int gb = gbase[bl];
                 if (gb < 0) continue;
-                item_pack<F>(items + (int64_t)(gb + (j - hoff[bl])) * ItemFmt<F>::NW, k & smask, bp.binshift,
-                             sval + j * F);
+                uint32_t code[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) code[f] = val_encode(sval[j * F + f], Et);
+                item_pack<F>(items + (int64_t)(gb + (j - hoff[bl])) * ItemFmt<F>::NW, k & smask, bp.binshift, code);
             }
             __syncthreads();
         }
@@ -809,32 +855,41 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, 
                                                                     int nblk, const int64_t *__restrict__ n_items,
                                                                     const unsigned long long *__restrict__ items,
                                                                     const uint32_t *__restrict__ lmax,
-                                                                    unsigned long long *__restrict__ acc64)
+                                                                    unsigned long long *__restrict__ acc)
 {
-    __shared__ unsigned long long acc[kAccWords];
+    // the bin's slots, feature-major (random slots spread over twice the
+    // banks): big[f * slots + slot] and small[...] (units 2^(Et-41), 2^(Et-63))
+    __shared__ unsigned long long big[kAccWords];
+    __shared__ unsigned long long small[kAccWords];
     const int64_t total = *n_items;
     const int slots = 1 << bp.binshift;
     const uint32_t smask = (uint32_t)slots - 1;
     constexpr int NW = ItemFmt<F>::NW;
     // one contiguous, equal share of the pass's items per block (the grid is
     // what the chip holds at once, so there is no tail of late blocks)
-    {
-        const int64_t c0 = total * blockIdx.x / gridDim.x, c1 = total * (blockIdx.x + 1) / gridDim.x;
-        if (c0 >= c1) return;
-        // the bins holding the share's first and last items (items carry only
-        // their slot within the bin)
-        const int bfirst = bin_of_item(offsets, nblk, bp.nb, c0);
-        const int blast = bin_of_item(offsets, nblk, bp.nb, c1 - 1);
-        for (int b = bfirst; b <= blast; ++b) {
-            const int64_t bs = offsets[(int64_t)b * nblk];
-            const int64_t be = b + 1 < bp.nb ? (int64_t)offsets[(int64_t)(b + 1) * nblk] : total;
-            const int64_t lo = bs > c0 ? bs : c0, hi = be < c1 ? be : c1;
-            if (lo >= hi) continue;
-            // the bin's first key: level and table position of slot 0
-            const uint32_t kbase = (uint32_t)b << bp.binshift;
-            const int lr = (int)(kbase >> bp.kt2_log2);
-            if (!level_ok(lmax[bp.l0 + lr])) continue;          // block-uniform
-            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) acc[e] = 0ull;
+    const int64_t c0 = total * blockIdx.x / gridDim.x, c1 = total * (blockIdx.x + 1) / gridDim.x;
+    if (c0 >= c1) return;
+    // the bins holding the share's first and last items (items carry only
+    // their slot within the bin)
+    const int bfirst = bin_of_item(offsets, nblk, bp.nb, c0);
+    const int blast = bin_of_item(offsets, nblk, bp.nb, c1 - 1);
+    for (int b = bfirst; b <= blast; ++b) {
+        const int64_t bs = offsets[(int64_t)b * nblk];
+        const int64_t be = b + 1 < bp.nb ? (int64_t)offsets[(int64_t)(b + 1) * nblk] : total;
+        const int64_t blo = bs > c0 ? bs : c0, bhi = be < c1 ? be : c1;
+        if (blo >= bhi) continue;
+        // the bin's first key: level and table position of slot 0
+        const uint32_t kbase = (uint32_t)b << bp.binshift;
+        const int lr = (int)(kbase >> bp.kt2_log2);
+        if (!level_ok(lmax[bp.l0 + lr])) continue;          // block-uniform
+        unsigned long long *dst = acc + (((int64_t)lr << bp.kt2_log2) + (int64_t)(kbase & ((1u << bp.kt2_log2) - 1u))) * F * 2;
+        // at most kFlushItems items between flushes keep the LDS sums in range
+        for (int64_t lo = blo; lo < bhi; lo += kFlushItems) {
+            const int64_t hi = lo + kFlushItems < bhi ? lo + kFlushItems : bhi;
+            for (int e = threadIdx.x; e < slots * F; e += blockDim.x) {
+                big[e] = 0ull;
+                small[e] = 0ull;
+            }
             __syncthreads();
             // kRU items per thread per round keep enough loads in flight
             for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kRU * blockDim.x) {
@@ -851,31 +906,74 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, 
                 for (int u = 0; u < kRU; ++u) {
                     if (i0 + (int64_t)u * blockDim.x < hi) {
                         uint32_t slot;
-                        int32_t v[F];
+                        uint32_t v[F];
                         item_unpack<F>(w[u], smask, bp.binshift, slot, v);
-                        // feature-major: random slots spread over twice the banks
 #pragma unroll
-                        for (int f = 0; f < F; ++f)
-                            atomicAdd(&acc[f * slots + slot], (unsigned long long)(long long)v[f]);
+                        for (int f = 0; f < F; ++f) val_accumulate(v[f], &big[f * slots + slot], &small[f * slots + slot]);
                     }
                 }
             }
             __syncthreads();
-            // exact: integer partial sums of several chunks add in any order
-            unsigned long long *dst = acc64 + ((int64_t)lr << bp.kt2_log2) * F + (int64_t)(kbase & ((1u << bp.kt2_log2) - 1u)) * F;
+            // W = big 2^22 + small (in units of 2^(Et-63)) as hi 2^52 + lo with
+            // |lo| < 2^51, added with 64-bit integer atomics into the pass-wide
+            // accumulator (exact, so the order of the flushes is irrelevant; a
+            // slot takes at most a few thousand flushes, so lo cannot overflow);
+            // hi is zero, and skipped, unless |W| >= 2^51
             for (int e = threadIdx.x; e < slots * F; e += blockDim.x) {
-                const unsigned long long a = acc[(e % F) * slots + e / F];
-                if (a) atomicAdd(dst + e, a);
+                const int sl = e / F, f = e - sl * F;
+                const long long A = (long long)big[f * slots + sl], B = (long long)small[f * slots + sl];
+                if ((A | B) == 0) continue;
+                const long long s0 = ((A & ((1ll << 30) - 1)) << 22) + (B & ((1ll << 52) - 1));   // [0, 2^53)
+                const long long h0 = (A >> 30) + (B >> 52);
+                const long long q = (s0 + (1ll << 51)) >> 52;                                       // 0, 1 or 2
+                const long long wlo = s0 - (q << 52), whi = h0 + q;
+                if (wlo) atomicAdd(dst + 2 * e, (unsigned long long)wlo);
+                if (whi) atomicAdd(dst + 2 * e + 1, (unsigned long long)whi);
             }
             __syncthreads();
         }
     }
 }
 
-// dtable += the pass's integer sums scaled back by 2^-E_l, one value per
-// table entry (the only floating-point rounding of the sum).
+// x 2^p as FP32 for x = (hi 2^64 + lo), given as sign and magnitude, rounded
+// once to nearest (ties to even) with integer operations only.  (A result
+// below FP32's normal range is rounded a second time by the scaling.)
+__device__ __forceinline__ float scaled_u128(bool neg, uint64_t hi, uint64_t lo, int p)
+{
+    float r;
+    if (hi == 0 && lo < (1ull << 24)) {
+        r = ldexpf((float)(uint32_t)lo, p);      // the integer is exact in FP32
+    } else {
+        const int bl = hi ? 128 - __clzll((long long)hi) : 64 - __clzll((long long)lo);   // bit length, > 24
+        const int sh = bl - 24;                  // >= 1
+        // the top 24 bits, the bit below them, and whether anything below that is set
+        uint64_t top, half, sticky;
+        if (sh >= 64) {
+            const int rb = sh - 64;              // bits of hi below the top 24
+            top = hi >> rb;
+            if (rb == 0) {
+                half = lo >> 63;
+                sticky = lo & ~(1ull << 63);
+            } else {
+                const uint64_t below = hi & ((1ull << rb) - 1ull);
+                half = (below >> (rb - 1)) & 1ull;
+                sticky = (below & ((1ull << (rb - 1)) - 1ull)) | lo;
+            }
+        } else {
+            top = (lo >> sh) | (hi << (64 - sh));   // x < 2^(sh+24): the shifted value has 24 bits
+            half = (lo >> (sh - 1)) & 1ull;
+            sticky = lo & ((1ull << (sh - 1)) - 1ull);
+        }
+        if (half && (sticky || (top & 1ull))) ++top;     // 2^24 stays exact
+        r = ldexpf((float)(uint32_t)top, sh + p);
+    }
+    return neg ? -r : r;
+}
+
+// dtable += the pass's exact sums, hi 2^52 + lo units of 2^(Et-63), rounded
+// once to FP32 (one value per table entry).
 template <int F>
-__global__ __launch_bounds__(256) void bin_convert_kernel(BinPlan bp, int L, const unsigned long long *__restrict__ acc64,
+__global__ __launch_bounds__(256) void bin_convert_kernel(BinPlan bp, int L, const unsigned long long *__restrict__ acc,
                                                           const uint32_t *__restrict__ lmax, int K,
                                                           float *__restrict__ dtable)
 {
@@ -884,12 +982,22 @@ __global__ __launch_bounds__(256) void bin_convert_kernel(BinPlan bp, int L, con
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int lr = (int)(e / per_level);
         const int64_t r = e - (int64_t)lr * per_level;              // key * F + f
-        const long long sv = (long long)acc64[((int64_t)lr << bp.kt2_log2) * F + r];
-        if (sv == 0) continue;
+        const int64_t a = (((int64_t)lr << bp.kt2_log2) * F + r) * 2;
+        const long long lo = (long long)acc[a], hi = (long long)acc[a + 1];
+        if ((lo | hi) == 0) continue;
+        // V = hi 2^52 + lo as a 128-bit two's-complement pair (vh, vl)
+        uint64_t vl = (uint64_t)lo + ((uint64_t)hi << 52);
+        const uint64_t carry = vl < (uint64_t)lo ? 1ull : 0ull;
+        uint64_t vh = (uint64_t)((hi >> 12) + (lo >> 63)) + carry;
+        const bool neg = (int64_t)vh < 0;
+        if (neg) {                               // magnitude
+            vl = ~vl + 1ull;
+            vh = ~vh + (vl == 0ull ? 1ull : 0ull);
+        }
         const int64_t key = r / F, f = r - key * F;
         const int64_t tile = key >> bp.T_log2, idx = key & ((1ll << bp.T_log2) - 1);
-        const int E = level_exponent(lmax[bp.l0 + lr]);
-        dtable[((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + f] += (float)ldexp((double)sv, -E);
+        const int Et = level_top(lmax[bp.l0 + lr]);
+        dtable[((tile * L + bp.l0 + lr) << bp.T_log2) * F + idx * F + f] += scaled_u128(neg, vh, vl, Et - 63);
     }
 }
 
@@ -906,12 +1014,12 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace of a pass over lg levels for n samples: counts, offsets, scan
 // sums, the item count, per-level maxima, the pass's integer accumulator
-// (lg x 2^kt2 x F int64) and the items.
+// (lg x 2^kt2 x F x two int64) and the items.
 static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F, int kt2_log2)
 {
     const int64_t ncnt = (int64_t)nb * kBinBlocks;
     return align256((size_t)SNAKE_MAX_LEVELS * 4) + 2 * align256((size_t)ncnt * 4) +
-           align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 + align256(((size_t)lg << kt2_log2) * F * 8) +
+           align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 + align256(((size_t)lg << kt2_log2) * F * 16) +
            align256((size_t)n * lg * 8 * (F == 4 ? 2 : 1) * 8);
 }
 
@@ -924,7 +1032,7 @@ static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
     int kt = log2T;
     while ((1 << (kt - log2T)) < K) ++kt;      // padded K*T
     bp.kt2_log2 = kt;
-    const int acc_log2 = F == 1 ? 13 : F == 2 ? 12 : 11;   // 2^acc_log2 * F int64 = 64 KB
+    const int acc_log2 = F == 1 ? 13 : F == 2 ? 12 : 11;   // 2^acc_log2 * F int64 = 64 KB (one accumulator)
     bp.binshift = kt < acc_log2 ? kt : acc_log2;
     bp.nbpl = 1 << (kt - bp.binshift);
     bp.nb = lg * bp.nbpl;
@@ -1119,7 +1227,7 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
         p += align256((size_t)scan::scan_blocks(ncnt) * 8);
         w.n_items = reinterpret_cast<int64_t *>(p);
         p += 256;
-        const int64_t n_acc = ((int64_t)lgp << bp.kt2_log2) * F;
+        const int64_t n_acc = ((int64_t)lgp << bp.kt2_log2) * F * 2;
         w.acc64 = reinterpret_cast<unsigned long long *>(p);
         p += align256((size_t)n_acc * 8);
         w.items = reinterpret_cast<unsigned long long *>(p);

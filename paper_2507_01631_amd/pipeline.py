@@ -8,7 +8,7 @@ Sec. 4.4 -> adjoints -> Adam, the I-NGP strategy of Sec. 4.6):
     -> snake_composite_fwd (early stop -> n_alive)
     -> snake_composite_bwd -> snake_pack_alive
     -> snake_mlp_bwd (recompute, or stored activations)
-    -> snake_hashgrid_bwd (binned fixed-point sums, or FP32 atomics)
+    -> snake_hashgrid_bwd (binned exact integer sums, or FP32 atomics)
     -> snake_adam_step (table) + snake_adam_step (MLP)
 
 PyTorch only owns device memory and the stream; every step runs in libsnake.

@@ -61,6 +61,51 @@ def assert_grad(got, ref, tol=1e-4, what=""):
         what, worst, tol, np.max(np.abs(ref)))
 
 
+def binned_floor(orc, res, log2T, pos, dfeat, F):
+    """Per table entry, the absolute part of the binned adjoint's error bound:
+    (number of corner contributions it receives) x 2^(e_l - 56), where
+    2^(e_l - 1) <= max|dfeat| of level l < 2^e_l.  Each value is stored with
+    its exponent counted down from the level's largest gradient, so a value
+    more than 37 binades below it is rounded to a multiple of 2^(e_l - 56)
+    and one more than 56 below it is stored as 0.  dfeat float64 [n][L*F];
+    returns float64 [L][T][F]."""
+    Lv, T = len(res), 1 << log2T
+    out = np.zeros((Lv, T))
+    _, idx = orc.hashgrid_fwd(res, log2T, np.zeros((1, Lv, T, F), np.float32), pos, None, Lv * F,
+                              return_index=True)
+    for l in range(Lv):
+        d = dfeat[:, l * F:(l + 1) * F]
+        m = float(np.max(np.abs(d)))
+        if m == 0.0:
+            continue
+        e = np.frexp(m)[1]
+        act = np.any(d != 0.0, axis=1)
+        cnt = np.bincount(idx[act, l, :].ravel().astype(np.int64), minlength=T)
+        out[l] = cnt * 2.0 ** (e - 56)
+    return np.repeat(out[:, :, None], F, axis=2)
+
+
+def assert_binned_bound(got, ref, absref, floor, what):
+    """The binned adjoint's own error bound, entry by entry: every stored value
+    is rounded once to 20 significant bits after at most a 64-term FP32 run
+    sum (at most about 2^-18 of the run's absolute sum), or below 2^-37 of the
+    level's largest gradient to the absolute unit in `floor` (binned_floor);
+    the sums are exact and the entry is rounded once to FP32, so
+    |got - ref| <= 2^-17 sum|w g| + 2^-22 |ref| + floor (absref = sum|w g|
+    per entry, from the oracle)."""
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    absref = np.asarray(absref, np.float64).ravel()
+    floor = np.asarray(floor, np.float64).ravel()
+    err = np.abs(got - ref)
+    lim = 2.0 ** -17 * absref + 2.0 ** -22 * np.abs(ref) + floor + 1e-38
+    bad = err > lim
+    w = np.argmax(err / lim)
+    assert not bad.any(), "%s: %d entries outside the rounding bound; worst got %r ref %r sum|c| %r floor %r" % (
+        what, int(bad.sum()), got[w], ref[w], absref[w], floor[w])
+    return lim
+
+
 def run_sampler(L, rays_o, rays_d, boxes, S, zband=None, spr=None, max_count=None, cap=None):
     R = int(np.asarray(rays_o).shape[0])
     if cap is None:

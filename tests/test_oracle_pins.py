@@ -718,6 +718,75 @@ def test_bf16_emulation_matches_torch_rounding(orc, which):
     np.testing.assert_allclose(c_e, rgb, rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("which", ["tiny", "full"])
+def test_bf16_adjoint_emulation(orc, which):
+    """The 16-bit adjoint emulation (mlp_bwd_q): with rounding off it is the
+    FP64 adjoint bit for bit (the same terms in the same order, so the FD pins
+    of mlp_bwd carry over); with rounding on it equals a NumPy chain that rounds
+    the same operands with torch's float32 -> bfloat16 conversion."""
+    import torch
+    rng = np.random.default_rng(18)
+    m = synth.tiny_tile().mlp if which == "tiny" else synth.MlpConfig(
+        feat_real=32, n_dir=6, colour_layers=2, colour_out=4)
+    w = synth.init_mlp(rng, m) * np.float32(2.0)
+    n = 400
+    feat = rng.normal(scale=0.5, size=(n, 32))
+    view = rng.normal(size=(n, 3)).astype(np.float32)
+    sun = rng.normal(size=(n, 3)).astype(np.float32) if m.n_dir == 6 else None
+    rid = np.arange(n, dtype=np.int32)
+    dsig = rng.normal(size=n)
+    drgb = rng.normal(size=(n, 3))
+    dW0, df0 = orc.mlp_bwd(m, w, feat, view, rid, dsig, drgb, sun=sun)
+    dWq0, dfq0 = orc.mlp_bwd_q(m, w, feat, view, rid, dsig, drgb, sun=sun, round16=0)
+    assert np.array_equal(dW0, dWq0) and np.array_equal(df0, dfq0)
+    # rounding on: the same chain written with NumPy products and torch's rounding
+    bf = lambda a: torch.tensor(np.asarray(a, np.float64)).float().bfloat16().double().numpy()
+    shapes = synth.mlp_param_shapes(m)
+    mats, o = [], 0
+    for (a, b) in shapes:
+        mats.append(bf(w[o:o + a * b]).reshape(a, b))
+        o += a * b
+    CL = m.colour_layers
+    x = bf(feat)
+    h1 = np.maximum(x @ mats[0].T, 0)
+    h1q = bf(h1)
+    out = h1q @ mats[1].T
+    ci = np.concatenate([bf(out[:, 1:]), bf(view)] + ([bf(sun)] if m.n_dir == 6 else []), 1)
+    gs, gq = [], []
+    prev = ci
+    for li in range(CL):
+        gl = np.maximum(prev @ mats[2 + li].T, 0)
+        gs.append(gl)
+        gq.append(bf(gl))
+        prev = gq[-1]
+    y = prev @ mats[2 + CL].T
+    sg = lambda v: 1 / (1 + np.exp(-v))
+    if m.colour_out == 3:
+        dout = drgb * sg(y) * (1 - sg(y))
+    else:
+        alb, vis = sg(y[:, :3]), sg(y[:, 3:4])
+        dout = np.concatenate([drgb * vis * alb * (1 - alb), (drgb * alb).sum(1, keepdims=True) * vis * (1 - vis)], 1)
+    dout = bf(dout)
+    dWs = [None] * len(mats)
+    dWs[2 + CL] = dout.T @ gq[-1]
+    dg = bf((dout @ mats[2 + CL]) * (gs[-1] > 0))
+    for li in range(CL - 1, 0, -1):
+        dWs[2 + li] = dg.T @ gq[li - 1]
+        dg = bf((dg @ mats[2 + li]) * (gs[li - 1] > 0))
+    dWs[2] = dg.T @ ci
+    dos = bf(np.concatenate([(dsig * np.exp(out[:, 0]))[:, None], dg @ mats[2][:, :m.dens_out - 1]], 1))
+    dWs[1] = dos.T @ h1q
+    dh = bf((dos @ mats[1]) * (h1 > 0))
+    dWs[0] = dh.T @ x
+    dfeat = dh @ mats[0]
+    dW = np.concatenate([d.ravel() for d in dWs])
+    dWq, dfq = orc.mlp_bwd_q(m, w, feat, view, rid, dsig, drgb, sun=sun, round16=1)
+    np.testing.assert_allclose(dfq, dfeat, rtol=1e-10, atol=1e-12 * np.abs(dfeat).max())
+    np.testing.assert_allclose(dWq, dW, rtol=1e-10, atol=1e-12 * np.abs(dW).max())
+    # and the rounding is real: the 16-bit adjoint is not the FP64 one
+    assert not np.allclose(dWq, dW0, rtol=1e-6)
+
+
 def test_train_step_per_tile_weights_reduce_to_shared(orc):
     """Window step on 2x2 tiles with one weight set per tile: when the four
     sets are equal, the forward, the loss and the table gradient are those of
