@@ -1,9 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of one tile-NeRF training step on one MI355X.
 
-Metric: ray-samples/s for forward + backward + Adam, BF16-MFMA MLP form (the
-reported value) beside the FP32 form, with the dominant kernel's fraction of
-its roofline.  A "step" is one pass of the whole path over one batch of rays:
+Metric: ray-samples/s for forward + backward + Adam of the BF16-MFMA form
+(BF16 networks with FP32 accumulation, FP32 hash table and Adam state: the
+reported value) beside the FP32 form and a form whose forward also gathers
+from a BF16 copy of the table, with the dominant kernel's fraction of its
+roofline.  Also: held-out PSNR of the three forms after a fixed number of
+steps, the binned table adjoint against the FP32-atomic one in training, the
+step on an opaque field where early stop truncates most rays, the 2x2 window
+and the snake sweep, and the FP64 CPU oracle's rate.  A "step" is one pass of the whole path over one batch of rays:
 segmented sampling -> hash encoding -> density/colour MLP -> volume rendering
 + MSE loss -> composite adjoint -> MLP adjoint (recomputed activations) ->
 binned exact-sum hash-table adjoint -> Adam on the table and the MLP.
@@ -65,21 +70,29 @@ def mlp_macs(n_dir, colour_layers, colour_out, feat=32, hidden=64, dens_out=16):
             + (colour_layers - 1) * hidden * hidden + hidden * colour_out)
 
 
-def make_nerf(wl, precision, max_rays, device):
+# The forms timed: name -> (MLP precision, forward gathers from a BF16 table copy).
+# "bf16" is the form the metric names (BF16-MFMA networks, FP32 hash table),
+# "bf16_t16" also gathers the encoding from a BF16 copy of the table.
+FORMS = {"bf16": ("bf16", False), "fp32": ("fp32", False), "bf16_t16": ("bf16", True)}
+
+
+def make_nerf(wl, form, max_rays, device, **kw):
     from paper_2507_01631_amd import TileNeRF, level_resolutions
     g, m = wl.grid, wl.mlp
+    precision, table_bf16 = FORMS[form]
     return TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
                     log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
                     colour_out=m.colour_out, boxes=wl.boxes, zband=wl.zband, samples=wl.samples_per_ray,
-                    early_stop=wl.early_stop, precision=precision, table=wl.table,
-                    mlp_params=wl.mlp_params, max_rays=max_rays, lr=wl.lr, device=device)
+                    early_stop=wl.early_stop, precision=precision, table=wl.table, table_bf16=table_bf16,
+                    mlp_params=wl.mlp_params, max_rays=max_rays, lr=wl.lr, device=device, **kw)
 
 
-def run_form(wl, precision, args, pool):
+def run_form(wl, precision, args, pool, steps=None, tune=None, nerf=None):
     import torch
     dev = "cuda:0"
     R = args.rays
-    nerf = make_nerf(wl, precision, R, dev)
+    if nerf is None:
+        nerf = make_nerf(wl, precision, R, dev)
     ro_all, rd_all, tg_all, sun_all = pool
     nb = args.batches
 
@@ -93,7 +106,7 @@ def run_form(wl, precision, args, pool):
     torch.cuda.synchronize()
     log("  %s: warmup %d steps done" % (precision, args.warmup))
     tuned = None
-    if args.tune:
+    if (args.tune if tune is None else tune):
         # launch shapes for this workload, picked by timing (untimed region)
         from paper_2507_01631_amd import autotune
         cnt = [0]
@@ -107,7 +120,7 @@ def run_form(wl, precision, args, pool):
         from paper_2507_01631_amd import autotune
         tuned = autotune.current()
 
-    K = args.steps
+    K = args.steps if steps is None else steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)] for _ in range(K)]
     n_alive = torch.zeros(K, dtype=torch.int64, device=dev)
     n_total = torch.zeros(K, dtype=torch.int64, device=dev)
@@ -177,8 +190,9 @@ def run_form(wl, precision, args, pool):
                 mlp_params=int(nerf.P), L=len(nerf.res), F=nerf.F, tuned=tuned, table_bf16=nerf.table_bf16)
 
 
-def roofline(form, wl, precision, R):
+def roofline(form, wl, name, R):
     """Algorithmic work per launch of each stage and its rate against peak."""
+    precision = FORMS[name][0]
     Lv, F = form["L"], form["F"]
     nt, na = form["samples_total"], form["samples_alive"]
     fb = 2 if precision == "bf16" else 4
@@ -354,7 +368,8 @@ def sweep_bench(args):
     out = {"config": "tiles L=16 F=2 T=2^19 (FP32 table + Adam), BF16 MLP 32-64-16 / 18-64-3; %d rays x "
                      "64..128 samples per step, %d steps per window" % (R, steps), "grids": []}
     for n in args.sweep_grids:
-        sw = SnakeSweep(n, n, precision="bf16", max_rays=R, samples=128, seed=n, device=dev, **kw)
+        init = synth.tile_init(n, 16, 2, 19, synth.MlpConfig(feat_real=32, n_dir=3, colour_layers=1, colour_out=3))
+        sw = SnakeSweep(n, n, init_tile=init, precision="bf16", max_rays=R, samples=128, device=dev, **kw)
         t = sw.run(steps, batches, graph=True)
         npath = len(snake_path(n, n))
         # the first window also pays for the graph capture and the initial load
@@ -388,15 +403,48 @@ def sweep_bench(args):
     return out
 
 
+def _heldout_psnr(nerf, held):
+    import torch
+    Rh = held[0].shape[0]
+    nerf.sample(held[0], held[1], Rh)
+    nerf.field_fwd(held[3])
+    nerf.render(Rh)
+    torch.cuda.synchronize()
+    mse = float(((nerf.rgb_out[:Rh] - held[2]) ** 2).mean().item())
+    return -10.0 * np.log10(max(mse, 1e-12))
+
+
+def _train(nerf, pool, R, nb, steps, off, name, occ_start=None):
+    """steps training steps on the batch cycle starting at offset off; returns
+    (seconds, samples entering the adjoint at the last step)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kept = 0
+    for k in range(steps):
+        b = (k + off) % nb
+        sl = slice(b * R, (b + 1) * R)
+        if nerf.G and occ_start is not None and k >= occ_start and k % 16 == 0:
+            nerf.update_occupancy()
+        n_dev = nerf.train_step(pool[0][sl], pool[1][sl], pool[2][sl], pool[3][sl])
+        if k == steps - 1:
+            kept = int(n_dev.item())
+        if (k + 1) % 250 == 0:
+            torch.cuda.synchronize()
+            log("    %s step %d (%.1f s)" % (name, k + 1, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, kept
+
+
 def convergence(args):
-    """BF16 against FP32 at equal step count on the full-tile scene: both forms
-    train from the same initial table and networks on the same cycle of ray
-    batches; the held-out ninth view (256^2 rays) is then rendered and its
-    PSNR against the scene's own rendering compared (both with early stop
-    only), as means over --conv-orders orders of the batch cycle.  With the
-    occupancy grid on, one more BF16 run trains with culling
-    (grid refreshed every 16 steps from step --conv-occ-start) and gives
-    culling's effect on PSNR and on the step time."""
+    """The three forms at equal step count on the full-tile scene: each trains
+    from the same initial table and networks on the same cycle of ray batches;
+    the held-out ninth view (256^2 rays) is then rendered and its PSNR against
+    the scene's own rendering compared (early stop only), as means over
+    --conv-orders orders of the batch cycle.  With the occupancy grid on, one
+    more run of the reported form trains with culling (grid refreshed every 16
+    steps from step --conv-occ-start) and gives culling's effect on PSNR and
+    on the step time."""
     import torch
     import synth
     dev = "cuda:0"
@@ -412,62 +460,131 @@ def convergence(args):
     out = {"config": "full_tile, %d rays/step, %d steps, lr %g, batches cycled from %d, occupancy grid %s"
                      % (R, steps, wl.lr, nb, "%d^3 (optical thickness of one step > min(0.01, mean))" % G
                         if G else "off")}
-    from paper_2507_01631_amd import TileNeRF, level_resolutions
-    g, m = wl.grid, wl.mlp
-    # the FP32 trajectory is sensitive to last-bit changes, so the two forms
-    # are compared over several orders of the batches (offsets of the cycle)
+    # the trajectories are sensitive to last-bit changes, so the forms are
+    # compared over several orders of the batches (offsets of the cycle)
     offsets = [0, 1, 3, 5, 2, 4, 6, 7][:max(1, args.conv_orders)]
-    runs = [(p, 0, o) for o in offsets for p in ("fp32", "bf16")] + ([("bf16", G, 0)] if G else [])
-    for prec, grid, off in runs:
-        name = (prec if grid == 0 else prec + "_grid") + ("" if off == 0 else "_order%d" % off)
-        nerf = TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
-                        log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
-                        colour_out=m.colour_out, boxes=wl.boxes, zband=wl.zband, samples=wl.samples_per_ray,
-                        early_stop=wl.early_stop, precision=prec, table=wl.table, mlp_params=wl.mlp_params,
-                        max_rays=max(R, held[0].shape[0]), lr=wl.lr, occ_grid=grid, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        kept = 0
-        for k in range(steps):
-            b = (k + off) % nb
-            sl = slice(b * R, (b + 1) * R)
-            if nerf.G and k >= args.conv_occ_start and k % 16 == 0:
-                nerf.update_occupancy()
-            n_dev = nerf.train_step(pool[0][sl], pool[1][sl], pool[2][sl], pool[3][sl])
-            if k == steps - 1:
-                kept = int(n_dev.item())
-            if (k + 1) % 250 == 0:
-                torch.cuda.synchronize()
-                log("    %s step %d (%.1f s)" % (name, k + 1, time.perf_counter() - t0))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        Rh = held[0].shape[0]
-        nerf.sample(held[0], held[1], Rh)
-        nerf.field_fwd(held[3])
-        nerf.render(Rh)
-        torch.cuda.synchronize()
-        mse = float(((nerf.rgb_out[:Rh] - held[2]) ** 2).mean().item())
-        psnr = -10.0 * np.log10(max(mse, 1e-12))
-        out[name] = {"psnr_db": round(psnr, 3), "train_s": round(dt, 3), "ms_per_step": round(1e3 * dt / steps, 3),
-                     "samples_last_step": kept}
+    forms = ("fp32", "bf16", "bf16_t16")
+    runs = [(p, 0, o) for o in offsets for p in forms] + ([("bf16", G, 0)] if G else [])
+    for form, grid, off in runs:
+        name = (form if grid == 0 else form + "_grid") + ("" if off == 0 else "_order%d" % off)
+        nerf = make_nerf(wl, form, max(R, held[0].shape[0]), dev, occ_grid=grid)
+        dt, kept = _train(nerf, pool, R, nb, steps, off, name, args.conv_occ_start if grid else None)
+        out[name] = {"psnr_db": round(_heldout_psnr(nerf, held), 3), "train_s": round(dt, 3),
+                     "ms_per_step": round(1e3 * dt / steps, 3), "samples_last_step": kept}
         if nerf.G:
             out[name]["occupied_fraction"] = round(nerf.occupied_fraction(), 4)
         log("  convergence %s: %s" % (name, json.dumps(out[name])))
         del nerf
 
-    def mean_psnr(p):
-        return float(np.mean([out[p + ("" if o == 0 else "_order%d" % o)]["psnr_db"] for o in offsets]))
+    def psnrs(p):
+        return [out[p + ("" if o == 0 else "_order%d" % o)]["psnr_db"] for o in offsets]
     out["orders"] = offsets
-    out["psnr_fp32_mean_db"] = round(mean_psnr("fp32"), 3)
-    out["psnr_bf16_mean_db"] = round(mean_psnr("bf16"), 3)
+    for p in forms:
+        v = psnrs(p)
+        out["psnr_%s_mean_db" % p] = round(float(np.mean(v)), 3)
+        out["psnr_%s_spread_db" % p] = round(float(np.max(v) - np.min(v)), 3)
+    gaps = [b - a for a, b in zip(psnrs("fp32"), psnrs("bf16"))]
     out["psnr_gap_db"] = round(out["psnr_bf16_mean_db"] - out["psnr_fp32_mean_db"], 3)
+    out["psnr_gap_per_order_db"] = [round(x, 3) for x in gaps]
+    out["psnr_gap_t16_db"] = round(out["psnr_bf16_t16_mean_db"] - out["psnr_fp32_mean_db"], 3)
+    out["within_0p1_db"] = bool(out["psnr_gap_db"] >= -0.1)
     if G:
         out["culling_psnr_delta_db"] = round(out["bf16_grid"]["psnr_db"] - out["bf16"]["psnr_db"], 3)
         out["culling_speedup"] = round(out["bf16"]["ms_per_step"] / out["bf16_grid"]["ms_per_step"], 3)
     return out
 
 
+def atomic_convergence(args):
+    """The binned table adjoint against the direct FP32-atomic one (the
+    reported form otherwise), trained side by side for --atomic-steps steps on
+    --atomic-rays rays per step from the same start: held-out PSNR of each and
+    the adjoint's time per call."""
+    import torch
+    import synth
+    dev = "cuda:0"
+    R, steps, nb = args.atomic_rays, args.atomic_steps, 8
+    wl = synth.full_tile(seed=0, n_rays=R * nb)
+    ho, hd, ht, hs = synth.full_tile_heldout(wl, 256)
+    pool = [torch.as_tensor(x).to(dev) for x in (wl.rays_o, wl.rays_d, wl.target, wl.sun)]
+    held = [torch.as_tensor(x).to(dev) for x in (ho, hd, ht, hs)]
+    out = {"config": "full_tile, bf16 form, %d rays/step, %d steps" % (R, steps)}
+    from paper_2507_01631_amd import _lib as L
+    for mode in ("binned", "atomic"):
+        nerf = make_nerf(wl, "bf16", max(R, held[0].shape[0]), dev, hash_bwd=mode)
+        dt, kept = _train(nerf, pool, R, nb, steps, 0, "adjoint_" + mode)
+        # one timed adjoint call on the last step's feature gradients
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        idx = nerf.alive_idx if nerf.early_stop > 0 else None
+        n_dev = nerf.n_alive_total if nerf.early_stop > 0 else nerf.n_out
+        ms = []
+        for _ in range(3):
+            e0.record()
+            L.snake_hashgrid_bwd(nerf.grid, nerf.K, nerf.pos, nerf.tile_id, idx, nerf.cap, n_dev, nerf.dfeat,
+                                 nerf.g_t, nerf.ws_hash)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        nerf.g_t.zero_()
+        out[mode] = {"psnr_db": round(_heldout_psnr(nerf, held), 3), "ms_per_step": round(1e3 * dt / steps, 3),
+                     "adjoint_ms": round(float(np.median(ms)), 3), "samples_last_step": kept}
+        log("  adjoint %s: %s" % (mode, json.dumps(out[mode])))
+        del nerf
+    out["psnr_binned_minus_atomic_db"] = round(out["binned"]["psnr_db"] - out["atomic"]["psnr_db"], 3)
+    return out
+
+
+def ragged_bench(args, wl, pool):
+    """The reported form's step on a seeded opaque field, so that early stop
+    truncates most rays: the table drawn from U(-1, 1) and the density
+    logit's weights made positive and 4x steeper (the ragged-count case of
+    the full-tile workload).  The forward still evaluates every packed
+    sample; the adjoints and the table gradient take only the kept ones."""
+    import copy
+    wo = copy.copy(wl)
+    rng = np.random.default_rng(8)
+    wo.table = rng.uniform(-1, 1, size=wl.table.shape).astype(np.float32)
+    mp = wl.mlp_params.copy()
+    row = slice(64 * 32, 64 * 32 + 64)                  # density-logit row of the second density layer
+    mp[row] = np.abs(mp[row]) * np.float32(4.0)
+    wo.mlp_params = mp
+    nerf = make_nerf(wo, "bf16", args.rays, "cuda:0")
+    r = run_form(wo, "bf16", args, pool, steps=10, tune=0, nerf=nerf)
+    out = {"config": "full_tile rays on an opaque seeded field (table U(-1,1), steep density head), bf16 form",
+           "ms_per_step": round(r["ms_per_step"], 3), "samples_total_per_step": r["samples_total"],
+           "samples_alive_per_step": r["samples_alive"],
+           "alive_fraction": round(r["samples_alive"] / max(r["samples_total"], 1.0), 4),
+           "samples_alive_per_s": r["value"],
+           "samples_total_per_s": r["samples_total"] / (r["ms_per_step"] * 1e-3),
+           "stages_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}}
+    log("  ragged: %s" % json.dumps(out))
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+_ONE_CORE = """
+import json, sys, time
+sys.path.insert(0, %r)
+import oracle, synth
+wl = synth.full_tile(seed=0, n_rays=%d)
+oracle.lib()
+t = time.perf_counter()
+out = oracle.train_step(wl)
+print(json.dumps({"samples": int(out["n_samples"]), "s": time.perf_counter() - t}))
+"""
+
+
 def cpu_baseline(args):
+    import subprocess
     import oracle
     import synth
     wl = synth.full_tile(seed=0, n_rays=args.cpu_rays)
@@ -476,10 +593,23 @@ def cpu_baseline(args):
     out = oracle.train_step(wl)
     dt = time.perf_counter() - t
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": out["n_samples"] / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
-            "sample": "one full step (sampler, encoding, MLP, rendering, adjoints, Adam) of the "
-                      "full-tile workload on %d rays (%d samples after early stop), FP64 C oracle, "
-                      "%.1f s" % (args.cpu_rays, out["n_samples"], dt)}
+    res = {"value": out["n_samples"] / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
+           "cpu_model": _cpu_model(),
+           "sample": "one full step (sampler, encoding, MLP, rendering, adjoints, Adam) of the "
+                     "full-tile workload on %d rays (%d samples after early stop), FP64 C oracle, "
+                     "%d threads, %.1f s" % (args.cpu_rays, out["n_samples"], cores, dt)}
+    # the same on one thread, in a child process (OpenMP fixes its team at start)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", _ONE_CORE % (ROOT, args.cpu_rays_1t)], env=env,
+                           capture_output=True, text=True, timeout=600)
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        res["one_core"] = {"value": one["samples"] / one["s"], "cores": 1,
+                           "sample": "the same step on %d rays (%d samples), 1 thread, %.1f s"
+                                     % (args.cpu_rays_1t, one["samples"], one["s"])}
+    except (subprocess.SubprocessError, ValueError, IndexError, KeyError) as e:
+        res["one_core"] = {"error": str(e)[:200]}
+    return res
 
 
 def main():
@@ -489,7 +619,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--rays", type=int, default=1 << 18)
     ap.add_argument("--batches", type=int, default=2, help="distinct ray batches cycled through")
-    ap.add_argument("--precision", choices=["bf16", "fp32", "both"], default="both")
+    ap.add_argument("--precision", choices=["bf16", "fp32", "bf16_t16", "all"], default="all",
+                    help="bf16: BF16-MFMA networks, FP32 table (the reported value); bf16_t16: also a BF16 "
+                         "table copy for the forward gathers; fp32: FP32 networks")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the opaque-field (early stop) timing")
+    ap.add_argument("--atomic-steps", type=int, default=500,
+                    help="steps of the binned-vs-atomic table adjoint training comparison (0: skip)")
+    ap.add_argument("--atomic-rays", type=int, default=1 << 15)
+    ap.add_argument("--cpu-rays-1t", type=int, default=1 << 13,
+                    help="rays of the single-thread CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", type=int, default=1, help="autotune launch shapes before timing (1) or not (0)")
     ap.add_argument("--shape", action="append", default=[], metavar="NAME=VALUE",
@@ -503,7 +641,7 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=5)
     ap.add_argument("--sweep-rays", type=int, default=1 << 16)
     ap.add_argument("--render-px", type=int, default=2048)
-    ap.add_argument("--convergence-steps", type=int, default=0,
+    ap.add_argument("--convergence-steps", type=int, default=500,
                     help="also train FP32 and BF16 this many steps and compare held-out PSNR")
     ap.add_argument("--conv-rays", type=int, default=1 << 17)
     ap.add_argument("--conv-orders", type=int, default=2,
@@ -541,7 +679,7 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % a.numel())
         del a, b
-    forms = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
+    forms = ["bf16", "fp32", "bf16_t16"] if args.precision == "all" else [args.precision]
     res = {}
     for p in forms:
         res[p] = run_form(wl, p, args, pool)
@@ -559,7 +697,8 @@ def main():
                                "%d rays/batch, <=128 samples/ray, z band [0.2,0.8], early stop 1e-4"
                                % args.rays,
                    "rays_per_step": args.rays, "samples_alive_per_step": f["samples_alive"],
-                   "samples_total_per_step": f["samples_total"], "precision": head},
+                   "samples_total_per_step": f["samples_total"], "form": head,
+                   "mlp_precision": FORMS[head][0], "hash_table": "bf16 copy" if FORMS[head][1] else "fp32"},
         "roofline": {"kernel": dom, "bound": "hbm" if d["bound"] == "hbm" else "mfma",
                      "achieved": d["achieved"] / (1e9 if d["bound"] == "hbm" else 1e12),
                      "peak": d["peak"] / (1e9 if d["bound"] == "hbm" else 1e12),
@@ -572,9 +711,14 @@ def main():
     }
     for p in forms[1:]:
         g = res[p]
+        rg = roofline(g, wl, p, args.rays)
         line["%s_form" % p] = {"value": g["value"], "ms_per_step": g["ms_per_step"],
                                "samples_alive_per_step": g["samples_alive"],
-                               "stages_ms": {k: round(v, 4) for k, v in g["stage_ms"].items()}}
+                               "mlp_precision": FORMS[p][0], "hash_table": "bf16 copy" if FORMS[p][1] else "fp32",
+                               "stages": {k: {"ms": round(v["ms"], 4), "frac": round(v["frac"], 4)}
+                                          for k, v in rg.items()}}
+    if not args.no_ragged:
+        line["ragged"] = ragged_bench(args, wl, pool)
     if not args.no_window:
         line["window"] = window_bench(args)
     if not args.no_recompute_check:
@@ -583,6 +727,8 @@ def main():
         line["sweep"] = sweep_bench(args)
     if args.convergence_steps > 0:
         line["convergence"] = convergence(args)
+    if args.atomic_steps > 0:
+        line["atomic_adjoint"] = atomic_convergence(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(args)

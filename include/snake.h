@@ -220,8 +220,9 @@ int snake_tile_partition(const uint8_t *tile_id, const float *pos, const int32_t
  * [ceil(n_cells/32)] uint32 are set to density > thr, where thr = threshold,
  * or with SNAKE_OCC_MEAN_CAP in flags thr = min(threshold, mean of the new
  * density over the n_cells cells), so that while the whole field is thin the
- * denser half of it stays occupied.  The mean is summed in FP64 in a fixed
- * order (the same bits on every call).  decay in [0, 1], sigma_scale > 0.
+ * denser half of it stays occupied.  The mean is summed in a fixed order in
+ * compensated FP32 (value plus rounding error, about 2^-44 relative; the same
+ * bits on every call).  decay in [0, 1], sigma_scale > 0.
  * Workspace: snake_occupancy_workspace_bytes(n_cells), 8-byte aligned.
  * snake_cull_samples keeps, ray by ray and in order, the packed samples
  * whose cell is occupied (a tile id >= K is dropped with
@@ -403,8 +404,8 @@ int snake_mlp_bwd(const snake_mlp_desc *m, int32_t K, const float *weights,
  * depth = sum w_i (t0_i + t1_i)/2; background 0.  early_stop_T > 0 keeps only
  * the samples with T_i >= early_stop_T (a prefix); n_alive [R] (may be NULL)
  * receives the kept count.  With target [R][3] given, *loss (device float)
- * += loss_scale * sum_r sum_ch (rgb_out - target)^2.  opacity, depth, loss may
- * be NULL.
+ * += loss_scale * sum_r sum_ch (rgb_out - target)^2, summed in a fixed order
+ * (the same bits on every run).  opacity, depth, loss may be NULL.
  */
 int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, const float *t1,
                         const int32_t *packed_info, int32_t R, const int32_t *sample_map,
@@ -440,7 +441,8 @@ int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, c
 /* g' = g + l2 p; m = b1 m + (1-b1) g'; v = b2 v + (1-b2) g'^2;
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), step >= 1.
  * p, g, m, v [n] float, 16-byte aligned.  The bias corrections are
- * fl32(1 - b^step) with b^step formed by binary powering in FP64.
+ * 1 - b^step with b^step formed by binary powering in FP32 (the same bits
+ * whether the step comes from the host or from step_dev).
  * step_dev: NULL, or a device int32 holding the step (then `step` is
  * ignored), so that a captured HIP graph replays with the current step;
  * snake_counter_add advances it inside the same graph. */

@@ -13,11 +13,11 @@ struct AdamArgs {
     const int32_t *step_dev;             // step read on the device when set
 };
 
-// b^k by binary powering in FP64: the same multiplications, in the same
+// b^k by binary powering in FP32: the same multiplications, in the same
 // order, on the host and on the device, so both give the same bits.
-__host__ __device__ inline double pow_int(double b, int k)
+__host__ __device__ inline float pow_int(float b, int k)
 {
-    double r = 1.0;
+    float r = 1.0f;
     while (k > 0) {
         if (k & 1) r *= b;
         b *= b;
@@ -28,8 +28,8 @@ __host__ __device__ inline double pow_int(double b, int k)
 
 __host__ __device__ inline void bias_corrections(AdamArgs &a, int step)
 {
-    a.c1 = (float)(1.0 - pow_int((double)a.b1, step));
-    a.c2 = (float)(1.0 - pow_int((double)a.b2, step));
+    a.c1 = 1.0f - pow_int(a.b1, step);
+    a.c2 = 1.0f - pow_int(a.b2, step);
 }
 
 __device__ __forceinline__ void adam1(float &p, float &g, float &m, float &v, const AdamArgs &a)

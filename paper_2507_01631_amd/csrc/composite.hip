@@ -69,13 +69,10 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(
     const float *__restrict__ sigma, const float *__restrict__ rgb, const float *__restrict__ t0,
     const float *__restrict__ t1, const int32_t *__restrict__ info, int R, const int32_t *__restrict__ map,
     float thr,
-    const float *__restrict__ target, float loss_scale, float *__restrict__ rgb_out,
-    float *__restrict__ opacity, float *__restrict__ depth, int32_t *__restrict__ n_alive,
-    float *__restrict__ loss)
+    float *__restrict__ rgb_out, float *__restrict__ opacity, float *__restrict__ depth,
+    int32_t *__restrict__ n_alive)
 {
-    __shared__ float red[kWaves];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    float loss_acc = 0.0f;
     for (int r = blockIdx.x * kWaves + wv; r < R; r += gridDim.x * kWaves) {
         const int64_t start = info[2 * (int64_t)r];
         const int count = info[2 * (int64_t)r + 1];
@@ -110,21 +107,37 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(
             if (opacity) opacity[r] = acc;
             if (depth) depth[r] = dep;
             if (n_alive) n_alive[r] = kept;
-            if (target) {
-                const float e0 = C0 - target[3 * (int64_t)r], e1 = C1 - target[3 * (int64_t)r + 1],
-                            e2 = C2 - target[3 * (int64_t)r + 2];
-                loss_acc += e0 * e0 + e1 * e1 + e2 * e2;
-            }
         }
     }
-    if (target && loss) {
-        if (lane == 0) red[wv] = loss_acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float s = 0.f;
-            for (int i = 0; i < kWaves; ++i) s += red[i];
-            atomicAdd(loss, loss_scale * s);
-        }
+}
+
+// *loss += loss_scale * sum_r sum_ch (rgb_out - target)^2, by one block in a
+// fixed order (each thread a compensated sum over a fixed stride of rays,
+// then a fixed tree), so the loss has the same bits on every run.
+constexpr int kLossThreads = 1024;
+
+__global__ __launch_bounds__(kLossThreads) void loss_kernel(const float *__restrict__ rgb_out,
+                                                            const float *__restrict__ target, int R, float loss_scale,
+                                                            float *__restrict__ loss)
+{
+    __shared__ float red[kLossThreads / 64];
+    float s = 0.0f, comp = 0.0f;                 // Kahan sum of this thread's rays
+    for (int r = threadIdx.x; r < R; r += kLossThreads) {
+        const float e0 = rgb_out[3 * (int64_t)r] - target[3 * (int64_t)r];
+        const float e1 = rgb_out[3 * (int64_t)r + 1] - target[3 * (int64_t)r + 1];
+        const float e2 = rgb_out[3 * (int64_t)r + 2] - target[3 * (int64_t)r + 2];
+        const float y = (e0 * e0 + e1 * e1 + e2 * e2) - comp;
+        const float t = s + y;
+        comp = (t - s) - y;
+        s = t;
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float tot = 0.0f;
+        for (int i = 0; i < kLossThreads / 64; ++i) tot += red[i];
+        *loss += loss_scale * tot;
     }
 }
 
@@ -222,8 +235,8 @@ int snake_composite_fwd(const float *sigma, const float *rgb, const float *t0, c
     SNAKE_NOT_NULL(rgb_out);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     composite_fwd_kernel<<<grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_COMPOSITE_BLOCKS_PER_CU)), 256, 0, st>>>(
-        sigma, rgb, t0, t1, packed_info, R, sample_map, early_stop_T, target, loss_scale, rgb_out, opacity, depth,
-        n_alive, loss);
+        sigma, rgb, t0, t1, packed_info, R, sample_map, early_stop_T, rgb_out, opacity, depth, n_alive);
+    if (target && loss) loss_kernel<<<1, kLossThreads, 0, st>>>(rgb_out, target, R, loss_scale, loss);
     return launch_status(__func__);
 }
 

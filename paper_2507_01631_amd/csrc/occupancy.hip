@@ -41,46 +41,79 @@ __global__ __launch_bounds__(256) void cells_kernel(int G, int K, float *__restr
     }
 }
 
+// Compensated FP32 sums ("float-float": a value and its rounding error),
+// about 2^-44 relative over the grid without FP64 arithmetic.
+struct FF {
+    float hi, lo;
+};
+
+__device__ __forceinline__ FF ff_two_sum(float a, float b)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    return FF{s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ FF ff_add(FF x, FF y)
+{
+    const FF s = ff_two_sum(x.hi, y.hi);
+    const float lo = s.lo + (x.lo + y.lo);
+    const float hi = s.hi + lo;                  // renormalise: |lo| is far below |s.hi|
+    return FF{hi, lo - (hi - s.hi)};
+}
+
+__device__ __forceinline__ FF ff_wave_sum(FF v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const FF u{__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)};
+        v = ff_add(v, u);
+    }
+    return v;
+}
+
 // Occupancy update, first half: density = max(decay density, scale sigma)
-// for every cell, and each block's FP64 sum of the new densities (for the
-// mean cap).  The grid is a function of n alone and every block sums its
+// for every cell, and each block's compensated sum of the new densities (for
+// the mean cap).  The grid is a function of n alone and every block sums its
 // cells in a fixed order, so the partial sums are reproducible.
 __global__ __launch_bounds__(256) void occ_decay_kernel(const float *__restrict__ sigma, int64_t n, float decay,
                                                         float scale, float *__restrict__ density,
-                                                        double *__restrict__ partial)
+                                                        float2 *__restrict__ partial)
 {
-    __shared__ double red[4];
-    double acc = 0.0;
+    __shared__ FF red[4];
+    FF acc{0.0f, 0.0f};
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const float d = fmaxf(density[c] * decay, scale * sigma[c]);
         density[c] = d;
-        acc += (double)d;
+        acc = ff_add(acc, FF{d, 0.0f});
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    acc = ff_wave_sum(acc);
     if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        const FF s = ff_add(ff_add(red[0], red[1]), ff_add(red[2], red[3]));
+        partial[blockIdx.x] = make_float2(s.hi, s.lo);
+    }
 }
 
 // Second half: bit = density > thr, with thr = min(threshold, mean density)
 // under the mean cap (every block adds the partial sums in the same order).
 // One wavefront writes the two 32-bit words of its 64 cells.
 __global__ __launch_bounds__(256) void occ_bits_kernel(const float *__restrict__ density, int64_t n, float threshold,
-                                                       int mean_cap, const double *__restrict__ partial, int nparts,
+                                                       int mean_cap, const float2 *__restrict__ partial, int nparts,
                                                        uint32_t *__restrict__ bits)
 {
-    __shared__ double red[4];
+    __shared__ FF red[4];
     __shared__ float thr_s;
     if (mean_cap) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[i];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        FF acc{0.0f, 0.0f};
+        for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc = ff_add(acc, FF{partial[i].x, partial[i].y});
+        acc = ff_wave_sum(acc);
         if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
-            const float mean = (float)(((red[0] + red[1]) + (red[2] + red[3])) / (double)n);
+            const FF s = ff_add(ff_add(red[0], red[1]), ff_add(red[2], red[3]));
+            const float mean = (s.hi + s.lo) / (float)n;
             thr_s = fminf(threshold, mean);
         }
     } else if (threadIdx.x == 0) {
@@ -202,7 +235,7 @@ int snake_occupancy_cells(int32_t G, int32_t K, float *pos, uint8_t *tile_id, sn
 
 size_t snake_occupancy_workspace_bytes(int64_t n_cells)
 {
-    return n_cells < 0 ? 0 : (size_t)occ_blocks(n_cells) * sizeof(double);
+    return n_cells < 0 ? 0 : (size_t)occ_blocks(n_cells) * sizeof(float2);
 }
 
 int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, float sigma_scale, float threshold,
@@ -224,7 +257,7 @@ int snake_occupancy_update(const float *sigma, int64_t n_cells, float decay, flo
     SNAKE_ALIGNED(workspace, 8);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const unsigned nb = occ_blocks(n_cells);
-    double *partial = static_cast<double *>(workspace);
+    float2 *partial = static_cast<float2 *>(workspace);
     occ_decay_kernel<<<nb, 256, 0, st>>>(sigma, n_cells, decay, sigma_scale, density, partial);
     occ_bits_kernel<<<grid_for(n_cells, 256, 8), 256, 0, st>>>(density, n_cells, threshold,
                                                                (flags & SNAKE_OCC_MEAN_CAP) ? 1 : 0, partial,

@@ -58,8 +58,8 @@ class SnakeSweep:
     FIELDS_W = ("params", "m_w", "v_w")
 
     def __init__(self, nx, ny, *, res, n_features, log2_table, n_dir, colour_layers, colour_out,
-                 precision="bf16", band=(0.0, 1.0), max_rays=1 << 16, samples=128, early_stop=0.0,
-                 lr=1e-2, seed=0, device="cuda"):
+                 init_tile, precision="bf16", band=(0.0, 1.0), max_rays=1 << 16, samples=128,
+                 early_stop=0.0, lr=1e-2, device="cuda"):
         assert nx >= 2 and ny >= 2
         self.nx, self.ny = int(nx), int(ny)
         dev = torch.device(device)
@@ -75,9 +75,10 @@ class SnakeSweep:
         self.per_w = w.P
         n = self.nx * self.ny
         # host store: one pinned buffer per tile and field (many moderate
-        # pinned allocations rather than a few of several GB each); tables
-        # U(-1e-4, 1e-4) and network weights from the seed
-        rng = np.random.default_rng(seed)
+        # pinned allocations rather than a few of several GB each); every
+        # tile's table and network weights come from init_tile(t) ->
+        # (table [L*T*F] float32, weights [P] float32), its Adam state from zero
+        n = self.nx * self.ny
         self.h = {}
         for f in self.FIELDS_T:
             self.h[f] = [torch.zeros(self.per_t, dtype=torch.float32).pin_memory() for _ in range(n)]
@@ -85,14 +86,14 @@ class SnakeSweep:
             self.h[f] = [torch.zeros(self.per_w, dtype=torch.float32).pin_memory() for _ in range(n)]
         self.h["step"] = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(n)]
         for t in range(n):
-            self.h["table"][t].copy_(torch.from_numpy(rng.uniform(-1e-4, 1e-4, size=self.per_t).astype(np.float32)))
-        from synth import MlpConfig, init_mlp      # weight init recipe (seeded)
-        m = MlpConfig(feat_real=min(32, w.Lv * w.F), n_dir=n_dir, colour_layers=colour_layers,
-                      colour_out=colour_out)
-        for t in range(n):
-            w0 = init_mlp(rng, m)
-            assert w0.shape[0] == self.per_w
-            self.h["params"][t].copy_(torch.from_numpy(np.ascontiguousarray(w0, dtype=np.float32)))
+            tab, par = init_tile(t)
+            tab = np.ascontiguousarray(tab, dtype=np.float32).reshape(-1)
+            par = np.ascontiguousarray(par, dtype=np.float32).reshape(-1)
+            if tab.size != self.per_t or par.size != self.per_w:
+                raise ValueError("init_tile(%d) gave %d table and %d weight values, expected %d and %d"
+                                 % (t, tab.size, par.size, self.per_t, self.per_w))
+            self.h["table"][t].copy_(torch.from_numpy(tab))
+            self.h["params"][t].copy_(torch.from_numpy(par))
         # device staging: two slots in, two out
         mk = lambda k: torch.empty((2, k), dtype=torch.float32, device=dev)   # noqa: E731
         self.st_in = {f: mk(self.per_t) for f in self.FIELDS_T}

@@ -356,6 +356,16 @@ def window_rays(seed: int, n_rays: int, max_off_nadir_deg: float = 10.0, margin:
     return o, d, target, spr
 
 
+def tile_init(seed: int, n_levels: int, n_features: int, log2_table: int, m: MlpConfig):
+    """init_tile(t) for a sweep over many NeRF tiles: tile t's table U(-1e-4,
+    1e-4) (flattened [L][T][F]) and Xavier weights, from the seed and t."""
+    def init(t):
+        rng = np.random.default_rng([seed, t])
+        table = rng.uniform(-1e-4, 1e-4, size=n_levels * (1 << log2_table) * n_features).astype(np.float32)
+        return table, init_mlp(rng, m)
+    return init
+
+
 def full_tile_heldout(wl: Workload, n_px: int = 256):
     """Rays and rendered targets of the held-out ninth view of a full_tile
     workload on an n_px x n_px pixel grid over the tile (pixel centres), with
