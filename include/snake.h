@@ -158,6 +158,28 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
                            void *workspace, size_t workspace_bytes, snake_stream_t stream);
 
 /*
+ * No-allocation variant of snake_sample_segmented, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and results, without the
+ * workspace: the count/scan scratch is a static device array of the library
+ * sized for R <= snake_sample_segmented_static_max_rays() (2^20 rays, about
+ * 8 MiB, held by every device the library runs on until the process ends).
+ * A larger R returns SNAKE_ERR_INVALID_ARG before any launch.  The call
+ * allocates nothing.  All calls on one device share that device's scratch,
+ * so calls that overlap on one device (two streams, two host threads) race:
+ * the caller serialises them.  Every call writes all the scratch it reads,
+ * so nothing carries over from the previous call.
+ */
+int32_t snake_sample_segmented_static_max_rays(void);
+int snake_sample_segmented_static(const double *rays_o, const double *rays_d, int32_t R,
+                                  const double *boxes, int32_t K, const double *zband,
+                                  const int32_t *samples_per_ray, int32_t S,
+                                  const int32_t *max_count,
+                                  int32_t *packed_info, float *t0, float *t1, float *pos,
+                                  int32_t *ray_id, uint8_t *tile_id, float *view,
+                                  int64_t cap, int64_t *n_out, snake_stream_t stream);
+
+/*
  * Index list of the samples kept by early stop: for each ray r, the first
  * n_alive[r] of its packed samples, in order.  idx_out [cap] int32 receives
  * their packed indices and *n_out (device int64) their total.  Workspace:

@@ -9,6 +9,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "scan.h"
 
@@ -323,49 +325,38 @@ extern "C" {
 
 size_t snake_sample_workspace_bytes(int32_t R) { return scan_ws_bytes(R); }
 
-int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R, const double *boxes,
-                           int32_t K, const double *zband, const int32_t *samples_per_ray, int32_t S,
-                           const int32_t *max_count, int32_t *packed_info, float *t0, float *t1,
-                           float *pos, int32_t *ray_id, uint8_t *tile_id, float *view, int64_t cap,
-                           int64_t *n_out, void *workspace, size_t workspace_bytes,
-                           snake_stream_t stream)
+// The sampler on a given count/scan workspace; fn names the entry point in
+// error messages.
+static int sample_impl(const char *fn, const double *rays_o, const double *rays_d, int32_t R, const double *boxes,
+                       int32_t K, const double *zband, const int32_t *samples_per_ray, int32_t S,
+                       const int32_t *max_count, int32_t *packed_info, float *t0, float *t1, float *pos,
+                       int32_t *ray_id, uint8_t *tile_id, float *view, int64_t cap, int64_t *n_out,
+                       void *workspace, size_t workspace_bytes, snake_stream_t stream)
 {
-    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "snake_sample_segmented: R = %d < 0", R);
-    SNAKE_REQUIRE(K >= 1 && K <= kMaxTiles, SNAKE_ERR_INVALID_ARG,
-                  "snake_sample_segmented: K = %d not in [1, %d]", K, kMaxTiles);
-    SNAKE_REQUIRE(K == 1 || tile_id != nullptr, SNAKE_ERR_NULL,
-                  "snake_sample_segmented: tile_id is NULL with K = %d > 1", K);
-    SNAKE_REQUIRE(samples_per_ray != nullptr || S >= 0, SNAKE_ERR_INVALID_ARG,
-                  "snake_sample_segmented: S = %d < 0", S);
-    SNAKE_REQUIRE(cap >= 0 && cap <= INT32_MAX, SNAKE_ERR_INVALID_ARG,
-                  "snake_sample_segmented: cap = %lld not in [0, 2^31)", (long long)cap);
-    SNAKE_NOT_NULL(boxes);
-    SNAKE_NOT_NULL(n_out);
-    if (R > 0) {
-        SNAKE_NOT_NULL(rays_o);
-        SNAKE_NOT_NULL(rays_d);
-        SNAKE_NOT_NULL(packed_info);
-    }
-    if (cap > 0) {
-        SNAKE_NOT_NULL(t0);
-        SNAKE_NOT_NULL(t1);
-        SNAKE_NOT_NULL(pos);
-        SNAKE_NOT_NULL(ray_id);
-    }
+    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "%s: R = %d < 0", fn, R);
+    SNAKE_REQUIRE(K >= 1 && K <= kMaxTiles, SNAKE_ERR_INVALID_ARG, "%s: K = %d not in [1, %d]", fn, K, kMaxTiles);
+    SNAKE_REQUIRE(K == 1 || tile_id != nullptr, SNAKE_ERR_NULL, "%s: tile_id is NULL with K = %d > 1", fn, K);
+    SNAKE_REQUIRE(samples_per_ray != nullptr || S >= 0, SNAKE_ERR_INVALID_ARG, "%s: S = %d < 0", fn, S);
+    SNAKE_REQUIRE(cap >= 0 && cap <= INT32_MAX, SNAKE_ERR_INVALID_ARG, "%s: cap = %lld not in [0, 2^31)", fn,
+                  (long long)cap);
+    SNAKE_REQUIRE(boxes != nullptr && n_out != nullptr, SNAKE_ERR_NULL, "%s: boxes or n_out is NULL", fn);
+    SNAKE_REQUIRE(R == 0 || (rays_o && rays_d && packed_info), SNAKE_ERR_NULL,
+                  "%s: rays_o, rays_d or packed_info is NULL", fn);
+    SNAKE_REQUIRE(cap == 0 || (t0 && t1 && pos && ray_id), SNAKE_ERR_NULL, "%s: t0, t1, pos or ray_id is NULL", fn);
     SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= scan_ws_bytes(R), SNAKE_ERR_WORKSPACE,
-                  "snake_sample_segmented: workspace needs %zu bytes", scan_ws_bytes(R));
-    SNAKE_ALIGNED(workspace, 256);
+                  "%s: workspace needs %zu bytes", fn, scan_ws_bytes(R));
+    SNAKE_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % 256 == 0, SNAKE_ERR_ALIGN,
+                  "%s: workspace is not 256-byte aligned", fn);
     Boxes bx{};
     bx.K = K;
     for (int k = 0; k < K; ++k) {
         for (int a = 0; a < 6; ++a) bx.b[k][a] = boxes[6 * k + a];
         for (int a = 0; a < 3; ++a)
-            SNAKE_REQUIRE(bx.b[k][3 + a] > bx.b[k][a], SNAKE_ERR_INVALID_ARG,
-                          "snake_sample_segmented: box %d is empty on axis %d", k, a);
+            SNAKE_REQUIRE(bx.b[k][3 + a] > bx.b[k][a], SNAKE_ERR_INVALID_ARG, "%s: box %d is empty on axis %d", fn,
+                          k, a);
     }
     if (zband) {
-        SNAKE_REQUIRE(zband[1] > zband[0], SNAKE_ERR_INVALID_ARG,
-                      "snake_sample_segmented: empty altitude band");
+        SNAKE_REQUIRE(zband[1] > zband[0], SNAKE_ERR_INVALID_ARG, "%s: empty altitude band", fn);
         bx.use_band = 1;
         bx.z_lo = zband[0];
         bx.z_hi = zband[1];
@@ -373,7 +364,7 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (R == 0) {
         set_i64_kernel<<<1, 1, 0, st>>>(n_out, 0);
-        return launch_status(__func__);
+        return launch_status(fn);
     }
     ScanWs w = carve(workspace, R);
     const unsigned gc = grid_for(R, 256, 8), gf = grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU));
@@ -391,7 +382,70 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
         SNAKE_SAMPLER_LAUNCH(kMaxTiles);
     }
 #undef SNAKE_SAMPLER_LAUNCH
-    return launch_status(__func__);
+    return launch_status(fn);
+}
+
+// The no-allocation variant's scratch: the count/scan workspace for up to
+// kStaticRays rays in one file-scope device array (each device holds its own
+// copy until the process ends).  Host code never uses the array's name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr int32_t kStaticRays = 1 << 20;
+constexpr size_t kStaticScratchBytes =
+    2 * (((size_t)kStaticRays * 4 + 255) / 256 * 256) + ((size_t)kStaticRays / scan::kScanTile + 1) * 8 + 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static constexpr int kScratchDevices = 64;
+static void *g_scratch[kScratchDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch (the current device), resolved on
+// the first call on that device; nullptr (with the error message set) on failure.
+static void *scratch_address(const char *fn)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+        set_error("%s: no usable current device", fn);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("%s: hipGetSymbolAddress of the static scratch failed: %s", fn, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+
+int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R, const double *boxes,
+                           int32_t K, const double *zband, const int32_t *samples_per_ray, int32_t S,
+                           const int32_t *max_count, int32_t *packed_info, float *t0, float *t1,
+                           float *pos, int32_t *ray_id, uint8_t *tile_id, float *view, int64_t cap,
+                           int64_t *n_out, void *workspace, size_t workspace_bytes,
+                           snake_stream_t stream)
+{
+    return sample_impl(__func__, rays_o, rays_d, R, boxes, K, zband, samples_per_ray, S, max_count, packed_info, t0,
+                       t1, pos, ray_id, tile_id, view, cap, n_out, workspace, workspace_bytes, stream);
+}
+
+int32_t snake_sample_segmented_static_max_rays(void) { return kStaticRays; }
+
+int snake_sample_segmented_static(const double *rays_o, const double *rays_d, int32_t R, const double *boxes,
+                                  int32_t K, const double *zband, const int32_t *samples_per_ray, int32_t S,
+                                  const int32_t *max_count, int32_t *packed_info, float *t0, float *t1,
+                                  float *pos, int32_t *ray_id, uint8_t *tile_id, float *view, int64_t cap,
+                                  int64_t *n_out, snake_stream_t stream)
+{
+    SNAKE_REQUIRE(R <= kStaticRays, SNAKE_ERR_INVALID_ARG,
+                  "snake_sample_segmented_static: R = %d exceeds the static scratch limit of %d rays", R,
+                  kStaticRays);
+    void *ws = scratch_address(__func__);
+    if (!ws) return SNAKE_ERR_HIP;
+    return sample_impl(__func__, rays_o, rays_d, R, boxes, K, zband, samples_per_ray, S, max_count, packed_info, t0,
+                       t1, pos, ray_id, tile_id, view, cap, n_out, ws, kStaticScratchBytes, stream);
 }
 
 int snake_pack_alive(const int32_t *packed_info, const int32_t *n_alive, int32_t R, int32_t *idx_out,
