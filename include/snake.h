@@ -296,7 +296,8 @@ typedef struct {
  * g->flags its bfloat16 mirror of the same layout (the FP32 table rounded by
  * snake_convert_bf16; the blend stays FP32), 16-byte aligned; pos [.][3]
  * float, tile_id (NULL = tile 0 for all; an id >= K gives zero features and
- * SNAKE_DEVERR_TILE_ID), feat [L][n][F] written.  idx_dbg (NULL or
+ * SNAKE_DEVERR_TILE_ID), feat [L][n][F] written (with F == 2 aligned to one
+ * row, 4 bytes for bf16, 8 for float; else SNAKE_ERR_ALIGN).  idx_dbg (NULL or
  * [n][L][8] uint32) receives the corner slots.  The adjoint ignores the flag
  * (its dtable is always FP32).
  */

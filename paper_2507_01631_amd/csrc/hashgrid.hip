@@ -208,12 +208,22 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[q] = Entry<F, TabT>::one(lev, idx[q]);
         }
+        float acc[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            float acc = 0.0f;
+            acc[f] = 0.0f;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc = fmaf(wt[q], Vec<F>::get(v[q], f), acc);
-            store_feat(feat + ((int64_t)l * n + s) * F + f, acc);
+            for (int q = 0; q < 8; ++q) acc[f] = fmaf(wt[q], Vec<F>::get(v[q], f), acc[f]);
+        }
+        if constexpr (F == 2 && std::is_same<OutT, __hip_bfloat16>::value) {
+            // both features of the sample-level in one 4-byte store
+            const __hip_bfloat16 h0 = __float2bfloat16(acc[0]), h1 = __float2bfloat16(acc[1]);
+            const uint32_t packed = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                                    ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            *reinterpret_cast<uint32_t *>(feat + ((int64_t)l * n + s) * F) = packed;
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) store_feat(feat + ((int64_t)l * n + s) * F + f, acc[f]);
         }
         if (idx_dbg) {
 #pragma unroll
@@ -1111,6 +1121,7 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const void *table, 
     const unsigned grid = grid_for(n * g.L, 256, tune(SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU));
     const bool bf = gd->feat_dtype == SNAKE_BF16;
     const bool tb = (gd->flags & SNAKE_GRID_TABLE_BF16) != 0;
+    if (F == 2) SNAKE_ALIGNED(feat, bf ? 4 : 8);    // one store per sample-level
     const float *tf = static_cast<const float *>(table);
     const __hip_bfloat16 *th = static_cast<const __hip_bfloat16 *>(table);
     __hip_bfloat16 *fh = static_cast<__hip_bfloat16 *>(feat);

@@ -284,6 +284,78 @@ __device__ __forceinline__ void load_features(const FT *feat, int64_t ld, int64_
         }
 }
 
+// Raw feature words of one lane for the pipelined forward (F == 2): the
+// loads issue back to back and nothing reads their results until the unit is
+// computed, so they stay in flight meanwhile.  Every lane loads from a valid
+// address (row 0 of the first sample when its own rows are not wanted).
+template <typename FT>
+struct RawFeat;
+template <>
+struct RawFeat<__hip_bfloat16> {
+    uint32_t w[2][2];
+    __device__ void load(const __hip_bfloat16 *p, int t, int h) { w[t][h] = *reinterpret_cast<const uint32_t *>(p); }
+    __device__ float2 get(int t, int h) const
+    {
+        return make_float2(__uint_as_float(w[t][h] << 16), __uint_as_float(w[t][h] & 0xffff0000u));
+    }
+};
+template <>
+struct RawFeat<float> {
+    float2 w[2][2];
+    __device__ void load(const float *p, int t, int h) { w[t][h] = *reinterpret_cast<const float2 *>(p); }
+    __device__ float2 get(int t, int h) const { return w[t][h]; }
+};
+
+template <typename FT>
+__device__ __forceinline__ void issue_features(const FT *feat, int64_t ld, int64_t s, bool valid, const MlpArgs &a,
+                                               RawFeat<FT> &raw, uint32_t &use)
+{
+    const int q = lane_id() >> 4;
+    use = 0u;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int lvl = 8 * t + 2 * q + h;           // rows 2 lvl, 2 lvl + 1: the level's two features
+            const bool u = valid && 2 * lvl < a.n_feat;
+            raw.load(feat + (u ? (int64_t)lvl * ld + s : 0) * 2, t, h);
+            use |= (u ? 1u : 0u) << (2 * t + h);
+        }
+}
+
+template <typename FT>
+__device__ __forceinline__ void take_features(const RawFeat<FT> &raw, uint32_t use, bool ok, float (&x)[2][4])
+{
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool u = ok && ((use >> (2 * t + h)) & 1u);
+            const float2 v = raw.get(t, h);
+            x[t][2 * h] = u ? v.x : 0.0f;
+            x[t][2 * h + 1] = u ? v.y : 0.0f;
+        }
+}
+
+// Colour-input directions of one lane (rows 16..31: view xyz, sun xyz, then
+// zeros), loaded from valid addresses without branches; mask bit r says
+// whether row 4q + r is a direction.
+__device__ __forceinline__ void issue_dirs(const float *view, const float *sun, int64_t ray, const MlpArgs &a,
+                                           float (&c)[4], uint32_t &mask)
+{
+    const int q = lane_id() >> 4;
+    mask = 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 4 * q + r;
+        const bool from_view = k < 3, from_sun = k >= 3 && k < a.n_dir && sun != nullptr;
+        const uintptr_t pv = reinterpret_cast<uintptr_t>(view + (from_view ? 3 * ray + k : 0));
+        const uintptr_t ps = reinterpret_cast<uintptr_t>(sun + (from_sun ? 3 * ray + (k - 3) : 0));
+        c[r] = *reinterpret_cast<const float *>(from_sun ? ps : pv);
+        mask |= (from_view || from_sun ? 1u : 0u) << r;
+    }
+}
+
 // Colour input rows 16..31: view xyz, sun xyz (n_dir == 6), then zeros.
 __device__ __forceinline__ void load_dirs(const float *view, const float *sun, int64_t ray, bool valid,
                                           const MlpArgs &a, float (&c)[4])
@@ -495,6 +567,130 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_kernel(MlpArgs a, const float 
                 for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]) * vis;
             }
         }
+    }
+}
+
+template <int PREC, int CL, typename FT, bool STORE>
+__global__ __launch_bounds__(kBlock) void mlp_fwd_pipe_kernel(MlpArgs a, const float *__restrict__ w,
+                                                         const FT *__restrict__ feat,
+                                                         const float *__restrict__ view,
+                                                         const float *__restrict__ sun,
+                                                         const int32_t *__restrict__ ray_id, int64_t n,
+                                                         const int64_t *__restrict__ n_dev,
+                                                         float *__restrict__ sigma, float *__restrict__ rgb,
+                                                         float *__restrict__ act)
+{
+    typedef Layout<PREC, CL> Lt;
+    __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::FWD];
+    __shared__ UnitTable U;
+    const int64_t ne = effective_n(n, n_dev);
+    setup_units(U, a, ne);
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+    const int64_t total = U.ub[a.K + 1];
+    // Software pipeline (F == 2, no index list).  Unit u's ray ids and
+    // features are loaded one unit ahead, at the start of the previous unit
+    // of this block; its directions (which need the ray ids) at the end of
+    // that unit.  Loads issue back to back and no result is read before the
+    // layer that needs it, so they stay in flight while a unit is computed.
+    struct In {
+        int64_t s;
+        int k;
+        bool valid;
+        uint32_t use, dmask;
+        int32_t ray;
+        RawFeat<FT> raw;
+        float dirs[4];
+    };
+    auto issue = [&](int64_t u, In &in) {
+        int64_t s0, s1;
+        locate(U, a.K, u, in.k, s0, s1);
+        in.s = s0 + 16 * wv + i;
+        in.valid = in.s < s1;
+        in.ray = ray_id[in.valid ? in.s : s0];               // a sample that exists
+        issue_features<FT>(feat, n, in.s, in.valid, a, in.raw, in.use);
+    };
+    auto issue_dirs_of = [&](In &in) {
+        const bool ok = in.valid && in.k < a.K && in.ray >= 0 && in.ray < a.R;
+        issue_dirs(view, sun, ok ? in.ray : 0, a, in.dirs, in.dmask);
+    };
+    int cur = -1;
+    // one unit: compute `in`, loading unit u + grid into `nx` meanwhile (two
+    // buffers used alternately, so no loaded value is copied before use)
+    auto step = [&](int64_t u, In &in, In &nx) {
+        const bool more = u + gridDim.x < total;
+        if (more) issue(u + gridDim.x, nx);
+        const int64_t s = in.s;
+        const bool valid = in.valid && in.k < a.K;
+        const bool ok = valid && in.ray >= 0 && in.ray < a.R;   // a bad ray id drops the sample
+        if (valid && !ok && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
+        if (in.k == a.K) {                                   // invalid tile id: dropped
+            if (q == 0 && in.valid) {
+                sigma[s] = 0.0f;
+                rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
+            }
+            if (more) issue_dirs_of(nx);
+            return;
+        }
+        if (in.k != cur) {                                   // block-uniform
+            __syncthreads();
+            const float *wd, *wc;
+            tile_weights(a, w, in.k, wd, wc);
+            build_forward<PREC, CL>(lds, wd, wc, a);
+            __syncthreads();
+            cur = in.k;
+        }
+        Acts<PREC, CL> A;
+        // keep the scheduler from reading loaded values before their layer
+        // (the wait for a load sits at its first use)
+        __builtin_amdgcn_sched_barrier(0);
+        take_features<FT>(in.raw, in.use, ok, A.x);
+        apply<PREC, 64, 32>(lds + Lt::D1, A.x, A.h1);
+        relu(A.h1);
+        apply<PREC, 16, 64>(lds + Lt::D2, A.h1, A.o);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            A.cin[0][r] = A.o[0][r];
+            A.cin[1][r] = ok && ((in.dmask >> r) & 1u) ? in.dirs[r] : 0.0f;
+        }
+        apply<PREC, 64, 32>(lds + Lt::C1, A.cin, A.g1);
+        relu(A.g1);
+        if constexpr (CL == 2) {
+            apply<PREC, 64, 64>(lds + Lt::C2, A.g1, A.g2);
+            relu(A.g2);
+            apply<PREC, 16, 64>(lds + Lt::CO, A.g2, A.out);
+        } else {
+            apply<PREC, 16, 64>(lds + Lt::CO, A.g1, A.out);
+        }
+        if constexpr (STORE) {
+            if (ok) store_acts<PREC, CL>(act + s * ActLayout<CL>::W, A);
+        }
+        if (q == 0 && valid && !ok) {
+            sigma[s] = 0.0f;
+            rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
+        } else if (q == 0 && valid) {
+            sigma[s] = expf(A.o[0][0]);
+            if (a.CO == 3) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]);
+            } else {
+                const float vis = sigmoidf(A.out[0][3]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]) * vis;
+            }
+        }
+        if (more) issue_dirs_of(nx);
+    };
+    In b0, b1;
+    int64_t u = blockIdx.x;
+    if (u < total) {
+        issue(u, b0);
+        issue_dirs_of(b0);
+    }
+    for (; u < total; u += 2 * (int64_t)gridDim.x) {
+        step(u, b0, b1);
+        if (u + gridDim.x >= total) break;
+        step(u + gridDim.x, b1, b0);
     }
 }
 
@@ -1197,6 +1393,15 @@ void launch_fwd(const MlpArgs &a, const float *w, const void *feat, const float 
                 float *rgb, float *act, hipStream_t st)
 {
     const unsigned grid = grid_for(((n + 63) / 64 + a.K) * kBlock, kBlock, tune(SNAKE_TUNE_MLP_FWD_BLOCKS_PER_CU));
+    if (a.F == 2 && sidx == nullptr) {
+        if (act)
+            mlp_fwd_pipe_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(
+                a, w, static_cast<const FT *>(feat), view, sun, ray_id, n, n_dev, sigma, rgb, act);
+        else
+            mlp_fwd_pipe_kernel<PREC, CL, FT, false><<<grid, kBlock, 0, st>>>(
+                a, w, static_cast<const FT *>(feat), view, sun, ray_id, n, n_dev, sigma, rgb, act);
+        return;
+    }
     if (act)
         mlp_fwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), view, sun,
                                                                     ray_id, sidx, n, n_dev, sigma, rgb, act);
