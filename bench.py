@@ -375,8 +375,12 @@ def sweep_bench(args):
         # the first window also pays for the graph capture and the initial load
         steady = t[1:] if len(t) > 1 else t
         cm = sw.copy_ms()
+        comp = sw.compute_ms()
+        comp_steady = comp[1:] if len(comp) > 1 else comp
         out["grids"].append({"tiles": n * n, "windows": npath, "total_s": round(sum(t), 4),
                              "ms_per_window_step": round(1e3 * float(np.mean(steady)) / steps, 4),
+                             "compute_ms_per_window_step": round(float(np.mean(comp_steady)) / steps, 4),
+                             "move_issue_ms": round(float(np.mean(sw.move_issue_ms()[1:] or [0.0])), 3),
                              "host_copy_ms_per_move": round(float(np.mean(cm)), 3) if cm else None,
                              "window_ms": [round(1e3 * x, 2) for x in t]})
         log("  sweep %dx%d: %s" % (n, n, json.dumps(out["grids"][-1])))

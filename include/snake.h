@@ -108,7 +108,12 @@ typedef enum {
     SNAKE_TUNE_BIN_LEVELS_PER_PASS = 5,     /* binned table adjoint: most levels per pass,
                                                0..32 (0: as many as the workspace holds) */
     SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU = 6,   /* sampler fill grid, 1..64 (16) */
-    SNAKE_TUNE_COUNT = 7
+    SNAKE_TUNE_HASH_FWD_SUPERCHUNK = 7,     /* hash-grid forward work order, 0..64 (0): 0 walks
+                                               level by level over all samples; v > 0 walks
+                                               super-chunks of v x 2^20 samples, every level of
+                                               one before the next (their positions then stay
+                                               in the on-package cache across levels) */
+    SNAKE_TUNE_COUNT = 8
 } snake_tunable;
 
 int snake_tune_set(int32_t which, int32_t value);
@@ -472,6 +477,15 @@ int snake_composite_bwd(const float *sigma, const float *rgb, const float *t0, c
 int snake_adam_step(float *p, float *g, float *m, float *v, int64_t n,
                     float lr, float b1, float b2, float eps, int32_t step,
                     const int32_t *step_dev, float l2, uint32_t flags, snake_stream_t stream);
+
+/* Adam over K NeRF tiles in one launch (the window step, whose tiles keep
+ * their own step counts, Sec. 4.4): p, g, m, v hold K consecutive blocks of
+ * tile_n floats (4-byte aligned), and block k takes its step from step_dev[k]
+ * (device int32; values below 1 count as 1).  Otherwise as snake_adam_step,
+ * with the same bits as K separate calls.  1 <= K <= 64. */
+int snake_adam_step_tiles(float *p, float *g, float *m, float *v, int64_t tile_n, int32_t K,
+                          float lr, float b1, float b2, float eps, const int32_t *step_dev, float l2,
+                          uint32_t flags, snake_stream_t stream);
 
 /* counter[i] += delta for i < n on the stream (device int32 [n]; per-tile
  * Adam step counters). */

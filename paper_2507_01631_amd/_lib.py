@@ -29,6 +29,7 @@ MAX_LEVELS = 32
 TUNABLES = {
     "hash_fwd_blocks_per_cu": 0, "mlp_fwd_blocks_per_cu": 1, "mlp_bwd_blocks_per_cu": 2,
     "composite_blocks_per_cu": 3, "bin_blocks": 4, "bin_levels_per_pass": 5, "sampler_blocks_per_cu": 6,
+    "hash_fwd_superchunk": 7,
 }
 
 EXPORTS = (
@@ -41,7 +42,7 @@ EXPORTS = (
     "snake_convert_bf16", "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_weight_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
-    "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step", "snake_counter_add",
+    "snake_composite_fwd", "snake_composite_bwd", "snake_adam_step", "snake_adam_step_tiles", "snake_counter_add",
 )
 
 
@@ -123,6 +124,7 @@ _SIGS = {
                             ctypes.c_int),
     "snake_composite_bwd": ([_P, _P, _P, _P, _P, _I32, _P, _P, _P, _F, _P, _P, _P], ctypes.c_int),
     "snake_adam_step": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P, _F, _U32, _P], ctypes.c_int),
+    "snake_adam_step_tiles": ([_P, _P, _P, _P, _I64, _I32, _F, _F, _F, _F, _P, _F, _U32, _P], ctypes.c_int),
     "snake_counter_add": ([_P, _I32, _I32, _P], ctypes.c_int),
 }
 
@@ -372,6 +374,12 @@ def snake_adam_step(p, g, m, v, n, lr, b1, b2, eps, step, l2=0.0, flags=0, step_
                                float(b2), float(eps), int(step), _ptr(step_dev), float(l2), int(flags),
                                _stream(stream))
     _check("snake_adam_step", rc)
+
+
+def snake_adam_step_tiles(p, g, m, v, tile_n, K, lr, b1, b2, eps, step_dev, l2=0.0, flags=0, stream=None):
+    rc = lib().snake_adam_step_tiles(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(tile_n), int(K), float(lr), float(b1),
+                                     float(b2), float(eps), _ptr(step_dev), float(l2), int(flags), _stream(stream))
+    _check("snake_adam_step_tiles", rc)
 
 
 def snake_counter_add(counter, delta, n=None, stream=None):

@@ -31,6 +31,7 @@ CANDIDATES = {
     "bin_blocks": [512, 1024, 2048],
     "bin_levels_per_pass": [0, 2, 4],
     "sampler_blocks_per_cu": [8, 16, 32],
+    "hash_fwd_superchunk": [0, 1, 2, 4],
 }
 
 

@@ -145,15 +145,22 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
                                                            const int32_t *__restrict__ sidx, int64_t n,
                                                            const int64_t *__restrict__ n_dev,
                                                            OutT *__restrict__ feat,
-                                                           uint32_t *__restrict__ idx_dbg)
+                                                           uint32_t *__restrict__ idx_dbg, int superchunk)
 {
     typedef typename Vec<F>::T VT;
     const int64_t ne = effective_n(n, n_dev);
     const int64_t chunks = (ne + 255) / 256;
     const int64_t units = chunks * g.L;
+    // super-chunks of sc chunks, every level of one before the next (sc =
+    // chunks: level by level over all samples)
+    const int64_t sc = superchunk > 0 && (int64_t)superchunk < chunks ? (int64_t)superchunk : chunks;
+    const int64_t per = sc * g.L;
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int l = (int)(u / chunks);
-        const int64_t s = (u - (int64_t)l * chunks) * 256 + threadIdx.x;
+        const int64_t b = u / per, r = u - b * per;
+        const int64_t c0 = b * sc;
+        const int64_t se = chunks - c0 < sc ? chunks - c0 : sc;      // chunks of this super-chunk
+        const int l = (int)(r / se);
+        const int64_t s = (c0 + (r - (int64_t)l * se)) * 256 + threadIdx.x;
         if (s >= ne) continue;
         const int64_t si = sidx ? sidx[s] : s;
         const float x[3] = {pos[3 * si], pos[3 * si + 1], pos[3 * si + 2]};
@@ -1119,6 +1126,7 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const void *table, 
     const int F = gd->n_features;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const unsigned grid = grid_for(n * g.L, 256, tune(SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU));
+    const int superchunk = tune(SNAKE_TUNE_HASH_FWD_SUPERCHUNK) * 4096;   // in 256-sample chunks
     const bool bf = gd->feat_dtype == SNAKE_BF16;
     const bool tb = (gd->flags & SNAKE_GRID_TABLE_BF16) != 0;
     if (F == 2) SNAKE_ALIGNED(feat, bf ? 4 : 8);    // one store per sample-level
@@ -1130,16 +1138,16 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const void *table, 
     if (tb && bf)                                                                                               \
         hashgrid_fwd_kernel<FF, __hip_bfloat16, __hip_bfloat16><<<grid, 256, 0, st>>>(g, th, pos, tile_id,      \
                                                                                     sample_idx, n, n_dev, fh,   \
-                                                                                    idx_dbg);                   \
+                                                                                    idx_dbg, superchunk);       \
     else if (tb)                                                                                                \
         hashgrid_fwd_kernel<FF, float, __hip_bfloat16><<<grid, 256, 0, st>>>(g, th, pos, tile_id, sample_idx, n, \
-                                                                           n_dev, ff, idx_dbg);                 \
+                                                                           n_dev, ff, idx_dbg, superchunk);     \
     else if (bf)                                                                                                \
         hashgrid_fwd_kernel<FF, __hip_bfloat16, float><<<grid, 256, 0, st>>>(g, tf, pos, tile_id, sample_idx, n, \
-                                                                           n_dev, fh, idx_dbg);                 \
+                                                                           n_dev, fh, idx_dbg, superchunk);     \
     else                                                                                                        \
         hashgrid_fwd_kernel<FF, float, float><<<grid, 256, 0, st>>>(g, tf, pos, tile_id, sample_idx, n, n_dev,  \
-                                                                  ff, idx_dbg)
+                                                                  ff, idx_dbg, superchunk)
     if (F == 1) {
         SNAKE_HG_FWD(1);
     } else if (F == 2) {

@@ -1241,6 +1241,179 @@ __global__ __launch_bounds__(kBlock, PREC == P_BF16 ? 2 : 1) void mlp_bwd_kernel
     }
 }
 
+// The adjoint for F == 2 with recomputed activations, software-pipelined
+// like the forward: the index list entry of unit u + 2 grid, the ray id,
+// features and output gradients of unit u + grid, and (after the current
+// unit) the directions of unit u + grid are in flight while unit u is
+// computed.  Loads go to valid addresses without branches, into two
+// alternating buffers, and nothing reads them before the layer that needs
+// them.  Results are those of mlp_bwd_kernel bit for bit.
+template <int PREC, int CL, typename FT>
+__global__ __launch_bounds__(kBlock, PREC == P_BF16 ? 2 : 1) void mlp_bwd_pipe_kernel(
+    MlpArgs a, const float *__restrict__ w, const FT *__restrict__ feat, int64_t feat_ld,
+    const float *__restrict__ view, const float *__restrict__ sun, const int32_t *__restrict__ ray_id,
+    const int32_t *__restrict__ sidx, int64_t n, const int64_t *__restrict__ n_dev,
+    const float *__restrict__ dsigma, const float *__restrict__ drgb, float *__restrict__ dfeat,
+    float *__restrict__ partial, const typename FragT<PREC>::T *__restrict__ frag)
+{
+    typedef Layout<PREC, CL> Lt;
+    typedef WGrad<PREC, CL, PREC == P_BF16> WG;
+    __shared__ __attribute__((aligned(16))) typename Lt::T lds[Lt::ALL];
+    __shared__ __attribute__((aligned(16))) unsigned char wg_lds[WG::kLdsBytes];
+    __shared__ UnitTable U;
+    const int64_t ne = effective_n(n, n_dev);
+    setup_units(U, a, ne);
+    const int lane = lane_id(), i = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+    WG wg(wg_lds);
+    const int lofs = 16 * wv + i;
+
+    struct D {
+        int64_t s;
+        bool in_range;
+        int32_t ray;
+        uint32_t use, dmask;
+        RawFeat<FT> raw;
+        float dsig, dr[3], dirs[4];
+    };
+    int64_t g0 = 0, g1 = 0, gbase = 0;   // group's first entry and end; entry of unit 0 in its numbering
+    auto si_of = [&](int uu) -> int64_t {
+        const int64_t s = gbase + 64 * (int64_t)uu + lofs;
+        const int64_t sc = s < g1 ? s : g0;                  // an entry that exists
+        return sidx ? (int64_t)sidx[sc] : sc;
+    };
+    auto issue_data = [&](int uu, int64_t si, D &d) {
+        d.s = gbase + 64 * (int64_t)uu + lofs;
+        d.in_range = d.s < g1;
+        d.ray = ray_id[si];
+        issue_features<FT>(feat, feat_ld, si, d.in_range, a, d.raw, d.use);
+        d.dsig = dsigma[si];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d.dr[c] = drgb[3 * si + c];
+    };
+    auto issue_dirs_of = [&](D &d) {
+        const bool ok = d.in_range && d.ray >= 0 && d.ray < a.R;
+        issue_dirs(view, sun, ok ? d.ray : 0, a, d.dirs, d.dmask);
+    };
+    auto compute = [&](const D &x) {
+        const bool valid = x.in_range && x.ray >= 0 && x.ray < a.R;   // a bad ray id drops the sample
+        if (x.in_range && !valid && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
+        Acts<PREC, CL> A;
+        __builtin_amdgcn_sched_barrier(0);
+        take_features<FT>(x.raw, x.use, valid, A.x);
+        apply<PREC, 64, 32>(lds + Lt::D1, A.x, A.h1);
+        relu(A.h1);
+        apply<PREC, 16, 64>(lds + Lt::D2, A.h1, A.o);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            A.cin[0][r] = A.o[0][r];
+            A.cin[1][r] = valid && ((x.dmask >> r) & 1u) ? x.dirs[r] : 0.0f;
+        }
+        apply<PREC, 64, 32>(lds + Lt::C1, A.cin, A.g1);
+        relu(A.g1);
+        if constexpr (CL == 2) {
+            apply<PREC, 64, 64>(lds + Lt::C2, A.g1, A.g2);
+            relu(A.g2);
+            apply<PREC, 16, 64>(lds + Lt::CO, A.g2, A.out);
+        } else {
+            apply<PREC, 16, 64>(lds + Lt::CO, A.g1, A.out);
+        }
+        // output activation adjoint (rows 0..3 live in lane group 0)
+        float dout[1][4] = {{0.f, 0.f, 0.f, 0.f}};
+        const bool lead = q == 0 && valid;
+        const float dsig = lead ? x.dsig : 0.0f;
+        if (lead) {
+            if (a.CO == 3) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float y = sigmoidf(A.out[0][c]);
+                    dout[0][c] = x.dr[c] * y * (1.0f - y);
+                }
+            } else {
+                const float vis = sigmoidf(A.out[0][3]);
+                float dvis = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float alb = sigmoidf(A.out[0][c]);
+                    dout[0][c] = x.dr[c] * vis * alb * (1.0f - alb);
+                    dvis += x.dr[c] * alb;
+                }
+                dout[0][3] = dvis * vis * (1.0f - vis);
+            }
+        }
+        float dg2[4][4], dg1[4][4], dob[1][4], dh1[4][4], dx[2][4];
+        if constexpr (CL == 2) {
+            apply<PREC, 64, 16>(lds + Lt::COT, dout, dg2);
+            relu_mask(dg2, A.g2);
+            wg.template layer<M_CO>(dout, A.g2);
+            apply<PREC, 64, 64>(lds + Lt::C2T, dg2, dg1);
+            relu_mask(dg1, A.g1);
+            wg.template layer<M_C2>(dg2, A.g1);
+        } else {
+            apply<PREC, 64, 16>(lds + Lt::COT, dout, dg1);
+            relu_mask(dg1, A.g1);
+            wg.template layer<M_CO>(dout, A.g1);
+        }
+        apply<PREC, 16, 64>(lds + Lt::C1T, dg1, dob);
+        if (q == 0) dob[0][0] = dsig * expf(A.o[0][0]);   // sigma = exp(o_0)
+        wg.template layer<M_C1>(dg1, A.cin);
+        apply<PREC, 64, 16>(lds + Lt::D2T, dob, dh1);
+        relu_mask(dh1, A.h1);
+        wg.template layer<M_D2>(dob, A.h1);
+        apply<PREC, 32, 64>(lds + Lt::D1T, dh1, dx);
+        store_dfeat<FT>(dfeat, n, x.s, x.in_range, a, dx);   // dropped samples store zeros
+        wg.template layer<M_D1>(dh1, A.x);
+    };
+
+    const int G = (int)gridDim.x;
+    for (int k = 0; k <= a.K; ++k) {                          // block-uniform
+        // this block's units of group k: u = blockIdx.x (mod G) in [ub[k], ub[k+1])
+        const int ua = (int)U.ub[k], ue = (int)U.ub[k + 1];
+        int u = ua + (((int)blockIdx.x - ua) % G + G) % G;
+        if (u >= ue) continue;
+        g0 = U.ts[k];
+        g1 = U.ts[k + 1];
+        gbase = U.ts[k] - 64 * (int64_t)ua;
+        if (k == a.K) {                                       // invalid tile id: dropped
+            const float zx[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            for (; u < ue; u += G) {
+                const int64_t s = gbase + 64 * (int64_t)u + lofs;
+                store_dfeat<FT>(dfeat, n, s, s < g1, a, zx);
+            }
+            continue;
+        }
+        {
+            // tile k's fragments, prepared once by mlp_frag_kernel, into LDS
+            constexpr int n16 = Lt::ALL * (int)sizeof(typename Lt::T) / 16;
+            const uint4 *src = reinterpret_cast<const uint4 *>(frag + (int64_t)k * Lt::ALL);
+            uint4 *dst = reinterpret_cast<uint4 *>(lds);
+            __syncthreads();
+            for (int e = threadIdx.x; e < n16; e += kBlock) dst[e] = src[e];
+            __syncthreads();
+        }
+        wg.zero_all();
+        D X, Y;
+        int64_t si_nx = si_of(u);
+        issue_data(u, si_nx, X);
+        if (u + G < ue) si_nx = si_of(u + G);
+        issue_dirs_of(X);
+        // one unit: compute `cur`, with unit uu + G loading into `nxt`
+        auto step = [&](int uu, D &cur, D &nxt) {
+            const bool more = uu + G < ue;
+            if (more) issue_data(uu + G, si_nx, nxt);
+            if (uu + 2 * G < ue) si_nx = si_of(uu + 2 * G);
+            compute(cur);
+            if (more) issue_dirs_of(nxt);
+        };
+        for (; u < ue; u += 2 * G) {
+            step(u, X, Y);
+            if (u + G >= ue) break;
+            step(u + G, Y, X);
+        }
+        wg.flush(partial + ((int64_t)blockIdx.x * a.K + k) * PadRow<CL>::W);
+    }
+}
+
 // Matrix-core fragments (forward and transposed) of weight set blockIdx.x,
 // in the LDS layout of the adjoint kernel.
 template <int PREC, int CL>
@@ -1422,7 +1595,11 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
     typedef typename FragT<PREC>::T FragEl;
     FragEl *frag = reinterpret_cast<FragEl *>(reinterpret_cast<char *>(partial) + partial_bytes(a));
     mlp_frag_kernel<PREC, CL><<<a.K, kBlock, 0, st>>>(a, w, frag);
-    if (act)
+    if (!act && a.F == 2)
+        mlp_bwd_pipe_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view,
+                                                                   sun, ray_id, sidx, n, n_dev, dsigma, drgb, dfeat,
+                                                                   partial, frag);
+    else if (act)
         mlp_bwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view,
                                                                     sun, ray_id, sidx, n, n_dev, dsigma, drgb, act,
                                                                     dfeat, partial, frag);

@@ -100,6 +100,11 @@ class SnakeSweep:
         self.st_in.update({f: mk(self.per_w) for f in self.FIELDS_W})
         self.st_in["step"] = torch.empty((2, 1), dtype=torch.int32, device=dev)
         self.st_out = {f: torch.empty_like(v) for f, v in self.st_in.items()}
+        # the window trains on its own stream and the swaps run on a second
+        # one, created back to back so that the runtime puts them on different
+        # hardware queues (a copy stream that shares the compute stream's queue
+        # serialises the host transfers behind the training)
+        self.compute = torch.cuda.Stream(device=dev)
         self.copy = torch.cuda.Stream(device=dev)
         self.pos = None
         self.in_tiles = None       # tiles held in the in-staging slots
@@ -209,6 +214,10 @@ class SnakeSweep:
         batches(pos, k) returns (rays_o, rays_d, target, samples_per_ray) of
         window-local rays for step k at window position pos (device tensors
         of one fixed shape).  Returns per-window times (s)."""
+        with torch.cuda.stream(self.compute):
+            return self._run(steps_per_window, batches, graph, log)
+
+    def _run(self, steps_per_window, batches, graph, log):
         path = snake_path(self.nx, self.ny)
         self._copy_events = []
         self._load_window(path[0])
@@ -219,11 +228,15 @@ class SnakeSweep:
         if graph:
             self.win.capture(*static, warmup=1)
         times = []
+        self._compute_events, self._issue_s = [], []
         for wi, pos in enumerate(path):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if wi > 0:
                 self._move(pos, path[wi + 1] if wi + 1 < len(path) else None)
+            self._issue_s.append(time.perf_counter() - t0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             for k in range(steps_per_window):
                 b = batches(pos, k)
                 for dst, src in zip(static, b):
@@ -232,6 +245,8 @@ class SnakeSweep:
                     self.win.replay()
                 else:
                     self.win.step(*static)
+            e1.record()
+            self._compute_events.append((e0, e1))
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             if log:
@@ -247,6 +262,15 @@ class SnakeSweep:
                     self.h[f][t].copy_(self._wview(f)[s])
         torch.cuda.synchronize()
         return times
+
+    def compute_ms(self):
+        """Compute-stream time of each window's training steps (from after its
+        move to its last step), in ms, after run()."""
+        return [a.elapsed_time(b) for a, b in self._compute_events]
+
+    def move_issue_ms(self):
+        """Host time to issue each window's move (copies and events), in ms."""
+        return [1e3 * x for x in self._issue_s]
 
     def copy_ms(self):
         """Copy-stream time of each move's host transfers (write-back of the two

@@ -193,14 +193,11 @@ class WindowNeRF:
         per_t = self.Lv * (1 << self.log2T) * self.F
         per_w = self.Pd if self.shared_colour else self.P
         flags = L.SNAKE_ADAM_ZERO_GRAD
-        for k in range(self.K):
-            sd = self.step_dev[k:k + 1]
-            a, b = k * per_t, k * per_w
-            L.snake_adam_step(self.table.view(-1)[a:], self.g_t.view(-1)[a:], self.m_t.view(-1)[a:],
-                              self.v_t.view(-1)[a:], per_t, self.lr, self.b1, self.b2, self.eps, 0, 0.0, flags,
-                              step_dev=sd, stream=stream)
-            L.snake_adam_step(self.params[b:], self.g_w[b:], self.m_w[b:], self.v_w[b:], per_w, self.lr, self.b1,
-                              self.b2, self.eps, 0, 0.0, flags, step_dev=sd, stream=stream)
+        # every tile's table, then every tile's networks: one launch each
+        L.snake_adam_step_tiles(self.table, self.g_t, self.m_t, self.v_t, per_t, self.K, self.lr, self.b1, self.b2,
+                                self.eps, self.step_dev, 0.0, flags, stream=stream)
+        L.snake_adam_step_tiles(self.params, self.g_w, self.m_w, self.v_w, per_w, self.K, self.lr, self.b1, self.b2,
+                                self.eps, self.step_dev, 0.0, flags, stream=stream)
         if self.shared_colour:
             c = self.K * self.Pd
             L.snake_adam_step(self.params[c:], self.g_w[c:], self.m_w[c:], self.v_w[c:], self.n_w - c,

@@ -183,10 +183,14 @@ def test_binding_raises_on_error(L):
 
 def test_tunables_table(L):
     ids = L.TUNABLES
-    assert len(ids) == 7 and sorted(ids.values()) == list(range(7))
+    assert len(ids) == 8 and sorted(ids.values()) == list(range(8))
     saved = {k: L.snake_tune_get(k) for k in ids}
     try:
         assert saved["hash_fwd_blocks_per_cu"] == 16 and saved["bin_blocks"] == 2048
+        assert saved["hash_fwd_superchunk"] == 0
+        L.snake_tune_set("hash_fwd_superchunk", 64)
+        with pytest.raises(L.SnakeError):
+            L.snake_tune_set("hash_fwd_superchunk", 65)
         L.snake_tune_set("bin_blocks", 256)
         assert L.snake_tune_get("bin_blocks") == 256
         L.snake_tune_set("bin_blocks", 0)                      # 0 restores the default

@@ -116,6 +116,34 @@ def test_hashgrid_fwd_bf16_table(L, orc, name, bf16):
         assert_values(got, ref[:, :W], rel=1e-5, abs_=1e-6, what="feat (bf16 table)")
 
 
+def test_hashgrid_fwd_superchunk_order(L, orc):
+    """The forward's work order (level by level over all samples, or
+    super-chunks of 2^20 samples with every level of one before the next)
+    changes nothing: the same bits, with a partial last super-chunk."""
+    rng = np.random.default_rng(14)
+    c, res, table = _grid_setup(L, orc, "full", rng)
+    n = 3 * (1 << 20) + 4097
+    pos = _ray_positions(rng, n)
+    g = L.grid_desc(res, c["F"], c["log2T"], L.SNAKE_BF16)
+    outs = []
+    saved = L.snake_tune_get("hash_fwd_superchunk")
+    try:
+        for v in (0, 1, 2):
+            L.snake_tune_set("hash_fwd_superchunk", v)
+            feat = torch.empty((c["L"], n, c["F"]), dtype=torch.bfloat16, device=DEV)
+            L.snake_hashgrid_fwd(g, 1, dev(table), dev(pos), None, None, n, None, feat, None)
+            outs.append(feat)
+        sync()
+    finally:
+        L.snake_tune_set("hash_fwd_superchunk", saved)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    sel = rng.choice(n, size=2000, replace=False)
+    ref = orc.hashgrid_fwd(res, c["log2T"], table, pos[sel], None, 32)
+    got = host(outs[0][:, torch.as_tensor(sel, device=DEV), :]).transpose(1, 0, 2).reshape(sel.size, -1)
+    assert_values(got, ref, 2 ** -8, 1e-6, "feat (sampled)")
+
+
 def test_hashgrid_fwd_indexed_and_device_count(L, orc):
     rng = np.random.default_rng(11)
     c, res, table = _grid_setup(L, orc, "full", rng)

@@ -156,3 +156,26 @@ def test_composite_sample_map(L):
     assert np.array_equal(host(o["n_alive"]), ref["n_alive"])
     assert np.array_equal(host(ds)[inv], ref["dsigma"])
     assert np.array_equal(host(dr)[inv], ref["drgb"])
+
+
+def test_adam_tiles_equals_separate_calls(L):
+    """Adam over K tiles in one launch, each tile with its own step count,
+    gives the bits of K separate calls (tile length not a multiple of 4)."""
+    rng = np.random.default_rng(23)
+    K, tn = 5, 33331
+    steps = np.array([1, 4, 2, 7, 3], dtype=np.int32)
+    p = rng.normal(size=K * tn).astype(np.float32)
+    m = (rng.normal(size=K * tn) * 0.1).astype(np.float32)
+    v = np.abs(rng.normal(size=K * tn) * 0.01).astype(np.float32)
+    g = rng.normal(size=K * tn).astype(np.float32)
+    A = [dev(x) for x in (p, g, m, v)]
+    sd = dev(steps, torch.int32)
+    L.snake_adam_step_tiles(*A, tn, K, 1e-2, 0.9, 0.99, 1e-15, sd, 1e-3, L.SNAKE_ADAM_ZERO_GRAD)
+    for k in range(K):
+        sl = slice(k * tn, (k + 1) * tn)
+        B = [dev(x[sl]) for x in (p, g, m, v)]             # separate, aligned tensors per tile
+        L.snake_adam_step(*B, tn, 1e-2, 0.9, 0.99, 1e-15, int(steps[k]), 1e-3, L.SNAKE_ADAM_ZERO_GRAD)
+        sync()
+        for a, b in zip(A, B):
+            assert torch.equal(a[sl], b)
+    assert torch.count_nonzero(A[1]).item() == 0
