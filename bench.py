@@ -346,8 +346,9 @@ def sweep_bench(args):
     """Snake sweep over a grid of full-size tiles (L=16, F=2, T=2^19 tables
     and Adam state in FP32, BF16 networks 32-64-16 / 18-64-3), 2x2 window
     graph-replayed, tiles swapped host<->device by pinned async copies on a
-    side stream.  Times every window of a 3x3 and of a 4x4 grid (linearity:
-    time per window-step should not depend on the grid), then renders a
+    side stream on a hardware queue of its own.  Times every window of each
+    grid (3x3, 4x4, 8x8 by default: time per window-step should not depend
+    on the grid), then renders a
     depth map of 2048x2048 rays over one tile (forward only)."""
     import torch
     import synth
@@ -379,6 +380,7 @@ def sweep_bench(args):
         comp_steady = comp[1:] if len(comp) > 1 else comp
         out["grids"].append({"tiles": n * n, "windows": npath, "total_s": round(sum(t), 4),
                              "ms_per_window_step": round(1e3 * float(np.mean(steady)) / steps, 4),
+                             "median_ms_per_window_step": round(1e3 * float(np.median(steady)) / steps, 4),
                              "compute_ms_per_window_step": round(float(np.mean(comp_steady)) / steps, 4),
                              "move_issue_ms": round(float(np.mean(sw.move_issue_ms()[1:] or [0.0])), 3),
                              "host_copy_ms_per_move": round(float(np.mean(cm)), 3) if cm else None,

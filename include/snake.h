@@ -80,6 +80,16 @@ typedef enum { SNAKE_F32 = 0, SNAKE_BF16 = 1 } snake_dtype;
 /* Library version (SNAKE_ABI_VERSION). */
 int snake_abi_version(void);
 
+/* A stream of default priority on a hardware queue of its own (a CU-masked
+ * queue with every compute unit enabled): streams created the usual way share
+ * a small pool of hardware queues, and two streams on one queue run their
+ * work one after the other, so the host transfers of a tile swap would wait
+ * for the training they should overlap.  *stream receives the handle; the
+ * caller releases it with snake_stream_destroy once no pending work or
+ * framework bookkeeping (events recorded at a later free) refers to it. */
+int snake_stream_create_dedicated(snake_stream_t *stream);
+int snake_stream_destroy(snake_stream_t stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *snake_last_error(void);
 

@@ -34,6 +34,7 @@ TUNABLES = {
 
 EXPORTS = (
     "snake_abi_version", "snake_last_error", "snake_check_device_error", "snake_tune_set", "snake_tune_get",
+    "snake_stream_create_dedicated", "snake_stream_destroy",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_sample_segmented_static_max_rays",
     "snake_sample_segmented_static", "snake_pack_alive",
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
@@ -92,6 +93,8 @@ _SIGS = {
     "snake_abi_version": ([], ctypes.c_int),
     "snake_last_error": ([], ctypes.c_char_p),
     "snake_check_device_error": ([_P, _P], ctypes.c_int),
+    "snake_stream_create_dedicated": ([_P], ctypes.c_int),
+    "snake_stream_destroy": ([_P], ctypes.c_int),
     "snake_sample_workspace_bytes": ([_I32], _SZ),
     "snake_sample_segmented": ([_P, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
                                 _I64, _P, _P, _SZ, _P], ctypes.c_int),
@@ -380,6 +383,17 @@ def snake_adam_step_tiles(p, g, m, v, tile_n, K, lr, b1, b2, eps, step_dev, l2=0
     rc = lib().snake_adam_step_tiles(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(tile_n), int(K), float(lr), float(b1),
                                      float(b2), float(eps), _ptr(step_dev), float(l2), int(flags), _stream(stream))
     _check("snake_adam_step_tiles", rc)
+
+
+def snake_stream_create_dedicated():
+    """Handle (int) of a new stream on a hardware queue of its own."""
+    h = ctypes.c_void_p()
+    _check("snake_stream_create_dedicated", lib().snake_stream_create_dedicated(ctypes.byref(h)))
+    return int(h.value)
+
+
+def snake_stream_destroy(handle):
+    _check("snake_stream_destroy", lib().snake_stream_destroy(ctypes.c_void_p(handle)))
 
 
 def snake_counter_add(counter, delta, n=None, stream=None):

@@ -86,6 +86,32 @@ int32_t snake_tune_get(int32_t which)
     return snake::g_tune[which];
 }
 
+int snake_stream_create_dedicated(snake_stream_t *stream)
+{
+    SNAKE_REQUIRE(stream != nullptr, SNAKE_ERR_NULL, "snake_stream_create_dedicated: stream is NULL");
+    const int ncu = snake::num_cus();
+    uint32_t mask[64];
+    const uint32_t words = (uint32_t)((ncu + 31) / 32);
+    SNAKE_REQUIRE(words >= 1 && words <= 64, SNAKE_ERR_INVALID_ARG, "snake_stream_create_dedicated: %d compute units",
+                  ncu);
+    for (uint32_t i = 0; i < words; ++i) mask[i] = 0xffffffffu;
+    hipStream_t st = nullptr;
+    const hipError_t e = hipExtStreamCreateWithCUMask(&st, words, mask);
+    SNAKE_REQUIRE(e == hipSuccess, SNAKE_ERR_HIP, "snake_stream_create_dedicated: %s", hipGetErrorString(e));
+    *stream = reinterpret_cast<snake_stream_t>(st);
+    snake::clear_error();
+    return SNAKE_OK;
+}
+
+int snake_stream_destroy(snake_stream_t stream)
+{
+    SNAKE_REQUIRE(stream != nullptr, SNAKE_ERR_NULL, "snake_stream_destroy: stream is NULL");
+    const hipError_t e = hipStreamDestroy(reinterpret_cast<hipStream_t>(stream));
+    SNAKE_REQUIRE(e == hipSuccess, SNAKE_ERR_HIP, "snake_stream_destroy: %s", hipGetErrorString(e));
+    snake::clear_error();
+    return SNAKE_OK;
+}
+
 int snake_abi_version(void) { return SNAKE_ABI_VERSION; }
 
 const char *snake_last_error(void) { return snake::g_msg; }

@@ -50,6 +50,23 @@ def _slot(i, j):
     return 2 * i + j        # WindowNeRF box order: tile (wx + i, wy + j)
 
 
+_COPY_STREAMS = {}
+
+
+def _copy_stream(dev):
+    """The device's copy stream: one per device, on a hardware queue of its
+    own, kept until the process ends.  It is never destroyed, since torch's
+    pinned-memory allocator records events on every stream a host block was
+    copied on when that block is freed, which may be after any sweep ends."""
+    idx = torch.device(dev).index
+    idx = torch.cuda.current_device() if idx is None else idx
+    if idx not in _COPY_STREAMS:
+        with torch.cuda.device(idx):
+            h = L.snake_stream_create_dedicated()
+        _COPY_STREAMS[idx] = torch.cuda.ExternalStream(h, device=torch.device("cuda", idx))
+    return _COPY_STREAMS[idx]
+
+
 class SnakeSweep:
     """Pinned host store of every tile's state and the device window that
     slides over it."""
@@ -100,12 +117,12 @@ class SnakeSweep:
         self.st_in.update({f: mk(self.per_w) for f in self.FIELDS_W})
         self.st_in["step"] = torch.empty((2, 1), dtype=torch.int32, device=dev)
         self.st_out = {f: torch.empty_like(v) for f, v in self.st_in.items()}
-        # the window trains on its own stream and the swaps run on a second
-        # one, created back to back so that the runtime puts them on different
-        # hardware queues (a copy stream that shares the compute stream's queue
-        # serialises the host transfers behind the training)
+        # the window trains on its own stream and the swaps run on a stream
+        # with a hardware queue of its own: streams otherwise share a small
+        # pool of queues, and a copy stream on the compute stream's queue
+        # would run the host transfers after the training instead of beside it
         self.compute = torch.cuda.Stream(device=dev)
-        self.copy = torch.cuda.Stream(device=dev)
+        self.copy = _copy_stream(dev)
         self.pos = None
         self.in_tiles = None       # tiles held in the in-staging slots
         self.out_tiles = None      # tiles held in the out-staging slots (pending copy-back)
