@@ -64,6 +64,18 @@ __device__ __forceinline__ void corners(const Grid &g, int l, const float x[3], 
     }
 }
 
+// Identity of the cell holding x on a level of resolution N <= 256 in a
+// tile: one byte per coordinate and the tile's index in the top byte.
+__device__ __forceinline__ uint32_t cell_key(const Grid &g, int l, const float x[3], int64_t tile)
+{
+    const int N = g.res[l];
+    uint32_t c[3];
+    float w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cell(x[a], N, c[a], w[a]);
+    return c[0] | (c[1] << 8) | (c[2] << 16) | ((uint32_t)tile << 24);
+}
+
 template <int F>
 struct Vec;
 template <>
@@ -138,6 +150,11 @@ struct Entry<2, float> {
 __device__ __forceinline__ void store_feat(float *p, float v) { *p = v; }
 __device__ __forceinline__ void store_feat(__hip_bfloat16 *p, float v) { *p = __float2bfloat16(v); }
 
+// Four floats read with one 16-byte load from an 8-byte aligned address, and
+// two words with one 8-byte load from a 4-byte aligned one.
+typedef float F4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t U2a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 template <int F, typename OutT, typename TabT>
 __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *__restrict__ table,
                                                            const float *__restrict__ pos,
@@ -176,9 +193,21 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
         const TabT *lev = table + ((tile * g.L + l) << g.log2T) * F;
         VT v[8];
         if constexpr (F == 2 && std::is_same<TabT, __hip_bfloat16>::value) {
-            // BF16 entries are 4 bytes: one 16-byte load covers an aligned
-            // quad of slots, which holds both x-neighbours for three pairs in four
+            // BF16 entries are 4 bytes.  On a densely indexed level the
+            // x-neighbours' slots are consecutive: one 8-byte load (4-byte
+            // aligned) fetches both.  Elsewhere one 16-byte load covers an
+            // aligned quad of slots, which holds both x-neighbours for three
+            // pairs in four.
             const uint4 *lev4 = reinterpret_cast<const uint4 *>(lev);
+            if ((g.dense_bits >> l) & 1u) {
+                const uint32_t *lev1 = reinterpret_cast<const uint32_t *>(lev);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const U2a4 w = *reinterpret_cast<const U2a4 *>(lev1 + idx[2 * p]);
+                    v[2 * p] = make_float2(bf16_bits(w.x & 0xffffu), bf16_bits(w.x >> 16));
+                    v[2 * p + 1] = make_float2(bf16_bits(w.y & 0xffffu), bf16_bits(w.y >> 16));
+                }
+            } else {
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const uint32_t a = idx[2 * p], b = idx[2 * p + 1];
@@ -194,10 +223,22 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
                     v[2 * p + 1] = Entry<F, TabT>::one(lev, b);
                 }
             }
+            }
         } else if constexpr (F == 2) {
-            // corners q and q^1 differ only in x; when their slots are an
-            // aligned pair (2m, 2m+1) -- half of all pairs, dense or hashed --
-            // one load fetches both: one cache-line request, not two
+            // corners q and q^1 differ only in x.  On a densely indexed level
+            // their slots are always consecutive (a, a+1): one 16-byte load
+            // (8-byte aligned) fetches both.  Elsewhere, when the slots are an
+            // aligned pair (2m, 2m+1) -- half of all pairs -- one load fetches
+            // both: one cache-line request, not two.
+            if ((g.dense_bits >> l) & 1u) {
+                const float *levf = reinterpret_cast<const float *>(lev);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const F4a8 w = *reinterpret_cast<const F4a8 *>(levf + 2 * (size_t)idx[2 * p]);
+                    v[2 * p] = make_float2(w.x, w.y);
+                    v[2 * p + 1] = make_float2(w.z, w.w);
+                }
+            } else {
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const uint32_t a = idx[2 * p], b = idx[2 * p + 1];
@@ -210,6 +251,7 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
                     v[2 * p] = Entry<F, TabT>::one(lev, a);
                     v[2 * p + 1] = Entry<F, TabT>::one(lev, b);
                 }
+            }
             }
         } else {
 #pragma unroll
@@ -318,9 +360,9 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 // final one to FP32, so every table entry keeps its own relative precision
 // however small it is against the level's largest gradient.
 //
-// Consecutive samples of a ray that share a corner are first merged across
-// the wavefront (whole runs), which shortens the item list on the coarse
-// levels; an item is one 64-bit word for F <= 2.
+// Consecutive samples of a ray that lie in one cell are first merged across
+// the wavefront (whole runs, all eight corners at once), which shortens the
+// item list on the coarse levels; an item is one 64-bit word for F <= 2.
 
 constexpr int kBinBlocks = 2048;        // most count/scatter blocks (the workspace holds this many)
 constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
@@ -405,18 +447,21 @@ __device__ __forceinline__ void run_bounds(uint32_t key, bool act, unsigned long
     rs = hb ? 63 - __clzll((long long)hb) : lane;
 }
 
-// Sum each run across the wavefront (segmented inclusive scan, FP32); returns
-// whether this lane emits, with v the run total there.  The additions follow
-// the lanes' positions in the wavefront only, and wavefronts always cover the
-// same 64 samples, so the sums are the same bits for any grid.
+// Sum each run across the wavefront (segmented inclusive scan, FP32) for all
+// eight corners at once: a run is a stretch of consecutive active lanes whose
+// samples lie in one cell (cellkey), so every corner of the cell has the same
+// key along it.  Returns whether this lane emits the run's eight items, with
+// v the run totals there.  The additions follow the lanes' positions in the
+// wavefront only, and wavefronts always cover the same 64 samples, so the
+// sums are the same bits for any grid.
 template <int F>
-__device__ __forceinline__ bool merge_runs(uint32_t key, bool act, float (&v)[F])
+__device__ __forceinline__ bool merge_runs(uint32_t cellkey, bool act, float (&v)[8][F])
 {
     const int lane = lane_id();
     unsigned long long acts, heads;
     int rs;
     bool rtail;
-    run_bounds(key, act, acts, heads, rs, rtail);
+    run_bounds(cellkey, act, acts, heads, rs, rtail);
     if (heads == acts) return act;                 // no run longer than one lane
     // Scan steps d = 1, 2, ... complete every run of up to 2d lanes; c holds
     // the lanes that end d consecutive continuation lanes (active lanes that
@@ -424,24 +469,28 @@ __device__ __forceinline__ bool merge_runs(uint32_t key, bool act, float (&v)[F]
     // The count is the same on every lane (it comes from ballots).
     unsigned long long c = acts & ~heads;
     for (int d = 1; d < 64 && c != 0ull; d <<= 1) {
+        const bool take = lane - d >= rs;
 #pragma unroll
-        for (int f = 0; f < F; ++f) {
-            const float u = __shfl_up(v[f], d, 64);
-            if (lane - d >= rs) v[f] += u;
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const float u = __shfl_up(v[q][f], d, 64);
+                if (take) v[q][f] += u;
+            }
         }
         c &= c >> d;
     }
     return rtail;
 }
 
-// The lane that emits a run's item; the same decision as merge_runs, without
+// The lane that emits a run's items; the same decision as merge_runs, without
 // the sums (the count pass needs only how many items).
-__device__ __forceinline__ bool run_tail(uint32_t key, bool act)
+__device__ __forceinline__ bool run_tail(uint32_t cellkey, bool act)
 {
     unsigned long long acts, heads;
     int rs;
     bool rtail;
-    run_bounds(key, act, acts, heads, rs, rtail);
+    run_bounds(cellkey, act, acts, heads, rs, rtail);
     return rtail;
 }
 
@@ -562,19 +611,24 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
         }
         const bool tile_ok = tile < g.K;
         if (valid && !tile_ok && g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_TILE_ID);
+        const bool live = valid && tile_ok;
+        // the level's gradients, loaded one level ahead; lanes past the range
+        // read the block's first sample (a valid address) and discard it
+        const int64_t sl = valid ? s : s0;
+        VT gnext = *reinterpret_cast<const VT *>(dfeat + ((int64_t)bp.l0 * n + sl) * F);
         for (int lr = 0; lr < bp.lg; ++lr) {
             const int l = bp.l0 + lr;
             const bool dense_l = (g.dense_bits >> l) & 1u;
             const bool merge_l = g.res[l] <= kMergeMaxRes;
+            const VT gv = gnext;
+            if (lr + 1 < bp.lg) gnext = *reinterpret_cast<const VT *>(dfeat + ((int64_t)(l + 1) * n + sl) * F);
             // whether the sample contributes does not depend on its level's
             // largest |dfeat| (the scatter emits the same items, with zero
             // values for a level that holds a non-finite value); that maximum
             // is taken here, for the scatter's fixed-point scale
-            bool act = false;
+            const bool act = live && grad_nonzero<F>(gv);
             uint32_t gm = 0u;
-            if (valid && tile_ok) {
-                const VT gv = *reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F);
-                act = grad_nonzero<F>(gv);
+            if (live) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) gm = umax(gm, absbits(Vec<F>::get(gv, f)));
             }
@@ -594,10 +648,12 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
                 }
                 continue;
             }
+            // on merged levels a run of samples in one cell emits one item per
+            // corner, from its last lane
+            const bool emit = merge_l ? run_tail(cell_key(g, l, x, tile), act) : act;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint32_t key = ((uint32_t)tile << bp.T_log2) + idx[q];
-                const bool emit = merge_l ? run_tail(key, act) : act;
                 const int b = lr * bp.nbpl + (int)(key >> bp.binshift);
                 int b0;
                 // the vote must run on every lane: inside the leader's branch
@@ -622,74 +678,58 @@ __global__ __launch_bounds__(256) void bin_count_kernel(Grid g, BinPlan bp, cons
     }
 }
 
-// Exclusive prefix sum of cnt[0..m) into off[0..m) by the 256 threads of a
-// block; returns the total.  wtot is 4 ints of LDS.  Ends synchronised.
-__device__ __forceinline__ int block_exclusive_scan(const int *cnt, int *off, int m, int *wtot)
-{
-    const int per = (m + 255) >> 8;
-    const int b0 = threadIdx.x * per;
-    int sum = 0;
-    for (int k = 0; k < per; ++k)
-        if (b0 + k < m) sum += cnt[b0 + k];
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    int inc = sum;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += u;
-    }
-    if (lane == 63) wtot[wv] = inc;
-    __syncthreads();
-    int run = inc - sum, total = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const int t = wtot[w];
-        run += w < wv ? t : 0;
-        total += t;
-    }
-    for (int k = 0; k < per; ++k)
-        if (b0 + k < m) {
-            off[b0 + k] = run;
-            run += cnt[b0 + k];
-        }
-    __syncthreads();
-    return total;
-}
-
-constexpr int kScatterBatch = 256 * 8;  // items of one (256-sample chunk, level)
+// Scatter block: 512 threads (a batch of 4096 items) for one-word items,
+// 256 for two-word ones (F = 4), so the staging stays within 64 KB of LDS.
+// For one-word items the kernel is held to 80 registers, so three blocks
+// (24 wavefronts) share a CU: the batches' barriers leave fewer idle cycles.
+template <int F>
+struct ScatterShape {
+    static constexpr int threads = F == 4 ? 256 : 512;
+    static constexpr int batch = threads * 8;      // items of one (chunk, level) batch at most
+    static constexpr int waves_per_simd = F == 4 ? 1 : 6;
+};
 constexpr size_t kScatterLds = 64 * 1024;
+constexpr int kDropped = INT32_MIN;                 // a bin whose batch is not written
 
-// Dynamic LDS of the scatter pass, in ints.
+// Dynamic LDS of the scatter pass, in bytes: the staged items (8-byte words,
+// first, for alignment), their bins (16-bit), then the int arrays.
 static size_t scatter_lds_bytes(int nb, int nbpl, int F)
 {
-    return sizeof(int) * ((size_t)2 * nb + (size_t)3 * nbpl + 8 + (size_t)kScatterBatch * (1 + F));
+    const size_t nw = F == 4 ? 2 : 1;
+    const size_t threads = F == 4 ? ScatterShape<4>::threads : ScatterShape<1>::threads;
+    return threads * 8 * (8 * nw + 2) + sizeof(int) * ((size_t)2 * nb + (size_t)3 * nbpl + 1);
 }
 
-// Each (256-sample chunk, level) batch of items is counting-sorted by bin in
-// LDS first, then written out bin by bin, so consecutive lanes store
+// Each (chunk, level) batch of items is encoded in registers, counting-sorted
+// by bin into LDS, then written out in that order, so consecutive lanes store
 // consecutive item slots of one bin instead of each lane hitting its own
-// random cache line.
+// random cache line.  The next level's gradients are loaded while the
+// current level is sorted.
 template <int F>
-__global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
-                                                          const uint8_t *__restrict__ tile_id,
-                                                          const int32_t *__restrict__ sidx, int64_t n,
-                                                          const int64_t *__restrict__ n_dev,
-                                                          const float *__restrict__ dfeat,
-                                                          const int32_t *__restrict__ offsets,
-                                                          const int32_t *__restrict__ counts,
-                                                          const uint32_t *__restrict__ lmax,
-                                                          unsigned long long *__restrict__ items)
+__global__ __launch_bounds__(ScatterShape<F>::threads) __attribute__((amdgpu_waves_per_eu(ScatterShape<F>::waves_per_simd))) void bin_scatter_kernel(Grid g, BinPlan bp, const float *__restrict__ pos,
+                                                                      const uint8_t *__restrict__ tile_id,
+                                                                      const int32_t *__restrict__ sidx, int64_t n,
+                                                                      const int64_t *__restrict__ n_dev,
+                                                                      const float *__restrict__ dfeat,
+                                                                      const int32_t *__restrict__ offsets,
+                                                                      const int32_t *__restrict__ counts,
+                                                                      const uint32_t *__restrict__ lmax,
+                                                                      unsigned long long *__restrict__ items,
+                                                                      int64_t dummy)
 {
     typedef typename Vec<F>::T VT;
-    extern __shared__ int sm[];
-    int *cursor = sm;                                   // [nb] next free item of this block's range
-    int *cend = cursor + bp.nb;                         // [nb] end of this block's range
-    int *hcnt = cend + bp.nb;                           // [nbpl] items of the batch per bin
-    int *hoff = hcnt + bp.nbpl;                         // [nbpl] their start in the staging area
-    int *gbase = hoff + bp.nbpl;                        // [nbpl] their first global slot (-1: dropped)
-    int *wtot = gbase + bp.nbpl;                        // [8]
-    uint32_t *skey = reinterpret_cast<uint32_t *>(wtot + 8);        // [batch]
-    float *sval = reinterpret_cast<float *>(skey + kScatterBatch);  // [batch][F] item values
+    constexpr int NW = ItemFmt<F>::NW;
+    constexpr int NT = ScatterShape<F>::threads;
+    constexpr int kScatterBatch = ScatterShape<F>::batch;
+    extern __shared__ unsigned long long sm64[];
+    unsigned long long *sitem = sm64;                                         // [batch][NW], bin-sorted
+    uint16_t *sbin = reinterpret_cast<uint16_t *>(sitem + kScatterBatch * NW);  // [batch] bin in the level
+    int *cursor = reinterpret_cast<int *>(sbin + kScatterBatch);             // [nb] next free item of the range
+    int *cend = cursor + bp.nb;                                              // [nb] end of this block's range
+    int *hcnt = cend + bp.nb;                                                // [nbpl] items of the batch per bin
+    int *hoff = hcnt + bp.nbpl;                                              // [nbpl] their start in the staging
+    int *delta = hoff + bp.nbpl;                                             // [nbpl] global - staging index
+    int *wtot = delta + bp.nbpl;                                             // [1] the batch's item count
     for (int b = threadIdx.x; b < bp.nb; b += blockDim.x) {
         const int64_t i = (int64_t)b * gridDim.x + blockIdx.x;
         cursor[b] = offsets[i];
@@ -701,19 +741,18 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
     block_range(effective_n(n, n_dev), s0, s1);
     const int lane = lane_id();
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t base = s0; base < s1; base += blockDim.x) {
+    const uint32_t smask = (1u << bp.binshift) - 1u;
+    for (int64_t base = s0; base < s1; base += NT) {
         const int64_t s = base + threadIdx.x;
         const bool valid = s < s1;
-        float x[3] = {0.f, 0.f, 0.f};
-        int64_t tile = 0;
-        if (valid) {
-            const int64_t si = sidx ? sidx[s] : s;
-            x[0] = pos[3 * si];
-            x[1] = pos[3 * si + 1];
-            x[2] = pos[3 * si + 2];
-            tile = tile_id ? tile_id[si] : 0;
-        }
-        const bool tile_ok = tile < g.K;
+        // lanes past the range read the block's first sample (a valid
+        // address) and discard it; the loads are branch-free
+        const int64_t sl = valid ? s : s0;
+        const int64_t si = sidx ? sidx[sl] : sl;
+        const float x[3] = {pos[3 * si], pos[3 * si + 1], pos[3 * si + 2]};
+        const int64_t tile = tile_id ? tile_id[si] : 0;
+        const bool live = valid && tile < g.K;
+        VT gnext = *reinterpret_cast<const VT *>(dfeat + ((int64_t)bp.l0 * n + sl) * F);
         for (int lr = 0; lr < bp.lg; ++lr) {
             const int l = bp.l0 + lr;
             const bool dense_l = (g.dense_bits >> l) & 1u;
@@ -721,15 +760,12 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
             const uint32_t lm = lmax[l];
             const int Et = level_top(lm);
             const bool lok = level_ok(lm);
+            VT gv = gnext;
+            if (lr + 1 < bp.lg) gnext = *reinterpret_cast<const VT *>(dfeat + ((int64_t)(l + 1) * n + sl) * F);
             // the same decision as the count pass; a level without a finite,
             // nonzero maximum emits its items with zero values
-            bool act = false;
-            VT gv = {};
-            if (valid && tile_ok) {
-                gv = *reinterpret_cast<const VT *>(dfeat + ((int64_t)l * n + s) * F);
-                act = grad_nonzero<F>(gv);
-                if (!lok) gv = VT{};
-            }
+            const bool act = live && grad_nonzero<F>(gv);
+            if (!live || !lok) gv = VT{};
             uint32_t idx[8];
             float wt[8];
             corners(g, l, x, idx, wt);
@@ -751,9 +787,9 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                     for (int q = 0; q < 8; ++q) rank[q] = atomicAdd(&hcnt[key[q] >> bp.binshift], 1);
                 }
             } else {
+                const bool emit = merge_l ? merge_runs<F>(cell_key(g, l, x, tile), act, v) : act;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const bool emit = merge_l ? merge_runs<F>(key[q], act, v[q]) : act;
                     const int bl = (int)(key[q] >> bp.binshift);
                     int b0;
                     if (dense_l && wave_uniform(bl, emit, b0)) {
@@ -768,29 +804,57 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                     }
                 }
             }
+            // (this barrier also ends the previous batch's write-out on every
+            // wavefront, so its staging and offsets may be overwritten below)
             __syncthreads();
-            // 2. staging offsets, and this block's global slots for each bin
-            const int total = block_exclusive_scan(hcnt, hoff, bp.nbpl, wtot);
-            for (int bl = threadIdx.x; bl < bp.nbpl; bl += blockDim.x) {
-                const int c = hcnt[bl];
-                hcnt[bl] = 0;
-                if (c == 0) continue;
-                const int b = lr * bp.nbpl + bl;
-                const int at = cursor[b];
-                cursor[b] = at + c;
-                if (at + c > cend[b]) {            // count and scatter disagree: never write past the range
-                    if (g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_INTERNAL);
-                    gbase[bl] = -1;
-                } else {
-                    gbase[bl] = at;
-                }
-            }
-            // 3. counting-sort the batch into the staging area
-            auto stage_item = [&](int q) {
-                const int at = hoff[key[q] >> bp.binshift] + rank[q];
-                skey[at] = key[q];
+            // 3. one wavefront: staging offsets (exclusive scan of the bin
+            // counts), this block's global slots for each bin, counts reset
+            if (threadIdx.x < 64) {
+                const int per = (bp.nbpl + 63) >> 6;
+                const int b0 = lane * per;
+                int sum = 0;
+                for (int k = 0; k < per; ++k)
+                    if (b0 + k < bp.nbpl) sum += hcnt[b0 + k];
+                int inc = sum;
 #pragma unroll
-                for (int f = 0; f < F; ++f) sval[at * F + f] = v[q][f];
+                for (int dd = 1; dd < 64; dd <<= 1) {
+                    const int u = __shfl_up(inc, dd, 64);
+                    if (lane >= dd) inc += u;
+                }
+                int run = inc - sum;
+                for (int k = 0; k < per; ++k) {
+                    const int bl = b0 + k;
+                    if (bl >= bp.nbpl) break;
+                    const int c = hcnt[bl];
+                    hcnt[bl] = 0;
+                    hoff[bl] = run;
+                    if (c > 0) {
+                        const int b = lr * bp.nbpl + bl;
+                        const int at = cursor[b];
+                        cursor[b] = at + c;
+                        if (at + c > cend[b]) {        // count and scatter disagree: never write past the range
+                            if (g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_INTERNAL);
+                            delta[bl] = kDropped;
+                        } else {
+                            delta[bl] = at - run;
+                        }
+                    }
+                    run += c;
+                }
+                if (lane == 63) wtot[0] = inc;
+            }
+            __syncthreads();
+            const int total = wtot[0];
+            // 4. counting-sort the batch into the staging area, in the items'
+            // stored form (the level's scale is known)
+            auto stage_item = [&](int q) {
+                const int bl = (int)(key[q] >> bp.binshift);
+                const int at = hoff[bl] + rank[q];
+                uint32_t code[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) code[f] = val_encode(v[q][f], Et);
+                item_pack<F>(sitem + at * NW, key[q] & smask, bp.binshift, code);
+                sbin[at] = (uint16_t)bl;
             };
             if (!merge_l && !dense_l) {
                 if (act) {
@@ -803,19 +867,30 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(Grid g, BinPlan bp, co
                     if (rank[q] >= 0) stage_item(q);
             }
             __syncthreads();
-            // 4. write out: consecutive threads, consecutive slots of a bin
-            const uint32_t smask = (1u << bp.binshift) - 1u;
-            for (int j = threadIdx.x; j < total; j += blockDim.x) {
-                const uint32_t k = skey[j];
-                const int bl = (int)(k >> bp.binshift);
-                const int gb = gbase[bl];
-                if (gb < 0) continue;
-                uint32_t code[F];
+            // 5. write out: consecutive threads, consecutive slots of a bin.
+            // Branch-free: a lane with no item (past the batch, or in a bin
+            // the count did not allow) writes the dummy item, so every lane
+            // issues the same stores and the next level's gradient load can
+            // be waited for without draining them.
+            {
+                constexpr int U = kScatterBatch / NT;
+                int jj[U], d[U];
 #pragma unroll
-                for (int f = 0; f < F; ++f) code[f] = val_encode(sval[j * F + f], Et);
-                item_pack<F>(items + (int64_t)(gb + (j - hoff[bl])) * ItemFmt<F>::NW, k & smask, bp.binshift, code);
+                for (int u = 0; u < U; ++u) {
+                    const int j = threadIdx.x + u * NT;
+                    jj[u] = j < total ? j : -1;
+                    d[u] = sbin[j];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) d[u] = delta[jj[u] >= 0 ? d[u] : 0];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = threadIdx.x + u * NT;
+                    const int64_t dst = (jj[u] >= 0 && d[u] != kDropped) ? (int64_t)(j + d[u]) : dummy;
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) items[dst * NW + k] = sitem[j * NW + k];
+                }
             }
-            __syncthreads();
         }
     }
 }
@@ -908,27 +983,49 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, 
                 small[e] = 0ull;
             }
             __syncthreads();
-            // kRU items per thread per round keep enough loads in flight
-            for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kRU * blockDim.x) {
-                unsigned long long w[kRU][NW];
+            // kRU items per thread per round, and the next round's loads issued
+            // before this round's additions, keep enough loads in flight.  The
+            // loads are branch-free: past the end they re-read the last item,
+            // which then adds zero.
+            const int64_t stride = (int64_t)kRU * blockDim.x;
+            unsigned long long wa[kRU][NW], wb[kRU][NW];
+            auto load = [&](unsigned long long (&w)[kRU][NW], int64_t i0) {
 #pragma unroll
                 for (int u = 0; u < kRU; ++u) {
-                    const int64_t i = i0 + (int64_t)u * blockDim.x;
-                    if (i < hi) {
+                    int64_t i = i0 + (int64_t)u * blockDim.x;
+                    i = i < hi ? i : hi - 1;
 #pragma unroll
-                        for (int k = 0; k < NW; ++k) w[u][k] = items[i * NW + k];
-                    }
+                    for (int k = 0; k < NW; ++k) w[u][k] = items[i * NW + k];
                 }
+            };
+            auto add = [&](const unsigned long long (&w)[kRU][NW], int64_t i0) {
 #pragma unroll
                 for (int u = 0; u < kRU; ++u) {
-                    if (i0 + (int64_t)u * blockDim.x < hi) {
-                        uint32_t slot;
-                        uint32_t v[F];
-                        item_unpack<F>(w[u], smask, bp.binshift, slot, v);
+                    const bool ok = i0 + (int64_t)u * blockDim.x < hi;
+                    uint32_t slot;
+                    uint32_t v[F];
+                    item_unpack<F>(w[u], smask, bp.binshift, slot, v);
 #pragma unroll
-                        for (int f = 0; f < F; ++f) val_accumulate(v[f], &big[f * slots + slot], &small[f * slots + slot]);
-                    }
+                    for (int f = 0; f < F; ++f)
+                        val_accumulate(ok ? v[f] : 0u, &big[f * slots + slot], &small[f * slots + slot]);
                 }
+            };
+            // the rounds alternate between the two buffers (unrolled by two);
+            // every load is unconditional, so the compiler can count them
+            // (the scheduling barriers keep the compiler from sinking a round's
+            // loads below the previous round's additions)
+            int64_t i0 = lo + threadIdx.x;
+            load(wa, i0);
+            while (i0 < hi) {
+                load(wb, i0 + stride);
+                __builtin_amdgcn_sched_barrier(0);
+                add(wa, i0);
+                i0 += stride;
+                if (i0 >= hi) break;
+                load(wa, i0 + stride);
+                __builtin_amdgcn_sched_barrier(0);
+                add(wb, i0);
+                i0 += stride;
             }
             __syncthreads();
             // W = big 2^22 + small (in units of 2^(Et-63)) as hi 2^52 + lo with
@@ -1031,13 +1128,14 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace of a pass over lg levels for n samples: counts, offsets, scan
 // sums, the item count, per-level maxima, the pass's integer accumulator
-// (lg x 2^kt2 x F x two int64) and the items.
+// (lg x 2^kt2 x F x two int64) and the items (with one dummy item past the
+// last, which the scatter's idle lanes write).
 static size_t bin_ws_bytes(int nb, int64_t n, int lg, int F, int kt2_log2)
 {
     const int64_t ncnt = (int64_t)nb * kBinBlocks;
     return align256((size_t)SNAKE_MAX_LEVELS * 4) + 2 * align256((size_t)ncnt * 4) +
            align256((size_t)scan::scan_blocks(ncnt) * 8) + 256 + align256(((size_t)lg << kt2_log2) * F * 16) +
-           align256((size_t)n * lg * 8 * (F == 4 ? 2 : 1) * 8);
+           align256(((size_t)n * lg * 8 + 1) * (F == 4 ? 2 : 1) * 8);
 }
 
 static BinPlan make_plan(int L, int F, int log2T, int K, int l0, int lg)
@@ -1259,8 +1357,8 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.lmax,     \
                                                w.counts);                                                  \
     scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items, err, st);   \
-    bin_scatter_kernel<FF><<<nblk, 256, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(                     \
-        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.lmax, w.items);            \
+    bin_scatter_kernel<FF><<<nblk, ScatterShape<FF>::threads, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(                     \
+        g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.lmax, w.items, w.item_cap); \
     bin_reduce_kernel<FF><<<rgrid, kReduceThreads, 0, st>>>(bp, w.offsets, nblk, w.n_items, w.items, w.lmax, w.acc64); \
     bin_convert_kernel<FF><<<cgrid, 256, 0, st>>>(bp, g.L, w.acc64, w.lmax, K, dtable)
         if (F == 1) {
