@@ -338,12 +338,15 @@ __global__ __launch_bounds__(256) void hashgrid_bwd_kernel(Grid g, const float *
 // A pass covers `lg` levels; bins never straddle levels.
 //
 // Item values.  Each stored value (one corner's w*g, or the FP32 sum of a run
-// of consecutive samples of a ray sharing the slot) is rounded once to a
-// 26-bit float: a sign, a 6-bit exponent k counted down from the level's top
-// exponent Et = e + 7 (2^(e-1) <= max|dfeat of the level| < 2^e, so every
-// value is below 2^(Et-1) even for a run of 64 lanes), and 19 stored mantissa
-// bits, i.e. |v| = 1.m * 2^(Et-k) with 20 significant bits (relative error
-// at most 2^-20).  Values below 2^(Et-63) = 2^(e-56) are stored as zero.
+// of consecutive samples of a ray in one cell) is rounded once to a 26-bit
+// float: a sign, a 6-bit code exponent j and 19 stored mantissa bits.  With
+// the level's top exponent Et = e + 7 (2^(e-1) <= max|dfeat of the level| <
+// 2^e, so every value is below 2^(Et-1) even for a run of 64 lanes) a value
+// |v| = 1.m * 2^(Et-k) has k = 1..63 and is stored with j = 64 - k (j = 0
+// is the value 0), i.e. its biased FP32 exponent less a per-level base: the
+// code is the rounded exponent-and-mantissa bits less a constant.  20
+// significant bits (relative error at most 2^-20); values below 2^(Et-63) =
+// 2^(e-56) are stored as zero.
 //
 // Exact sums.  LDS float atomics are slow on this chip (about 2e11/s) while
 // LDS integer atomics are about 20x faster, so the values are summed as
@@ -369,8 +372,10 @@ constexpr int kMaxBins = 4096;          // bins per pass (LDS counters)
 constexpr int kAccWords = 8192;         // LDS accumulators: 2 x 8192 int64 = 128 KB
 constexpr int kReduceThreads = 1024;    // reduce block: many loads in flight per CU
 constexpr int kReducePerCU = 1;         // reduce blocks resident per CU (128 KB of LDS each)
-constexpr int kRU = 8;                  // items in flight per thread in the reduce (more: the F = 4
-                                        // kernel reaches 128 registers, and then gave wrong sums)
+constexpr int kRU = 6;                  // items in flight per thread in the reduce, per buffer (16
+                                        // wavefronts per CU allow 128 registers; builds of this
+                                        // kernel at exactly 128 have given wrong sums, so kRU keeps
+                                        // it below that)
 constexpr int64_t kFlushItems = 1 << 21;  // most items a block adds into its LDS copy between flushes
 
 struct BinPlan {
@@ -494,28 +499,43 @@ __device__ __forceinline__ bool run_tail(uint32_t cellkey, bool act)
     return rtail;
 }
 
-// 26-bit item value of v for a level of top exponent Et (see above): sign in
-// bit 25, k = Et - exponent in bits 19..24 (1..63; 0 only for the value 0),
-// mantissa rounded to 19 bits (nearest, ties to even) in bits 0..18.
-// Zeros, subnormals and values below 2^(Et-63) are stored as 0.
-__device__ __forceinline__ uint32_t val_encode(float v, int Et)
+// A level's item code: the biased exponent B - 1 that code exponent 0 sits
+// below (B = Et + 64, at least 1, so that code exponent j = 1 holds
+// 2^(Et-63) whenever Et + 64 >= 1), and k0 with k = k0 - j, the distance of
+// a value's exponent below Et (1..63 for every value of the level).
+struct LevelCode {
+    uint32_t base;      // (B - 1) << 19
+    int k0;             // Et + 128 - B
+};
+__device__ __forceinline__ LevelCode level_code(int Et)
+{
+    const int B = Et + 64 > 1 ? Et + 64 : 1;
+    return LevelCode{(uint32_t)(B - 1) << 19, Et + 128 - B};
+}
+
+// 26-bit item value of v (see above): sign in bit 25, code exponent j (1..63;
+// 0 only for the value 0) in bits 19..24, mantissa rounded to 19 bits
+// (nearest, ties to even) in bits 0..18.  The rounded exponent and mantissa
+// less the level's base are j and the mantissa at once (a carry out of the
+// mantissa moves into the exponent, as it should).  Zeros, subnormals and
+// values below the level's range are stored as 0.
+__device__ __forceinline__ uint32_t val_encode(float v, uint32_t base)
 {
     const uint32_t u = __float_as_uint(v);
     const uint32_t a = u & 0x7fffffffu;
-    // exponent and mantissa rounded to 19 bits at once: a carry out of the
-    // mantissa moves into the exponent field, as it should
     const uint32_t r = (a + 0x7u + ((a >> 4) & 1u)) >> 4;
-    const int k = Et + 127 - (int)(r >> 19);
-    // every value is below 2^(Et-1), so k >= 1 unless v is not finite (a level
-    // with a non-finite gradient stores zeros before this point)
-    return (a >= 0x00800000u && k <= 63) ? (((u >> 31) << 25) | ((uint32_t)k << 19) | (r & 0x7ffffu)) : 0u;
+    const uint32_t d = r - base;
+    // every value is below 2^(Et-1), so j <= 63 unless v is not finite (a
+    // level with a non-finite gradient stores zeros before this point)
+    return d - (1u << 19) < (63u << 19) ? (d | ((u >> 6) & (1u << 25))) : 0u;
 }
 
-// An item is one 64-bit word (F = 1, 2) or two (F = 4): the slot within its
-// bin in the low binshift bits (at most 13), then F 26-bit values, the
-// fourth feature's pair in the second word.
+// An item is one 64-bit word (F = 1, 2) or two (F = 4): the F 26-bit values
+// from bit 0 up (the fourth feature's pair in the second word), and the slot
+// within the bin in the top bits of the first word (from bit 26 for F = 1,
+// bit 52 otherwise: at most 13 and 12 bits).
 constexpr int kValBits = 26;
-constexpr uint64_t kValMask = (1ull << kValBits) - 1ull;
+constexpr uint32_t kValMask = (1u << kValBits) - 1u;
 
 template <int F>
 struct ItemFmt {
@@ -523,38 +543,47 @@ struct ItemFmt {
 };
 
 template <int F>
-__device__ __forceinline__ void item_pack(unsigned long long *dst, uint32_t slot, int sb, const uint32_t *v)
+__device__ __forceinline__ void item_pack(unsigned long long *dst, uint32_t slot, const uint32_t *v)
 {
-    uint64_t w0 = (uint64_t)slot;
-    w0 |= ((uint64_t)v[0] & kValMask) << sb;
-    if constexpr (F >= 2) w0 |= ((uint64_t)v[1] & kValMask) << (sb + kValBits);
-    dst[0] = w0;
-    if constexpr (F == 4) dst[1] = ((uint64_t)v[2] & kValMask) | (((uint64_t)v[3] & kValMask) << kValBits);
+    if constexpr (F == 1) {
+        dst[0] = (unsigned long long)v[0] | ((unsigned long long)slot << kValBits);
+    } else {
+        const uint32_t lo = v[0] | (v[1] << kValBits);
+        const uint32_t hi = (v[1] >> (32 - kValBits)) | (slot << 20);
+        dst[0] = (unsigned long long)lo | ((unsigned long long)hi << 32);
+    }
+    if constexpr (F == 4) dst[1] = (unsigned long long)v[2] | ((unsigned long long)v[3] << kValBits);
 }
 
 template <int F>
-__device__ __forceinline__ void item_unpack(const unsigned long long *src, uint32_t smask, int sb, uint32_t &slot,
-                                            uint32_t (&v)[F])
+__device__ __forceinline__ void item_unpack(const unsigned long long *src, uint32_t &slot, uint32_t (&v)[F])
 {
     const uint64_t w0 = src[0];
-    slot = (uint32_t)w0 & smask;
-    v[0] = (uint32_t)(w0 >> sb) & (uint32_t)kValMask;
-    if constexpr (F >= 2) v[1] = (uint32_t)(w0 >> (sb + kValBits)) & (uint32_t)kValMask;
+    const uint32_t lo = (uint32_t)w0, hi = (uint32_t)(w0 >> 32);
+    if constexpr (F == 1) {
+        slot = (uint32_t)(w0 >> kValBits);
+        v[0] = lo & kValMask;
+    } else {
+        slot = hi >> 20;
+        v[0] = lo & kValMask;
+        v[1] = ((lo >> kValBits) | (hi << (32 - kValBits))) & kValMask;
+    }
     if constexpr (F == 4) {
         const uint64_t w1 = src[1];
-        v[2] = (uint32_t)w1 & (uint32_t)kValMask;
-        v[3] = (uint32_t)(w1 >> kValBits) & (uint32_t)kValMask;
+        v[2] = (uint32_t)w1 & kValMask;
+        v[3] = (uint32_t)(w1 >> kValBits) & kValMask;
     }
 }
 
 // Adds a 26-bit value into the big (unit 2^(Et-41)) or the small (unit
 // 2^(Et-63)) LDS accumulator, without branches (a zero value adds 0).
-__device__ __forceinline__ void val_accumulate(uint32_t code, unsigned long long *big, unsigned long long *small)
+__device__ __forceinline__ void val_accumulate(uint32_t code, int k0, unsigned long long *big,
+                                               unsigned long long *small)
 {
-    const int k = (int)((code >> 19) & 63u);
+    const int k = k0 - (int)((code >> 19) & 63u);       // k0 for the value 0
     const uint32_t m = code ? ((code & 0x7ffffu) | 0x80000u) : 0u;
     const bool isbig = k <= 22;
-    const int sh = (isbig ? 22 : 44) - k;        // -19 .. 21 (k = 0 only for the value 0)
+    const int sh = (isbig ? 22 : 44) - k;        // -19 .. 21 for the values (k = 1..63)
     const int shl = sh > 0 ? sh : 0, shr = sh < 0 ? -sh : 0;
     // below 2^(Et-44) (shr > 0): rounded to the unit, halves away from 0
     const uint32_t mr = (m + ((1u << shr) >> 1)) >> shr;
@@ -758,7 +787,7 @@ __global__ __launch_bounds__(ScatterShape<F>::threads) __attribute__((amdgpu_wav
             const bool dense_l = (g.dense_bits >> l) & 1u;
             const bool merge_l = g.res[l] <= kMergeMaxRes;
             const uint32_t lm = lmax[l];
-            const int Et = level_top(lm);
+            const uint32_t cbase = level_code(level_top(lm)).base;
             const bool lok = level_ok(lm);
             VT gv = gnext;
             if (lr + 1 < bp.lg) gnext = *reinterpret_cast<const VT *>(dfeat + ((int64_t)(l + 1) * n + sl) * F);
@@ -852,8 +881,8 @@ __global__ __launch_bounds__(ScatterShape<F>::threads) __attribute__((amdgpu_wav
                 const int at = hoff[bl] + rank[q];
                 uint32_t code[F];
 #pragma unroll
-                for (int f = 0; f < F; ++f) code[f] = val_encode(v[q][f], Et);
-                item_pack<F>(sitem + at * NW, key[q] & smask, bp.binshift, code);
+                for (int f = 0; f < F; ++f) code[f] = val_encode(v[q][f], cbase);
+                item_pack<F>(sitem + at * NW, key[q] & smask, code);
                 sbin[at] = (uint16_t)bl;
             };
             if (!merge_l && !dense_l) {
@@ -974,6 +1003,7 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, 
         const uint32_t kbase = (uint32_t)b << bp.binshift;
         const int lr = (int)(kbase >> bp.kt2_log2);
         if (!level_ok(lmax[bp.l0 + lr])) continue;          // block-uniform
+        const int k0 = level_code(level_top(lmax[bp.l0 + lr])).k0;
         unsigned long long *dst = acc + (((int64_t)lr << bp.kt2_log2) + (int64_t)(kbase & ((1u << bp.kt2_log2) - 1u))) * F * 2;
         // at most kFlushItems items between flushes keep the LDS sums in range
         for (int64_t lo = blo; lo < bhi; lo += kFlushItems) {
@@ -1004,10 +1034,10 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, 
                     const bool ok = i0 + (int64_t)u * blockDim.x < hi;
                     uint32_t slot;
                     uint32_t v[F];
-                    item_unpack<F>(w[u], smask, bp.binshift, slot, v);
+                    item_unpack<F>(w[u], slot, v);
 #pragma unroll
                     for (int f = 0; f < F; ++f)
-                        val_accumulate(ok ? v[f] : 0u, &big[f * slots + slot], &small[f * slots + slot]);
+                        val_accumulate(ok ? v[f] : 0u, k0, &big[f * slots + slot], &small[f * slots + slot]);
                 }
             };
             // the rounds alternate between the two buffers (unrolled by two);
@@ -1357,7 +1387,7 @@ int snake_hashgrid_bwd(const snake_grid_desc *gd, int32_t K, const float *pos, c
     bin_count_kernel<FF><<<nblk, 256, 0, st>>>(g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.lmax,     \
                                                w.counts);                                                  \
     scan::launch_scan(w.counts, ncnt, w.bsum, w.offsets, 1, nullptr, w.item_cap, w.n_items, err, st);   \
-    bin_scatter_kernel<FF><<<nblk, ScatterShape<FF>::threads, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>(                     \
+    bin_scatter_kernel<FF><<<nblk, ScatterShape<FF>::threads, scatter_lds_bytes(bp.nb, bp.nbpl, FF), st>>>( \
         g, bp, pos, tile_id, sample_idx, n, n_dev, dfeat, w.offsets, w.counts, w.lmax, w.items, w.item_cap); \
     bin_reduce_kernel<FF><<<rgrid, kReduceThreads, 0, st>>>(bp, w.offsets, nblk, w.n_items, w.items, w.lmax, w.acc64); \
     bin_convert_kernel<FF><<<cgrid, 256, 0, st>>>(bp, g.L, w.acc64, w.lmax, K, dtable)
