@@ -446,11 +446,13 @@ def convergence(args):
     """The three forms at equal step count on the full-tile scene: each trains
     from the same initial table and networks on the same cycle of ray batches;
     the held-out ninth view (256^2 rays) is then rendered and its PSNR against
-    the scene's own rendering compared (early stop only), as means over
-    --conv-orders orders of the batch cycle.  With the occupancy grid on, one
-    more run of the reported form trains with culling (grid refreshed every 16
-    steps from step --conv-occ-start) and gives culling's effect on PSNR and
-    on the step time."""
+    the scene's own rendering compared (early stop only).  The FP32 and BF16
+    forms run --conv-orders orders of the batch cycle, the BF16-table form
+    --conv-orders-t16, and the forms are compared by the median and the mean
+    over orders.  With the occupancy grid on, one more run of the reported
+    form trains with culling (grid refreshed every 16 steps from step
+    --conv-occ-start) and gives culling's effect on PSNR and on the step
+    time."""
     import torch
     import synth
     dev = "cuda:0"
@@ -466,11 +468,15 @@ def convergence(args):
     out = {"config": "full_tile, %d rays/step, %d steps, lr %g, batches cycled from %d, occupancy grid %s"
                      % (R, steps, wl.lr, nb, "%d^3 (optical thickness of one step > min(0.01, mean))" % G
                         if G else "off")}
-    # the trajectories are sensitive to last-bit changes, so the forms are
-    # compared over several orders of the batches (offsets of the cycle)
-    offsets = [0, 1, 3, 5, 2, 4, 6, 7][:max(1, args.conv_orders)]
+    # The trajectories are sensitive to last-bit changes: in about one batch
+    # order in eight either form settles in a worse basin (1.5-2 dB lower),
+    # so the forms the metric compares run over several orders (offsets of
+    # the batch cycle) and are compared by the median as well as the mean.
+    offsets = [0, 1, 2, 3, 4, 5, 6, 7][:max(1, args.conv_orders)]
     forms = ("fp32", "bf16", "bf16_t16")
-    runs = [(p, 0, o) for o in offsets for p in forms] + ([("bf16", G, 0)] if G else [])
+    n_off = {"fp32": len(offsets), "bf16": len(offsets), "bf16_t16": max(1, min(args.conv_orders_t16, len(offsets)))}
+    runs = [(p, 0, o) for o in offsets for p in forms if offsets.index(o) < n_off[p]] + \
+        ([("bf16", G, 0)] if G else [])
     for form, grid, off in runs:
         name = (form if grid == 0 else form + "_grid") + ("" if off == 0 else "_order%d" % off)
         nerf = make_nerf(wl, form, max(R, held[0].shape[0]), dev, occ_grid=grid)
@@ -483,19 +489,26 @@ def convergence(args):
         del nerf
 
     def psnrs(p):
-        return [out[p + ("" if o == 0 else "_order%d" % o)]["psnr_db"] for o in offsets]
+        return [out[p + ("" if o == 0 else "_order%d" % o)]["psnr_db"] for o in offsets[:n_off[p]]]
     out["orders"] = offsets
     for p in forms:
         v = psnrs(p)
+        med = float(np.median(v))
+        out["psnr_%s_db" % p] = v
         out["psnr_%s_mean_db" % p] = round(float(np.mean(v)), 3)
+        out["psnr_%s_median_db" % p] = round(med, 3)
         out["psnr_%s_spread_db" % p] = round(float(np.max(v) - np.min(v)), 3)
+        out["%s_runs_1db_below_median" % p] = int(sum(x < med - 1.0 for x in v))
     gaps = [b - a for a, b in zip(psnrs("fp32"), psnrs("bf16"))]
     out["psnr_gap_db"] = round(out["psnr_bf16_mean_db"] - out["psnr_fp32_mean_db"], 3)
+    out["psnr_gap_median_db"] = round(out["psnr_bf16_median_db"] - out["psnr_fp32_median_db"], 3)
     out["psnr_gap_per_order_db"] = [round(x, 3) for x in gaps]
-    out["psnr_gap_t16_db"] = round(out["psnr_bf16_t16_mean_db"] - out["psnr_fp32_mean_db"], 3)
-    out["within_0p1_db"] = bool(out["psnr_gap_db"] >= -0.1)
+    out["psnr_gap_t16_db"] = round(out["psnr_bf16_t16_mean_db"] - float(np.mean(psnrs("fp32")[:n_off["bf16_t16"]])), 3)
+    out["within_0p1_db"] = bool(out["psnr_gap_median_db"] >= -0.1)
+    out["within_0p1_db_mean"] = bool(out["psnr_gap_db"] >= -0.1)
     if G:
         out["culling_psnr_delta_db"] = round(out["bf16_grid"]["psnr_db"] - out["bf16"]["psnr_db"], 3)
+        out["culling_psnr_vs_bf16_median_db"] = round(out["bf16_grid"]["psnr_db"] - out["psnr_bf16_median_db"], 3)
         out["culling_speedup"] = round(out["bf16"]["ms_per_step"] / out["bf16_grid"]["ms_per_step"], 3)
     return out
 
@@ -513,11 +526,14 @@ def atomic_convergence(args):
     ho, hd, ht, hs = synth.full_tile_heldout(wl, 256)
     pool = [torch.as_tensor(x).to(dev) for x in (wl.rays_o, wl.rays_d, wl.target, wl.sun)]
     held = [torch.as_tensor(x).to(dev) for x in (ho, hd, ht, hs)]
-    out = {"config": "full_tile, bf16 form, %d rays/step, %d steps" % (R, steps)}
+    out = {"config": "full_tile, bf16 form, %d rays/step, %d steps, batch orders 0..%d"
+                     % (R, steps, max(1, args.atomic_orders) - 1)}
     from paper_2507_01631_amd import _lib as L
-    for mode in ("binned", "atomic"):
+    runs = [(m, o) for o in range(max(1, args.atomic_orders)) for m in ("binned", "atomic")]
+    for mode, off in runs:
+        name = mode + ("" if off == 0 else "_order%d" % off)
         nerf = make_nerf(wl, "bf16", max(R, held[0].shape[0]), dev, hash_bwd=mode)
-        dt, kept = _train(nerf, pool, R, nb, steps, 0, "adjoint_" + mode)
+        dt, kept = _train(nerf, pool, R, nb, steps, off, "adjoint_" + name)
         # one timed adjoint call on the last step's feature gradients
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         idx = nerf.alive_idx if nerf.early_stop > 0 else None
@@ -531,11 +547,14 @@ def atomic_convergence(args):
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         nerf.g_t.zero_()
-        out[mode] = {"psnr_db": round(_heldout_psnr(nerf, held), 3), "ms_per_step": round(1e3 * dt / steps, 3),
+        out[name] = {"psnr_db": round(_heldout_psnr(nerf, held), 3), "ms_per_step": round(1e3 * dt / steps, 3),
                      "adjoint_ms": round(float(np.median(ms)), 3), "samples_last_step": kept}
-        log("  adjoint %s: %s" % (mode, json.dumps(out[mode])))
+        log("  adjoint %s: %s" % (name, json.dumps(out[name])))
         del nerf
-    out["psnr_binned_minus_atomic_db"] = round(out["binned"]["psnr_db"] - out["atomic"]["psnr_db"], 3)
+    gaps = [out["binned" + sfx]["psnr_db"] - out["atomic" + sfx]["psnr_db"]
+            for sfx in [""] + ["_order%d" % o for o in range(1, max(1, args.atomic_orders))]]
+    out["psnr_binned_minus_atomic_per_order_db"] = [round(x, 3) for x in gaps]
+    out["psnr_binned_minus_atomic_db"] = round(float(np.mean(gaps)), 3)
     return out
 
 
@@ -650,8 +669,10 @@ def main():
     ap.add_argument("--convergence-steps", type=int, default=500,
                     help="also train FP32 and BF16 this many steps and compare held-out PSNR")
     ap.add_argument("--conv-rays", type=int, default=1 << 17)
-    ap.add_argument("--conv-orders", type=int, default=2,
-                    help="batch orders each form trains on in the convergence leg (PSNR means compared)")
+    ap.add_argument("--conv-orders", type=int, default=6,
+                    help="batch orders for the FP32 and BF16 forms")
+    ap.add_argument("--conv-orders-t16", type=int, default=2, help="batch orders for the BF16-table form")
+    ap.add_argument("--atomic-orders", type=int, default=2)
     ap.add_argument("--conv-occupancy", type=int, default=1,
                     help="add a BF16 convergence run with a 128^3 occupancy grid")
     ap.add_argument("--conv-occ-start", type=int, default=256, help="first step that updates the grid")
