@@ -250,6 +250,112 @@ def test_autograd_function_matches_oracle_and_fd(orc):
     assert bad <= 2
 
 
+@pytest.mark.timeout(900)
+def test_fd_full_tile_shapes_2e16_rays(orc):
+    """Full-tile shapes (L=16, T=2^19, 128 samples in the band, early stop,
+    21->64->64->4 colour net) at 2^16 rays: the adjoint chain behind the
+    autograd function against central differences (h = 1e-3) of the FP64
+    oracle's loss, early-stop counts held at the GPU's.  256 hash entries, each
+    on its own: an entry enters only the samples whose corners hit it, so its
+    difference is taken over the rays holding those samples (every other ray's
+    loss does not depend on it).  256 network weights, which every sample
+    sees: in 8 random-sign directions of 32 weights, one central difference of
+    the whole loss per direction against the adjoint's projection on it."""
+    from paper_2507_01631_amd import SnakeTileStep, level_resolutions
+    w = synth.full_tile(seed=11, n_rays=1 << 16)
+    rng = np.random.default_rng(12)
+    w.table = rng.uniform(-0.5, 0.5, size=w.table.shape).astype(np.float32)
+    R = w.n_rays
+    nerf = make_nerf(w)
+    table = nerf.table.requires_grad_(True)
+    params = nerf.params.requires_grad_(True)
+    loss = SnakeTileStep.apply(table, params, nerf, dev(w.rays_o), dev(w.rays_d), dev(w.target), dev(w.sun))
+    loss.backward()
+    sync()
+    gt, gw = host(table.grad).ravel(), host(params.grad)
+    alive = host(nerf.n_alive)[:R]
+    g, m = w.grid, w.mlp
+    res = level_resolutions(g.n_levels, g.res_min, g.res_max)
+    S = int(w.samples_per_ray)
+
+    def sample(sel):
+        return orc.sample_segmented(w.rays_o[sel], w.rays_d[sel], w.boxes, S, zband=w.zband)
+
+    def loss_of(s, sel, tab, par, feat=None):
+        if feat is None:
+            feat = orc.hashgrid_fwd(res, g.log2_table, tab, s["pos"], s["tile_id"], g.out_width)
+        sg, c = orc.mlp_fwd(m, par, feat, s["view"], s["ray_id"], sun=w.sun[sel])
+        return orc.composite_fwd(s["packed_info"], sg, c, s["t0"], s["t1"], w.target[sel], 1.0 / (3 * R),
+                                 early_stop=w.early_stop, alive=alive[sel])["loss"]
+
+    allr = np.arange(R)
+    s_all = sample(allr)
+    feat_all = orc.hashgrid_fwd(res, g.log2_table, w.table, s_all["pos"], s_all["tile_id"], g.out_width)
+    base = loss_of(s_all, allr, w.table, w.mlp_params, feat_all)
+    assert abs(float(loss.detach()) - base) <= 1e-5 * base
+    print("kept samples %d of %d" % (int(alive.sum()), s_all["n"]))
+
+    # --- 256 hash entries on the hashed levels (a densely indexed coarse
+    # level's entry is seen by too many rays for a per-entry difference)
+    K, L, T, F = w.table.shape
+    hashed = [l for l in range(L) if (res[l] + 1) ** 3 > T]
+    flat = np.arange(gt.size).reshape(w.table.shape)
+    cand = np.concatenate([flat[0, l].ravel() for l in hashed])
+    cand = cand[np.abs(gt[cand]) > 1e-2 * np.abs(gt).max()]
+    pick = np.sort(rng.choice(cand, size=256, replace=False))
+    lvl_of = (pick // (T * F)) % L
+    slot_of = (pick // F) % T
+    # the rays holding a sample whose corners hit each picked entry
+    rays_of = {int(p): set() for p in pick}
+    step = 1 << 20
+    for a in range(0, s_all["n"], step):
+        b = min(a + step, s_all["n"])
+        _, idx = orc.hashgrid_fwd(res, g.log2_table, w.table, s_all["pos"][a:b], s_all["tile_id"][a:b],
+                                  g.out_width, return_index=True)
+        rid = s_all["ray_id"][a:b]
+        for l in np.unique(lvl_of):
+            sel_p = pick[lvl_of == l]
+            slots = slot_of[lvl_of == l]
+            hit = np.isin(idx[:, l, :], slots)
+            rows, cols = np.nonzero(hit)
+            for r_, c_ in zip(rows, cols):
+                sl = idx[r_, l, c_]
+                for p in sel_p[slots == sl]:
+                    rays_of[int(p)].add(int(rid[r_]))
+    bad, worst = 0, 0.0
+    gmax = np.abs(gt).max()
+    for p in pick:
+        sel = np.array(sorted(rays_of[int(p)]), dtype=np.int64)
+        assert sel.size > 0
+        s = sample(sel)
+        tp, tm = w.table.copy().ravel(), w.table.copy().ravel()
+        tp[p] += np.float32(1e-3)
+        tm[p] -= np.float32(1e-3)
+        fd = (loss_of(s, sel, tp.reshape(w.table.shape), w.mlp_params)
+              - loss_of(s, sel, tm.reshape(w.table.shape), w.mlp_params)) / float(tp[p] - tm[p])
+        err = abs(fd - gt[p])
+        worst = max(worst, err / gmax)
+        bad += err > 2e-3 * gmax + 1e-2 * abs(fd)
+    print("hash entries: %d of 256 outside the bar, worst |fd - g| / max|g| = %.2e" % (bad, worst))
+    assert bad <= 8
+
+    # --- 256 network weights in 8 directions of 32
+    candw = np.nonzero(np.abs(gw) > 1e-3 * np.abs(gw).max())[0]
+    pw = rng.choice(candw, size=256, replace=False).reshape(8, 32)
+    bad = 0
+    for grp in pw:
+        v = rng.choice([-1.0, 1.0], size=grp.size).astype(np.float32)
+        wp, wm = w.mlp_params.copy(), w.mlp_params.copy()
+        wp[grp] += np.float32(1e-3) * v
+        wm[grp] -= np.float32(1e-3) * v
+        fd = loss_of(s_all, allr, w.table, wp, feat_all) - loss_of(s_all, allr, w.table, wm, feat_all)
+        proj = float(np.dot(gw[grp].astype(np.float64), (wp[grp] - wm[grp]).astype(np.float64)))
+        scale = float(np.dot(np.abs(gw[grp]).astype(np.float64), np.abs(wp[grp] - wm[grp]).astype(np.float64)))
+        bad += abs(fd - proj) > 2e-3 * scale + 1e-2 * abs(fd)
+    print("network weights: %d of 8 directions outside the bar" % bad)
+    assert bad <= 1
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_full_size_sampled(orc, prec):
