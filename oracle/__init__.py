@@ -317,6 +317,61 @@ def cull_samples(smp, occupied, G):
     return out
 
 
+def refine_samples(rays_o, rays_d, boxes, budget, kept):
+    """Density-driven sampling after culling (Sec. 4.1: the coarse grid's
+    occupancy gives each ray segment its sample density).  A ray whose culled
+    set ``kept`` (a sampler-like dict, e.g. from cull_samples) holds c > 0
+    intervals spends its whole budget B (``budget[r]``, its sample count
+    before culling) on them: interval i gets e(i+1) - e(i) equal
+    sub-intervals, e(i) = floor((2 B i + c) / (2 c)) (B i / c rounded, halves
+    up), so the sample density rises where the grid is occupied.  A ray with
+    nothing kept gets no samples.  Sub-interval k of q in [ta, tb] is
+    [ta + k h, ta + (k+1) h] with h = (tb - ta) / q (the last one ends at tb),
+    and its sample sits at the midpoint, mapped into its tile's frame
+    ((o - lo) / ext + m d / ext, clamped to [0, 1]) -- the sampler's own FP32
+    rounding points, evaluated one operation at a time here."""
+    rays_o = np.asarray(rays_o, dtype=np.float64).reshape(-1, 3)
+    rays_d = np.asarray(rays_d, dtype=np.float64).reshape(-1, 3)
+    boxes = np.asarray(boxes, dtype=np.float64).reshape(-1, 6)
+    budget = np.asarray(budget, dtype=np.int64)
+    info = np.asarray(kept["packed_info"], dtype=np.int64)
+    R = info.shape[0]
+    t0o, t1o, poso, rido, tido = [], [], [], [], []
+    counts = np.zeros(R, dtype=np.int32)
+    f32 = np.float32
+    for r in range(R):
+        s0, c = int(info[r, 0]), int(info[r, 1])
+        B = int(budget[r]) if c > 0 else 0
+        counts[r] = B
+        if B == 0:
+            continue
+        e = [(2 * B * i + c) // (2 * c) for i in range(c + 1)]
+        for i in range(c):
+            q = e[i + 1] - e[i]
+            ta, tb = f32(kept["t0"][s0 + i]), f32(kept["t1"][s0 + i])
+            tile = int(kept["tile_id"][s0 + i]) if kept.get("tile_id") is not None else 0
+            box = boxes[tile]
+            ol = [f32((rays_o[r, a] - box[a]) / (box[3 + a] - box[a])) for a in range(3)]
+            dl = [f32(rays_d[r, a] / (box[3 + a] - box[a])) for a in range(3)]
+            h = f32(f32(tb - ta) / f32(q))
+            for k in range(q):
+                a_ = f32(ta + f32(f32(k) * h))
+                b_ = tb if k + 1 == q else f32(ta + f32(f32(k + 1) * h))
+                m = f32(f32(0.5) * f32(a_ + b_))
+                x = [min(max(f32(ol[a] + f32(m * dl[a])), f32(0.0)), f32(1.0)) for a in range(3)]
+                t0o.append(a_)
+                t1o.append(b_)
+                poso.append(x)
+                rido.append(r)
+                tido.append(tile)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int32)
+    n = int(counts.sum())
+    return dict(packed_info=np.stack([starts, counts], 1).astype(np.int32), n=n,
+                t0=np.asarray(t0o, dtype=np.float32), t1=np.asarray(t1o, dtype=np.float32),
+                pos=np.asarray(poso, dtype=np.float32).reshape(n, 3), ray_id=np.asarray(rido, dtype=np.int32),
+                tile_id=np.asarray(tido, dtype=np.uint8), view=kept.get("view"))
+
+
 # ---------------------------------------------------------------------------
 # volume rendering
 # ---------------------------------------------------------------------------

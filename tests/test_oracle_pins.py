@@ -877,6 +877,69 @@ def test_occupancy_cells_and_culling(orc):
     assert np.allclose(d, [0.01, 0.03, 0.1]) and o.tolist() == [False, True, True]
 
 
+def test_refine_samples(orc):
+    """Density-driven sampling after culling.  With every cell occupied the
+    refinement is the uniform sampler itself, bit for bit (each kept interval
+    gets exactly one sample at its own midpoint), which pins its position
+    mapping to the sampler's.  With a partial grid every ray that keeps
+    anything spends exactly its budget, each kept interval gets floor(B/c) or
+    ceil(B/c) sub-intervals that tile it exactly (first starts at ta, last
+    ends at tb, no gaps), every sample lies in its interval, and a ray that
+    keeps nothing gets none.  Worked split: budget 5 over 2 intervals gives
+    3 and 2; budget 7 over 3 gives 2, 3, 2."""
+    G = 16
+    w = synth.tiny_tile(seed=11, n_rays=120, samples=40)
+    smp = orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 40)
+    budget = smp["packed_info"][:, 1]
+    allon = orc.cull_samples(smp, np.ones(G ** 3, dtype=bool), G)
+    ref = orc.refine_samples(w.rays_o, w.rays_d, w.boxes, budget, allon)
+    assert ref["n"] == smp["n"] and np.array_equal(ref["packed_info"], smp["packed_info"])
+    for k in ("t0", "t1", "pos", "ray_id", "tile_id"):
+        assert np.array_equal(ref[k], smp[k]), k
+    rng = np.random.default_rng(13)
+    occ = rng.random(G ** 3) < 0.3
+    cu = orc.cull_samples(smp, occ, G)
+    ref = orc.refine_samples(w.rays_o, w.rays_d, w.boxes, budget, cu)
+    kept_any = cu["packed_info"][:, 1] > 0
+    assert kept_any.any() and np.any(cu["packed_info"][:, 1] < budget)
+    assert np.array_equal(ref["packed_info"][:, 1], np.where(kept_any, budget, 0))
+    for r in range(120):
+        s, c = cu["packed_info"][r]
+        s2, n2 = ref["packed_info"][r]
+        if c == 0:
+            assert n2 == 0
+            continue
+        t0, t1 = ref["t0"][s2:s2 + n2], ref["t1"][s2:s2 + n2]
+        assert np.all(ref["ray_id"][s2:s2 + n2] == r)
+        # walk the kept intervals: each is tiled by floor/ceil(B/c) sub-intervals
+        j = 0
+        for i in range(c):
+            ta, tb = cu["t0"][s + i], cu["t1"][s + i]
+            q = 0
+            while j + q < n2 and t0[j + q] >= ta and t1[j + q] <= tb:
+                q += 1
+            assert q in (n2 // c, -(-n2 // c)), (r, i, q)
+            assert t0[j] == ta and t1[j + q - 1] == tb
+            assert np.all(t1[j:j + q - 1] == t0[j + 1:j + q])
+            assert np.all(t0[j:j + q] < t1[j:j + q])
+            j += q
+        assert j == n2
+    assert np.all((ref["pos"] >= 0.0) & (ref["pos"] <= 1.0))
+    # worked splits on a single ray with hand-made intervals
+    ray_o, ray_d = np.array([[0.5, 0.5, 2.0]]), np.array([[0.0, 0.0, -1.0]])
+    box = np.array([[0.0, 0.0, 0.0, 1.0, 1.0, 1.0]])
+    for B, ivals, want in ((5, [(1.0, 1.2), (1.5, 1.6)], [3, 2]), (7, [(1.0, 1.1), (1.2, 1.3), (1.4, 1.5)], [2, 3, 2])):
+        c = len(ivals)
+        kept = dict(packed_info=np.array([[0, c]], dtype=np.int32),
+                    t0=np.array([a for a, _ in ivals], dtype=np.float32),
+                    t1=np.array([b for _, b in ivals], dtype=np.float32), tile_id=np.zeros(c, dtype=np.uint8))
+        out = orc.refine_samples(ray_o, ray_d, box, np.array([B]), kept)
+        got = [int(np.sum((out["t0"] >= np.float32(a)) & (out["t1"] <= np.float32(b)))) for a, b in ivals]
+        assert got == want
+        # the ray falls straight down through the box centre: z = 2 - t, clamped
+        assert np.allclose(out["pos"][:, :2], 0.5) and np.allclose(out["pos"][:, 2], np.clip(2.0 - 0.5 * (out["t0"] + out["t1"]), 0, 1), atol=1e-6)
+
+
 def test_occupancy_mean_cap(orc):
     """Mean cap: with every cell below the threshold, exactly the cells above
     the mean stay occupied; with the mean above the threshold the cap is
