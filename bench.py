@@ -449,10 +449,11 @@ def convergence(args):
     the scene's own rendering compared (early stop only).  The FP32 and BF16
     forms run --conv-orders orders of the batch cycle, the BF16-table form
     --conv-orders-t16, and the forms are compared by the median and the mean
-    over orders.  With the occupancy grid on, one more run of the reported
-    form trains with culling (grid refreshed every 16 steps from step
-    --conv-occ-start) and gives culling's effect on PSNR and on the step
-    time."""
+    over orders.  With the occupancy grid on, two more runs of the reported
+    form train with culling (grid refreshed every 16 steps from step
+    --conv-occ-start), the second also spending each ray's whole sample
+    budget on its kept intervals, and give their effect on PSNR and on the
+    step time."""
     import torch
     import synth
     dev = "cuda:0"
@@ -475,11 +476,12 @@ def convergence(args):
     offsets = [0, 1, 2, 3, 4, 5, 6, 7][:max(1, args.conv_orders)]
     forms = ("fp32", "bf16", "bf16_t16")
     n_off = {"fp32": len(offsets), "bf16": len(offsets), "bf16_t16": max(1, min(args.conv_orders_t16, len(offsets)))}
-    runs = [(p, 0, o) for o in offsets for p in forms if offsets.index(o) < n_off[p]] + \
-        ([("bf16", G, 0)] if G else [])
-    for form, grid, off in runs:
-        name = (form if grid == 0 else form + "_grid") + ("" if off == 0 else "_order%d" % off)
-        nerf = make_nerf(wl, form, max(R, held[0].shape[0]), dev, occ_grid=grid)
+    runs = [(p, 0, o, False) for o in offsets for p in forms if offsets.index(o) < n_off[p]] + \
+        ([("bf16", G, 0, False), ("bf16", G, 0, True)] if G else [])
+    for form, grid, off, refine in runs:
+        name = (form if grid == 0 else form + ("_grid_refine" if refine else "_grid")) + \
+            ("" if off == 0 else "_order%d" % off)
+        nerf = make_nerf(wl, form, max(R, held[0].shape[0]), dev, occ_grid=grid, occ_refine=refine)
         dt, kept = _train(nerf, pool, R, nb, steps, off, name, args.conv_occ_start if grid else None)
         out[name] = {"psnr_db": round(_heldout_psnr(nerf, held), 3), "train_s": round(dt, 3),
                      "ms_per_step": round(1e3 * dt / steps, 3), "samples_last_step": kept}
@@ -510,6 +512,11 @@ def convergence(args):
         out["culling_psnr_delta_db"] = round(out["bf16_grid"]["psnr_db"] - out["bf16"]["psnr_db"], 3)
         out["culling_psnr_vs_bf16_median_db"] = round(out["bf16_grid"]["psnr_db"] - out["psnr_bf16_median_db"], 3)
         out["culling_speedup"] = round(out["bf16"]["ms_per_step"] / out["bf16_grid"]["ms_per_step"], 3)
+        # the grid also setting each segment's sample density (the ray's whole
+        # budget spent on its kept intervals)
+        out["refine_psnr_delta_db"] = round(out["bf16_grid_refine"]["psnr_db"] - out["bf16"]["psnr_db"], 3)
+        out["refine_psnr_vs_bf16_median_db"] = round(out["bf16_grid_refine"]["psnr_db"] - out["psnr_bf16_median_db"], 3)
+        out["refine_speedup"] = round(out["bf16"]["ms_per_step"] / out["bf16_grid_refine"]["ms_per_step"], 3)
     return out
 
 

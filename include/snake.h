@@ -269,6 +269,30 @@ int snake_tile_partition(const uint8_t *tile_id, const float *pos, const int32_t
  * Culled intervals then add no optical depth to the quadrature.
  * Workspace: snake_cull_workspace_bytes(R).
  */
+/*
+ * snake_sample_refine gives each ray segment its sample density from the
+ * grid (Sec. 4.1: the coarse grid's voxel density provides the sample
+ * density of each ray segment).  After culling, a ray that kept c > 0 of its
+ * samples spends its whole budget B -- its sample count before culling,
+ * packed_info_all[r][1] -- on the kept intervals: interval i is split into
+ * e(i+1) - e(i) equal sub-intervals, e(i) = floor((2 B i + c) / (2 c)) (so
+ * each gets floor(B/c) or ceil(B/c)), with its sample at the sub-interval's
+ * midpoint; a ray that kept nothing gets no samples.  Inputs: the rays and
+ * boxes of the sampler call (FP64, device rays, host boxes [K][6]), the
+ * sampler's packed_info_all [R][2] and the culled packed_info_kept [R][2],
+ * t0_kept / t1_kept / tile_id_kept (tile_id_kept may be NULL when K == 1).
+ * Outputs as for snake_sample_segmented (packed_info [R][2], t0, t1, pos
+ * [n][3] in the tile frame, ray_id, tile_id (may be NULL), up to cap
+ * samples, *n_out on the device; SNAKE_DEVERR_CAPACITY past cap).  Bounds and
+ * positions use the sampler's FP32 rounding points, so with every interval
+ * kept the result equals the sampler's.  Workspace:
+ * snake_sample_workspace_bytes(R).
+ */
+int snake_sample_refine(const double *rays_o, const double *rays_d, int32_t R, const double *boxes, int32_t K,
+                        const int32_t *packed_info_all, const int32_t *packed_info_kept, const float *t0_kept,
+                        const float *t1_kept, const uint8_t *tile_id_kept, int32_t *packed_info, float *t0,
+                        float *t1, float *pos, int32_t *ray_id, uint8_t *tile_id, int64_t cap, int64_t *n_out,
+                        void *workspace, size_t workspace_bytes, snake_stream_t stream);
 int snake_occupancy_cells(int32_t G, int32_t K, float *pos, uint8_t *tile_id, snake_stream_t stream);
 #define SNAKE_OCC_MEAN_CAP 1u          /* threshold capped at the mean density */
 size_t snake_occupancy_workspace_bytes(int64_t n_cells);

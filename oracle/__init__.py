@@ -420,7 +420,7 @@ def adam_step(p, g, m, v, lr, step, b1=0.9, b2=0.99, eps=1e-15, l2=0.0):
 # one training step, composed in the paper's order
 # ---------------------------------------------------------------------------
 def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=1,
-               alive=None, rays=None, timings=None, occupancy=None, bf16=False):
+               alive=None, rays=None, timings=None, occupancy=None, bf16=False, refine=False):
     """One step of the tile-NeRF: segmented sampling -> hash encoding -> density
     and colour nets -> volume rendering + MSE loss -> adjoints -> Adam.
 
@@ -452,7 +452,9 @@ def train_step(wl, res=None, table=None, mlp_params=None, adam_state=None, step=
                                samples_per_ray=np.asarray(spr, dtype=np.int32))
     if occupancy is not None:          # (G, occupied cells): SAT-NGP culling before the field
         out["sample_raw"] = smp
-        smp = cull_samples(smp, occupancy[1], occupancy[0])
+        kept = cull_samples(smp, occupancy[1], occupancy[0])
+        # with refine, each ray's budget goes to the intervals it kept
+        smp = refine_samples(rays_o, rays_d, wl.boxes, smp["packed_info"][:, 1], kept) if refine else kept
     out["sample"] = smp
     table_fwd = bf16_round(table).astype(np.float32).reshape(table.shape) if bf16 else table
     feat = hashgrid_fwd(res, g.log2_table, table_fwd, smp["pos"], smp["tile_id"], g.out_width)

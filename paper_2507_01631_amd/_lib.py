@@ -39,7 +39,7 @@ EXPORTS = (
     "snake_sample_segmented_static", "snake_pack_alive",
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
     "snake_occupancy_cells", "snake_occupancy_workspace_bytes", "snake_occupancy_update",
-    "snake_cull_workspace_bytes", "snake_cull_samples",
+    "snake_cull_workspace_bytes", "snake_cull_samples", "snake_sample_refine",
     "snake_convert_bf16", "snake_hashgrid_fwd", "snake_hashgrid_bwd", "snake_hashgrid_bwd_workspace_bytes",
     "snake_mlp_param_count", "snake_mlp_weight_count", "snake_mlp_act_width", "snake_mlp_bwd_workspace_bytes", "snake_mlp_fwd",
     "snake_mlp_bwd",
@@ -110,6 +110,8 @@ _SIGS = {
     "snake_cull_workspace_bytes": ([_I32], _SZ),
     "snake_cull_samples": ([_I32, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
                             _SZ, _P], ctypes.c_int),
+    "snake_sample_refine": ([_P, _P, _I32, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _SZ,
+                             _P], ctypes.c_int),
     "snake_tile_partition": ([_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_convert_bf16": ([_P, _I64, _P, _P], ctypes.c_int),
     "snake_hashgrid_fwd": ([_P, _I32, _P, _P, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
@@ -292,6 +294,17 @@ def snake_cull_samples(G, bits, K, R, packed_info, t0, t1, pos, ray_id, tile_id,
                                   _ptr(n_out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                                   _stream(stream))
     _check("snake_cull_samples", rc)
+
+
+def snake_sample_refine(rays_o, rays_d, R, boxes, packed_info_all, packed_info_kept, t0_kept, t1_kept, tile_id_kept,
+                        packed_info, t0, t1, pos, ray_id, tile_id, cap, n_out, workspace, stream=None):
+    boxes = _host_f64(boxes).reshape(-1, 6)
+    rc = lib().snake_sample_refine(
+        _ptr(rays_o), _ptr(rays_d), int(R), boxes.ctypes.data, int(boxes.shape[0]), _ptr(packed_info_all),
+        _ptr(packed_info_kept), _ptr(t0_kept), _ptr(t1_kept), _ptr(tile_id_kept), _ptr(packed_info), _ptr(t0),
+        _ptr(t1), _ptr(pos), _ptr(ray_id), _ptr(tile_id), int(cap), _ptr(n_out), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream))
+    _check("snake_sample_refine", rc)
 
 
 def snake_convert_bf16(src, n, dst, stream=None):

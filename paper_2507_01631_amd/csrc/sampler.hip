@@ -284,6 +284,83 @@ __global__ __launch_bounds__(256) void accept_fill_kernel(const int32_t *__restr
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 
 // workspace: counts[R] | offs[R] | bsum[nb]
+// ---- density-driven refinement after culling (Sec. 4.1) ---------------------
+// A ray whose culled set holds c > 0 intervals spends its whole budget B (its
+// sample count before culling) on them: interval i gets e(i+1) - e(i) equal
+// sub-intervals, e(i) = floor((2 B i + c) / (2 c)); a ray that keeps nothing
+// gets no samples.  The sub-interval bounds and the midpoint's tile-frame
+// position use the fill kernel's rounding points.
+__global__ __launch_bounds__(256) void refine_count_kernel(const int32_t *__restrict__ info_all,
+                                                           const int32_t *__restrict__ info_kept, int R,
+                                                           int32_t *__restrict__ counts)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x)
+        counts[r] = info_kept[2 * (int64_t)r + 1] > 0 ? info_all[2 * (int64_t)r + 1] : 0;
+}
+
+__device__ __forceinline__ int64_t split_edge(int64_t B, int64_t c, int64_t i) { return (2 * B * i + c) / (2 * c); }
+
+// One wavefront per ray, one lane per refined sample.
+template <int KMAX>
+__global__ __launch_bounds__(256) void refine_fill_kernel(const double *__restrict__ ro, const double *__restrict__ rd,
+                                                          int R, Boxes bx, const int32_t *__restrict__ info_kept,
+                                                          const float *__restrict__ t0k, const float *__restrict__ t1k,
+                                                          const uint8_t *__restrict__ tilek,
+                                                          const int32_t *__restrict__ info, int64_t cap,
+                                                          float *__restrict__ t0, float *__restrict__ t1,
+                                                          float *__restrict__ pos, int32_t *__restrict__ ray_id,
+                                                          uint8_t *__restrict__ tile_id)
+{
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < R; r += waves) {
+        const int64_t sk = info_kept[2 * (int64_t)r];
+        const int64_t c = info_kept[2 * (int64_t)r + 1];
+        const int64_t start = info[2 * (int64_t)r];
+        const int64_t B = info[2 * (int64_t)r + 1];
+        if (B == 0 || c == 0) continue;
+        double o[3], d[3];
+        load_ray(ro, rd, r, o, d);
+        for (int64_t j = lane; j < B; j += 64) {
+            // the kept interval holding refined sample j: the last i with e(i) <= j
+            int64_t i = j * c / B;
+            while (i + 1 < c && split_edge(B, c, i + 1) <= j) ++i;
+            while (i > 0 && split_edge(B, c, i) > j) --i;
+            const int64_t e0 = split_edge(B, c, i);
+            const int64_t q = split_edge(B, c, i + 1) - e0, k = j - e0;
+            const float ta = t0k[sk + i], tb = t1k[sk + i];
+            const int tile = tilek ? tilek[sk + i] : 0;
+            double b[6] = {bx.b[0][0], bx.b[0][1], bx.b[0][2], bx.b[0][3], bx.b[0][4], bx.b[0][5]};
+#pragma unroll
+            for (int t = 1; t < KMAX; ++t)
+                if (tile == t) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) b[e] = bx.b[t][e];
+                }
+            const float h = (tb - ta) / (float)q;
+            const float ta2 = ta + (float)k * h;
+            const float tb2 = (k + 1 == q) ? tb : ta + (float)(k + 1) * h;
+            const float m = 0.5f * (ta2 + tb2);
+            const int64_t out = start + j;
+            if (out >= cap) continue;
+            t0[out] = ta2;
+            t1[out] = tb2;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double ext = b[3 + a] - b[a];
+                const float ol = (float)((o[a] - b[a]) / ext);
+                const float dl = (float)(d[a] / ext);
+                float x = ol + m * dl;
+                x = x < 0.0f ? 0.0f : x;
+                x = x > 1.0f ? 1.0f : x;
+                pos[3 * out + a] = x;
+            }
+            ray_id[out] = r;
+            if (tile_id) tile_id[out] = (uint8_t)tile;
+        }
+    }
+}
+
 struct ScanWs {
     int32_t *counts, *offs;
     int64_t *bsum;
@@ -446,6 +523,59 @@ int snake_sample_segmented_static(const double *rays_o, const double *rays_d, in
     if (!ws) return SNAKE_ERR_HIP;
     return sample_impl(__func__, rays_o, rays_d, R, boxes, K, zband, samples_per_ray, S, max_count, packed_info, t0,
                        t1, pos, ray_id, tile_id, view, cap, n_out, ws, kStaticScratchBytes, stream);
+}
+
+int snake_sample_refine(const double *rays_o, const double *rays_d, int32_t R, const double *boxes, int32_t K,
+                        const int32_t *packed_info_all, const int32_t *packed_info_kept, const float *t0_kept,
+                        const float *t1_kept, const uint8_t *tile_id_kept, int32_t *packed_info, float *t0,
+                        float *t1, float *pos, int32_t *ray_id, uint8_t *tile_id, int64_t cap, int64_t *n_out,
+                        void *workspace, size_t workspace_bytes, snake_stream_t stream)
+{
+    const char *fn = __func__;
+    SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "%s: R = %d < 0", fn, R);
+    SNAKE_REQUIRE(K >= 1 && K <= kMaxTiles, SNAKE_ERR_INVALID_ARG, "%s: K = %d not in [1, %d]", fn, K, kMaxTiles);
+    SNAKE_REQUIRE(K == 1 || tile_id_kept != nullptr, SNAKE_ERR_NULL, "%s: tile_id_kept is NULL with K = %d > 1", fn,
+                  K);
+    SNAKE_REQUIRE(cap >= 0 && cap <= INT32_MAX, SNAKE_ERR_INVALID_ARG, "%s: cap = %lld not in [0, 2^31)", fn,
+                  (long long)cap);
+    SNAKE_REQUIRE(boxes != nullptr && n_out != nullptr, SNAKE_ERR_NULL, "%s: boxes or n_out is NULL", fn);
+    SNAKE_REQUIRE(R == 0 || (rays_o && rays_d && packed_info_all && packed_info_kept && t0_kept && t1_kept &&
+                             packed_info),
+                  SNAKE_ERR_NULL, "%s: an input array or packed_info is NULL", fn);
+    SNAKE_REQUIRE(cap == 0 || (t0 && t1 && pos && ray_id), SNAKE_ERR_NULL, "%s: t0, t1, pos or ray_id is NULL", fn);
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= scan_ws_bytes(R), SNAKE_ERR_WORKSPACE,
+                  "%s: workspace needs %zu bytes", fn, scan_ws_bytes(R));
+    SNAKE_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % 256 == 0, SNAKE_ERR_ALIGN,
+                  "%s: workspace is not 256-byte aligned", fn);
+    Boxes bx{};
+    bx.K = K;
+    for (int k = 0; k < K; ++k) {
+        for (int a = 0; a < 6; ++a) bx.b[k][a] = boxes[6 * k + a];
+        for (int a = 0; a < 3; ++a)
+            SNAKE_REQUIRE(bx.b[k][3 + a] > bx.b[k][a], SNAKE_ERR_INVALID_ARG, "%s: box %d is empty on axis %d", fn,
+                          k, a);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (R == 0) {
+        set_i64_kernel<<<1, 1, 0, st>>>(n_out, 0);
+        return launch_status(fn);
+    }
+    ScanWs w = carve(workspace, R);
+    const unsigned gc = grid_for(R, 256, 8), gf = grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU));
+    refine_count_kernel<<<gc, 256, 0, st>>>(packed_info_all, packed_info_kept, R, w.counts);
+    launch_scan(w, R, packed_info, 2, packed_info + 1, cap, n_out, st);
+#define SNAKE_REFINE_LAUNCH(KM)                                                                                  \
+    refine_fill_kernel<KM><<<gf, 256, 0, st>>>(rays_o, rays_d, R, bx, packed_info_kept, t0_kept, t1_kept,      \
+                                               tile_id_kept, packed_info, cap, t0, t1, pos, ray_id, tile_id)
+    if (K == 1) {
+        SNAKE_REFINE_LAUNCH(1);
+    } else if (K <= 4) {
+        SNAKE_REFINE_LAUNCH(4);
+    } else {
+        SNAKE_REFINE_LAUNCH(kMaxTiles);
+    }
+#undef SNAKE_REFINE_LAUNCH
+    return launch_status(fn);
 }
 
 int snake_pack_alive(const int32_t *packed_info, const int32_t *n_alive, int32_t R, int32_t *idx_out,

@@ -50,7 +50,8 @@ class TileNeRF:
                  boxes, zband=None, samples=64, early_stop=0.0, precision="fp32",
                  table=None, mlp_params=None, max_rays=4096, lr=1e-2, betas=(0.9, 0.99),
                  eps=1e-15, hash_bwd="binned", hash_ws_gib=24.0, recompute=True, occ_grid=0,
-                 occ_decay=0.95, occ_threshold=0.01, occ_mean_cap=True, table_bf16=None, device="cuda"):
+                 occ_decay=0.95, occ_threshold=0.01, occ_mean_cap=True, occ_refine=False, table_bf16=None,
+                 device="cuda"):
         self.device = torch.device(device)
         self.res = [int(r) for r in res]
         self.F = int(n_features)
@@ -104,7 +105,10 @@ class TileNeRF:
         # of one nominal sample step (band height / samples, unit-length rays) at
         # the cell centres; a cell is occupied while that exceeds occ_threshold,
         # capped at the grid's mean when occ_mean_cap is set.
+        # occ_refine: after culling, each ray spends its whole sample budget on
+        # the intervals it kept (the grid sets each segment's sample density)
         self.G = int(occ_grid)
+        self.occ_refine = bool(occ_refine) and self.G > 0
         self.occ_decay, self.occ_threshold = float(occ_decay), float(occ_threshold)
         self.occ_flags = L.SNAKE_OCC_MEAN_CAP if occ_mean_cap else 0
         b = self.boxes
@@ -174,6 +178,10 @@ class TileNeRF:
                             tile_id=torch.empty(cap, dtype=torch.uint8, device=dev) if self.K > 1 else None,
                             n=torch.zeros(1, dtype=i64, device=dev))
             self.ws_cull = torch.empty(L.snake_cull_workspace_bytes(R), dtype=torch.uint8, device=dev)
+            if self.occ_refine:
+                # culling packs the kept intervals here; the refinement writes
+                # the arrays the rest of the step reads
+                self.kept = {k: torch.empty_like(v) if v is not None else None for k, v in self.raw.items()}
         self.ws_hash = None
         if self.hash_bwd == "binned":
             # as many levels per pass as fit in the budget (at least one)
@@ -201,9 +209,18 @@ class TileNeRF:
         L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S, None,
                                  r["packed_info"], r["t0"], r["t1"], r["pos"], r["ray_id"], r["tile_id"], self.view,
                                  self.cap, r["n"], self.ws_sample, stream)
+        if not self.occ_refine:
+            L.snake_cull_samples(self.G, self.occ_bits, self.K, R, r["packed_info"], r["t0"], r["t1"], r["pos"],
+                                 r["ray_id"], r["tile_id"], self.packed_info, self.t0, self.t1, self.pos, self.ray_id,
+                                 self.tile_id, self.cap, self.n_out, self.ws_cull, stream)
+            return
+        k = self.kept
         L.snake_cull_samples(self.G, self.occ_bits, self.K, R, r["packed_info"], r["t0"], r["t1"], r["pos"],
-                             r["ray_id"], r["tile_id"], self.packed_info, self.t0, self.t1, self.pos, self.ray_id,
-                             self.tile_id, self.cap, self.n_out, self.ws_cull, stream)
+                             r["ray_id"], r["tile_id"], k["packed_info"], k["t0"], k["t1"], k["pos"], k["ray_id"],
+                             k["tile_id"], self.cap, k["n"], self.ws_cull, stream)
+        L.snake_sample_refine(rays_o, rays_d, R, self.boxes, r["packed_info"], k["packed_info"], k["t0"], k["t1"],
+                              k["tile_id"], self.packed_info, self.t0, self.t1, self.pos, self.ray_id, self.tile_id,
+                              self.cap, self.n_out, self.ws_sample, stream)
 
     def update_occupancy(self, stream=None):
         """Evaluate the density at every cell centre with the current table and

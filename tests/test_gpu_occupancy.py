@@ -90,3 +90,48 @@ def test_cull_matches_oracle(L, orc, K):
         assert np.array_equal(host(o[k])[:m], ref[key]), k
     if K > 1:
         assert np.array_equal(host(o["tid"])[:m], ref["tile_id"])
+
+
+@pytest.mark.parametrize("K", [1, 4])
+def test_refine_matches_oracle(L, orc, K):
+    """Density-driven sampling after culling: each ray's budget spread over
+    its kept intervals, bit for bit against the oracle (counts, bounds,
+    positions, ray and tile ids); with every cell occupied it reproduces the
+    sampler's own output."""
+    G = 64
+    if K == 1:
+        w = synth.tiny_tile(seed=4, n_rays=1500, samples=48)
+        spr, S = None, 48
+    else:
+        w = synth.window_2x2(seed=4, rays_per_tile=[500, 400, 600, 300])
+        spr, S = w.samples_per_ray, 0
+    boxes, R = w.boxes, w.n_rays
+    smp = orc.sample_segmented(w.rays_o, w.rays_d, boxes, S, samples_per_ray=spr)
+    n = smp["n"]
+    rng = np.random.default_rng(10)
+    for frac in (1.0, 0.3):
+        occ = rng.random(K * G ** 3) < frac
+        kept = orc.cull_samples(smp, occ, G)
+        ref = orc.refine_samples(w.rays_o, w.rays_d, boxes, smp["packed_info"][:, 1], kept)
+        o = dict(info=torch.zeros((R, 2), dtype=torch.int32, device=DEV), t0=torch.zeros(n, device=DEV),
+                 t1=torch.zeros(n, device=DEV), pos=torch.zeros((n, 3), device=DEV),
+                 rid=torch.zeros(n, dtype=torch.int32, device=DEV), tid=torch.zeros(n, dtype=torch.uint8, device=DEV),
+                 n=torch.zeros(1, dtype=torch.int64, device=DEV))
+        ws = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=DEV)
+        L.snake_sample_refine(dev(w.rays_o), dev(w.rays_d), R, boxes, dev(smp["packed_info"], torch.int32),
+                              dev(kept["packed_info"], torch.int32), dev(kept["t0"]), dev(kept["t1"]),
+                              dev(kept["tile_id"]) if K > 1 else None, o["info"], o["t0"], o["t1"], o["pos"],
+                              o["rid"], o["tid"] if K > 1 else None, n, o["n"], ws)
+        sync()
+        m = ref["n"]
+        assert int(o["n"].item()) == m
+        assert np.array_equal(host(o["info"]), ref["packed_info"])
+        for k, key in (("t0", "t0"), ("t1", "t1"), ("pos", "pos"), ("rid", "ray_id")):
+            assert np.array_equal(host(o[k])[:m], ref[key]), (frac, k)
+        if K > 1:
+            assert np.array_equal(host(o["tid"])[:m], ref["tile_id"])
+        if frac == 1.0:
+            assert m == n and np.array_equal(host(o["t0"])[:m], smp["t0"]) and \
+                np.array_equal(host(o["pos"])[:m], smp["pos"])
+        else:
+            assert int(kept["n"]) < m <= n

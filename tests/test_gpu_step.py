@@ -16,18 +16,19 @@ from _helpers import DEV, assert_binned_bound, assert_grad, binned_floor, assert
 pytestmark = pytest.mark.gpu
 
 
-def make_nerf(w, precision="fp32", max_rays=None, occ_grid=0):
+def make_nerf(w, precision="fp32", max_rays=None, occ_grid=0, occ_refine=False):
     from paper_2507_01631_amd import TileNeRF, level_resolutions
     g, m = w.grid, w.mlp
     return TileNeRF(res=level_resolutions(g.n_levels, g.res_min, g.res_max), n_features=g.n_features,
                     log2_table=g.log2_table, n_dir=m.n_dir, colour_layers=m.colour_layers,
                     colour_out=m.colour_out, boxes=w.boxes, zband=w.zband, samples=w.samples_per_ray,
                     early_stop=w.early_stop, precision=precision, table=w.table, mlp_params=w.mlp_params,
-                    max_rays=max_rays or w.n_rays, lr=w.lr, occ_grid=occ_grid, device=DEV)
+                    max_rays=max_rays or w.n_rays, lr=w.lr, occ_grid=occ_grid, occ_refine=occ_refine,
+                    device=DEV)
 
 
-def gpu_step(w, precision="fp32", occupancy=None):
-    nerf = make_nerf(w, precision, occ_grid=occupancy[0] if occupancy else 0)
+def gpu_step(w, precision="fp32", occupancy=None, refine=False):
+    nerf = make_nerf(w, precision, occ_grid=occupancy[0] if occupancy else 0, occ_refine=refine)
     if occupancy:
         occ = occupancy[1]
         by = np.packbits(occ.reshape(-1, 8)[:, ::-1], axis=1).reshape(-1)
@@ -439,6 +440,21 @@ def test_tiny_tile_step_with_occupancy_culling(orc):
     o = orc.train_step(w, occupancy=(G, occ))
     assert 0 < o["sample"]["n"] < o["sample_raw"]["n"]
     check_step(g, o, "fp32", w, orc, tag="tiny_tile_culled")
+
+
+def test_tiny_tile_step_with_culling_and_refinement(orc):
+    """Culling, then each ray's whole sample budget spread over the intervals
+    it kept: the whole FP32 step matches the oracle step that culls and
+    refines with the same grid."""
+    w = synth.tiny_tile(seed=7)
+    G = 32
+    rng = np.random.default_rng(32)
+    occ = rng.random(G ** 3) < 0.5
+    g = gpu_step(w, "fp32", occupancy=(G, occ), refine=True)
+    o = orc.train_step(w, occupancy=(G, occ), refine=True)
+    kept = orc.cull_samples(o["sample_raw"], occ, G)
+    assert kept["n"] < o["sample"]["n"] <= o["sample_raw"]["n"]
+    check_step(g, o, "fp32", w, orc, tag="tiny_tile_refined")
 
 
 def test_occupancy_update_from_the_field(orc):
