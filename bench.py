@@ -562,6 +562,7 @@ def atomic_convergence(args):
             for sfx in [""] + ["_order%d" % o for o in range(1, max(1, args.atomic_orders))]]
     out["psnr_binned_minus_atomic_per_order_db"] = [round(x, 3) for x in gaps]
     out["psnr_binned_minus_atomic_db"] = round(float(np.mean(gaps)), 3)
+    out["psnr_binned_minus_atomic_median_db"] = round(float(np.median(gaps)), 3)
     return out
 
 
@@ -679,7 +680,7 @@ def main():
     ap.add_argument("--conv-orders", type=int, default=6,
                     help="batch orders for the FP32 and BF16 forms")
     ap.add_argument("--conv-orders-t16", type=int, default=2, help="batch orders for the BF16-table form")
-    ap.add_argument("--atomic-orders", type=int, default=2)
+    ap.add_argument("--atomic-orders", type=int, default=4)
     ap.add_argument("--conv-occupancy", type=int, default=1,
                     help="add a BF16 convergence run with a 128^3 occupancy grid")
     ap.add_argument("--conv-occ-start", type=int, default=256, help="first step that updates the grid")
