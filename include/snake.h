@@ -123,7 +123,11 @@ typedef enum {
                                                super-chunks of v x 2^20 samples, every level of
                                                one before the next (their positions then stay
                                                in the on-package cache across levels) */
-    SNAKE_TUNE_COUNT = 8
+    SNAKE_TUNE_HASH_FWD_LDS = 8,            /* hash-grid forward, 0..1 (1): 1 gathers every level
+                                               whose slice of one tile fits in a block's LDS from
+                                               an LDS copy of it, 0 gathers all levels through
+                                               the caches (same results either way) */
+    SNAKE_TUNE_COUNT = 9
 } snake_tunable;
 
 int snake_tune_set(int32_t which, int32_t value);

@@ -29,7 +29,7 @@ MAX_LEVELS = 32
 TUNABLES = {
     "hash_fwd_blocks_per_cu": 0, "mlp_fwd_blocks_per_cu": 1, "mlp_bwd_blocks_per_cu": 2,
     "composite_blocks_per_cu": 3, "bin_blocks": 4, "bin_levels_per_pass": 5, "sampler_blocks_per_cu": 6,
-    "hash_fwd_superchunk": 7,
+    "hash_fwd_superchunk": 7, "hash_fwd_lds": 8,
 }
 
 EXPORTS = (

@@ -26,6 +26,7 @@ __device__ unsigned int g_device_error;
 static constexpr int kMaxDevices = 64;
 static unsigned int *g_err_ptr[kMaxDevices];
 static int g_cus[kMaxDevices];
+static int g_lds[kMaxDevices][2];
 static std::mutex g_mu;
 
 unsigned int *device_error_word()
@@ -55,11 +56,27 @@ int num_cus()
     return g_cus[dev];
 }
 
+int lds_bytes(bool per_cu)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 65536;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int &c = g_lds[dev][per_cu ? 1 : 0];
+    if (!c) {
+        int v = 0;
+        const hipDeviceAttribute_t a =
+            per_cu ? hipDeviceAttributeMaxSharedMemoryPerMultiprocessor : hipDeviceAttributeMaxSharedMemoryPerBlock;
+        if (hipDeviceGetAttribute(&v, a, dev) != hipSuccess || v <= 0) v = 65536;
+        c = v;
+    }
+    return c;
+}
+
 // Launch-shape tunables (the only process-wide setting).
-static const int32_t kTuneDefault[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 2048, 0, 16, 0};
-static const int32_t kTuneMin[SNAKE_TUNE_COUNT] = {1, 1, 0, 1, 64, 0, 1, 0};
-static const int32_t kTuneMax[SNAKE_TUNE_COUNT] = {64, 16, 2, 64, 2048, 32, 64, 64};
-static int32_t g_tune[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 2048, 0, 16, 0};
+static const int32_t kTuneDefault[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 2048, 0, 16, 0, 1};
+static const int32_t kTuneMin[SNAKE_TUNE_COUNT] = {1, 1, 0, 1, 64, 0, 1, 0, 0};
+static const int32_t kTuneMax[SNAKE_TUNE_COUNT] = {64, 16, 2, 64, 2048, 32, 64, 64, 1};
+static int32_t g_tune[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 2048, 0, 16, 0, 1};
 
 int tune(int which) { return g_tune[which]; }
 

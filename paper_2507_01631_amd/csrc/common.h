@@ -43,6 +43,9 @@ inline int launch_status(const char *fn)
 // Number of compute units of the current device (cached per device).
 int num_cus();
 
+// LDS bytes one block may allocate (per_cu false) or one CU holds (true).
+int lds_bytes(bool per_cu);
+
 // Current value of a launch-shape tunable (snake_tunable).
 int tune(int which);
 

@@ -162,22 +162,27 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
                                                            const int32_t *__restrict__ sidx, int64_t n,
                                                            const int64_t *__restrict__ n_dev,
                                                            OutT *__restrict__ feat,
-                                                           uint32_t *__restrict__ idx_dbg, int superchunk)
+                                                           uint32_t *__restrict__ idx_dbg, int superchunk,
+                                                           uint32_t levels)
 {
     typedef typename Vec<F>::T VT;
     const int64_t ne = effective_n(n, n_dev);
     const int64_t chunks = (ne + 255) / 256;
-    const int64_t units = chunks * g.L;
+    const int nl = __builtin_popcount(levels);      // the levels this launch gathers
+    const int64_t units = chunks * nl;
     // super-chunks of sc chunks, every level of one before the next (sc =
     // chunks: level by level over all samples)
     const int64_t sc = superchunk > 0 && (int64_t)superchunk < chunks ? (int64_t)superchunk : chunks;
-    const int64_t per = sc * g.L;
+    const int64_t per = sc * nl;
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
         const int64_t b = u / per, r = u - b * per;
         const int64_t c0 = b * sc;
         const int64_t se = chunks - c0 < sc ? chunks - c0 : sc;      // chunks of this super-chunk
-        const int l = (int)(r / se);
-        const int64_t s = (c0 + (r - (int64_t)l * se)) * 256 + threadIdx.x;
+        uint32_t lm = levels;
+        for (int k = (int)(r / se); k > 0; --k) lm &= lm - 1;       // the k-th level of the set
+        const int l = __builtin_ctz(lm);
+        const int64_t rl = r / se;
+        const int64_t s = (c0 + (r - rl * se)) * 256 + threadIdx.x;
         if (s >= ne) continue;
         const int64_t si = sidx ? sidx[s] : s;
         const float x[3] = {pos[3 * si], pos[3 * si + 1], pos[3 * si + 2]};
@@ -277,6 +282,196 @@ __global__ __launch_bounds__(256) void hashgrid_fwd_kernel(Grid g, const TabT *_
         if (idx_dbg) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) idx_dbg[(s * g.L + l) * 8 + q] = idx[q];
+        }
+    }
+}
+
+// ---- forward from an LDS copy of the level slice ----------------------------
+//
+// Gathers through the vector memory path are served at about one cache line
+// per clock per CU, so a wavefront's eight random corner loads per level cost
+// hundreds of clocks even when the slice sits in L2.  A level whose slice of
+// one tile (T entries, or (N+1)^3 on a densely indexed level) fits in LDS is
+// therefore gathered from an LDS copy: a block takes kLdsR x kLdsThreads
+// consecutive samples, keeps their positions in registers, and for each such
+// level copies the slice of every tile its samples use into LDS with
+// coalesced 16-byte loads, then reads the corners there.  Samples grouped by
+// tile (as a window's partition leaves them) use one or two tiles per block;
+// any order is correct, at one copy per tile between the block's smallest and
+// largest tile id.  The corner arithmetic and the blend are those of the
+// kernel above, so both give the same bits.
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsR = 4;
+
+template <int F, typename OutT>
+__device__ __forceinline__ void store_feats(OutT *__restrict__ feat, int64_t at, const float (&acc)[F])
+{
+    if constexpr (F == 2 && std::is_same<OutT, __hip_bfloat16>::value) {
+        const __hip_bfloat16 h0 = __float2bfloat16(acc[0]), h1 = __float2bfloat16(acc[1]);
+        const uint32_t packed = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                                ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+        *reinterpret_cast<uint32_t *>(feat + at * F) = packed;
+    } else {
+#pragma unroll
+        for (int f = 0; f < F; ++f) store_feat(feat + at * F + f, acc[f]);
+    }
+}
+
+// corners() with the indexing rule fixed at compile time (same arithmetic)
+template <bool Dense>
+__device__ __forceinline__ void corners_of(const Grid &g, int l, const float x[3], uint32_t idx[8], float wt[8])
+{
+    const int N = g.res[l];
+    uint32_t c[3];
+    float w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cell(x[a], N, c[a], w[a]);
+    const uint32_t side = (uint32_t)N + 1u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t i = c[0] + (q & 1), j = c[1] + ((q >> 1) & 1), k = c[2] + ((q >> 2) & 1);
+        idx[q] = Dense ? i + j * side + k * side * side
+                       : ((i * 1u) ^ (j * 2654435761u) ^ (k * 805459861u)) & g.mask;
+        const float wx = (q & 1) ? w[0] : 1.0f - w[0];
+        const float wy = ((q >> 1) & 1) ? w[1] : 1.0f - w[1];
+        const float wz = ((q >> 2) & 1) ? w[2] : 1.0f - w[2];
+        wt[q] = (wx * wy) * wz;
+    }
+}
+
+// One level of one tile for the block's samples of that tile, gathered from
+// the slice copy in LDS.  s0 is the thread's first sample; its r-th sample
+// is s0 + r * kLdsThreads.
+template <bool Dense, int F, typename OutT, typename TabT>
+__device__ __forceinline__ void lds_level(const Grid &g, int l, int t, const TabT *lev, const float (&x)[kLdsR][3],
+                                          const int (&tl)[kLdsR], OutT *__restrict__ feat, int64_t n, int64_t s0,
+                                          uint32_t *__restrict__ idx_dbg)
+{
+    typedef typename Vec<F>::T VT;
+#pragma unroll
+    for (int r = 0; r < kLdsR; ++r) {
+        if (tl[r] != t) continue;
+        const int64_t s = s0 + (int64_t)r * kLdsThreads;
+        uint32_t idx[8];
+        float wt[8];
+        corners_of<Dense>(g, l, x[r], idx, wt);
+        VT v[8];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            v[2 * p] = Entry<F, TabT>::one(lev, idx[2 * p]);
+            // on a densely indexed level the x-neighbour holds the next slot
+            v[2 * p + 1] = Entry<F, TabT>::one(lev, Dense ? idx[2 * p] + 1u : idx[2 * p + 1]);
+        }
+        float acc[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            acc[f] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[f] = fmaf(wt[q], Vec<F>::get(v[q], f), acc[f]);
+        }
+        store_feats<F>(feat, (int64_t)l * n + s, acc);
+        if (idx_dbg) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) idx_dbg[(s * g.L + l) * 8 + q] = idx[q];
+        }
+        // one sample at a time: interleaving them only adds registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int F, typename OutT, typename TabT>
+__global__ __launch_bounds__(kLdsThreads) void hashgrid_fwd_lds_kernel(Grid g, const TabT *__restrict__ table,
+                                                                      const float *__restrict__ pos,
+                                                                      const uint8_t *__restrict__ tile_id,
+                                                                      const int32_t *__restrict__ sidx, int64_t n,
+                                                                      const int64_t *__restrict__ n_dev,
+                                                                      OutT *__restrict__ feat,
+                                                                      uint32_t *__restrict__ idx_dbg,
+                                                                      uint32_t levels)
+{
+    extern __shared__ uint4 sslice[];
+    __shared__ int srange[2];
+    typedef typename Vec<F>::T VT;
+    const TabT *lev = reinterpret_cast<const TabT *>(sslice);
+    const int64_t ne = effective_n(n, n_dev);
+    const int64_t per = (int64_t)kLdsThreads * kLdsR;
+    const int64_t subs = (ne + per - 1) / per;
+    const int tid = (int)threadIdx.x;
+    for (int64_t b = blockIdx.x; b < subs; b += gridDim.x) {
+        float x[kLdsR][3];
+        int tl[kLdsR];
+        int tmin = 0x7fffffff, tmax = -1;
+#pragma unroll
+        for (int r = 0; r < kLdsR; ++r) {
+            const int64_t s = b * per + (int64_t)r * kLdsThreads + tid;
+            tl[r] = -1;
+            x[r][0] = x[r][1] = x[r][2] = 0.0f;
+            if (s < ne) {
+                const int64_t si = sidx ? sidx[s] : s;
+                x[r][0] = pos[3 * si];
+                x[r][1] = pos[3 * si + 1];
+                x[r][2] = pos[3 * si + 2];
+                const int t = tile_id ? (int)tile_id[si] : 0;
+                if (t >= g.K) {                 // no such tile: zero features, flag it
+                    const float z[F] = {};
+                    for (uint32_t lm = levels; lm; lm &= lm - 1)
+                        store_feats<F>(feat, (int64_t)__builtin_ctz(lm) * n + s, z);
+                    if (g.err) atomicOr(g.err, (unsigned)SNAKE_DEVERR_TILE_ID);
+                } else {
+                    tl[r] = t;
+                    tmin = t < tmin ? t : tmin;
+                    tmax = t > tmax ? t : tmax;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int a = __shfl_xor(tmin, o, 64), c = __shfl_xor(tmax, o, 64);
+            tmin = a < tmin ? a : tmin;
+            tmax = c > tmax ? c : tmax;
+        }
+        __syncthreads();                        // the previous sub-range has read srange
+        if (tid == 0) {
+            srange[0] = 0x7fffffff;
+            srange[1] = -1;
+        }
+        __syncthreads();
+        if (lane_id() == 0) {
+            atomicMin(&srange[0], tmin);
+            atomicMax(&srange[1], tmax);
+        }
+        __syncthreads();
+        const int t0 = srange[0], t1 = srange[1];
+        for (uint32_t lm = levels; lm; lm &= lm - 1) {
+            const int l = __builtin_ctz(lm);
+            const bool dense = (g.dense_bits >> l) & 1u;
+            const uint32_t side = (uint32_t)g.res[l] + 1u;
+            const uint32_t entries = dense ? side * side * side : g.mask + 1u;
+            const uint32_t nvec = (uint32_t)(((uint64_t)entries * F * sizeof(TabT) + 15) / 16);
+            for (int t = t0; t <= t1; ++t) {
+                __syncthreads();                // every gather from the previous copy is done
+                const uint4 *src = reinterpret_cast<const uint4 *>(table + (((int64_t)t * g.L + l) << g.log2T) * F);
+                // four 16-byte loads in flight per thread (a clamped index past
+                // the end re-reads the last vector, which is not stored)
+                for (uint32_t i0 = (uint32_t)tid; i0 < nvec; i0 += 4 * kLdsThreads) {
+                    uint4 w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t i = i0 + (uint32_t)k * kLdsThreads;
+                        w[k] = src[i < nvec ? i : nvec - 1];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t i = i0 + (uint32_t)k * kLdsThreads;
+                        if (i < nvec) sslice[i] = w[k];
+                    }
+                }
+                __syncthreads();
+                if (dense)
+                    lds_level<true, F, OutT, TabT>(g, l, t, lev, x, tl, feat, n, b * per + tid, idx_dbg);
+                else
+                    lds_level<false, F, OutT, TabT>(g, l, t, lev, x, tl, feat, n, b * per + tid, idx_dbg);
+            }
         }
     }
 }
@@ -1253,29 +1448,56 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const void *table, 
     SNAKE_ALIGNED(table, 16);
     const int F = gd->n_features;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const unsigned grid = grid_for(n * g.L, 256, tune(SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU));
     const int superchunk = tune(SNAKE_TUNE_HASH_FWD_SUPERCHUNK) * 4096;   // in 256-sample chunks
     const bool bf = gd->feat_dtype == SNAKE_BF16;
     const bool tb = (gd->flags & SNAKE_GRID_TABLE_BF16) != 0;
     if (F == 2) SNAKE_ALIGNED(feat, bf ? 4 : 8);    // one store per sample-level
+    // Levels whose slice of one tile fits in a block's LDS are gathered from
+    // an LDS copy, the rest through the caches.
+    const uint32_t all = g.L == 32 ? 0xffffffffu : (1u << g.L) - 1u;
+    uint32_t lds_lv = 0;
+    size_t lds_max = 0;
+    if (tune(SNAKE_TUNE_HASH_FWD_LDS)) {
+        const size_t budget = (size_t)lds_bytes(false) - 256;    // less the kernel's own LDS words
+        const size_t esz = (size_t)F * (tb ? 2 : 4);
+        for (int l = 0; l < g.L; ++l) {
+            const uint64_t side = (uint64_t)g.res[l] + 1;
+            const uint64_t entries = ((g.dense_bits >> l) & 1u) ? side * side * side : (uint64_t)g.mask + 1;
+            const size_t bytes = (size_t)((entries * esz + 15) / 16 * 16);
+            if (bytes <= budget) {
+                lds_lv |= 1u << l;
+                lds_max = bytes > lds_max ? bytes : lds_max;
+            }
+        }
+    }
+    const uint32_t l2_lv = all & ~lds_lv;
+    const unsigned grid = grid_for(n * __builtin_popcount(l2_lv), 256, tune(SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU));
+    // at most two 1024-thread blocks fit a CU's wavefront slots
+    const int per_cu = (int)((size_t)lds_bytes(true) / (lds_max + 256));
+    const unsigned lgrid = grid_for((n + (int64_t)kLdsThreads * kLdsR - 1) / ((int64_t)kLdsThreads * kLdsR) *
+                                        kLdsThreads, kLdsThreads, per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
     const float *tf = static_cast<const float *>(table);
     const __hip_bfloat16 *th = static_cast<const __hip_bfloat16 *>(table);
     __hip_bfloat16 *fh = static_cast<__hip_bfloat16 *>(feat);
     float *ff = static_cast<float *>(feat);
-#define SNAKE_HG_FWD(FF)                                                                                        \
-    if (tb && bf)                                                                                               \
-        hashgrid_fwd_kernel<FF, __hip_bfloat16, __hip_bfloat16><<<grid, 256, 0, st>>>(g, th, pos, tile_id,      \
-                                                                                    sample_idx, n, n_dev, fh,   \
-                                                                                    idx_dbg, superchunk);       \
-    else if (tb)                                                                                                \
-        hashgrid_fwd_kernel<FF, float, __hip_bfloat16><<<grid, 256, 0, st>>>(g, th, pos, tile_id, sample_idx, n, \
-                                                                           n_dev, ff, idx_dbg, superchunk);     \
-    else if (bf)                                                                                                \
-        hashgrid_fwd_kernel<FF, __hip_bfloat16, float><<<grid, 256, 0, st>>>(g, tf, pos, tile_id, sample_idx, n, \
-                                                                           n_dev, fh, idx_dbg, superchunk);     \
-    else                                                                                                        \
-        hashgrid_fwd_kernel<FF, float, float><<<grid, 256, 0, st>>>(g, tf, pos, tile_id, sample_idx, n, n_dev,  \
-                                                                  ff, idx_dbg, superchunk)
+#define SNAKE_HG_FWD1(FF, OT, TT, tab, out)                                                                      \
+    do {                                                                                                         \
+        if (lds_lv)                                                                                              \
+            hashgrid_fwd_lds_kernel<FF, OT, TT><<<lgrid, kLdsThreads, lds_max, st>>>(                            \
+                g, tab, pos, tile_id, sample_idx, n, n_dev, out, idx_dbg, lds_lv);                               \
+        if (l2_lv)                                                                                               \
+            hashgrid_fwd_kernel<FF, OT, TT><<<grid, 256, 0, st>>>(g, tab, pos, tile_id, sample_idx, n, n_dev,    \
+                                                                  out, idx_dbg, superchunk, l2_lv);              \
+    } while (0)
+#define SNAKE_HG_FWD(FF)                                                                                         \
+    if (tb && bf)                                                                                                \
+        SNAKE_HG_FWD1(FF, __hip_bfloat16, __hip_bfloat16, th, fh);                                               \
+    else if (tb)                                                                                                 \
+        SNAKE_HG_FWD1(FF, float, __hip_bfloat16, th, ff);                                                        \
+    else if (bf)                                                                                                 \
+        SNAKE_HG_FWD1(FF, __hip_bfloat16, float, tf, fh);                                                        \
+    else                                                                                                         \
+        SNAKE_HG_FWD1(FF, float, float, tf, ff)
     if (F == 1) {
         SNAKE_HG_FWD(1);
     } else if (F == 2) {
@@ -1284,6 +1506,7 @@ int snake_hashgrid_fwd(const snake_grid_desc *gd, int32_t K, const void *table, 
         SNAKE_HG_FWD(4);
     }
 #undef SNAKE_HG_FWD
+#undef SNAKE_HG_FWD1
     return launch_status(__func__);
 }
 

@@ -183,11 +183,15 @@ def test_binding_raises_on_error(L):
 
 def test_tunables_table(L):
     ids = L.TUNABLES
-    assert len(ids) == 8 and sorted(ids.values()) == list(range(8))
+    assert len(ids) == 9 and sorted(ids.values()) == list(range(9))
     saved = {k: L.snake_tune_get(k) for k in ids}
     try:
         assert saved["hash_fwd_blocks_per_cu"] == 16 and saved["bin_blocks"] == 2048
-        assert saved["hash_fwd_superchunk"] == 0
+        assert saved["hash_fwd_superchunk"] == 0 and saved["hash_fwd_lds"] == 1
+        L.snake_tune_set("hash_fwd_lds", 0)                    # 0 is a value here: off
+        assert L.snake_tune_get("hash_fwd_lds") == 0
+        with pytest.raises(L.SnakeError):
+            L.snake_tune_set("hash_fwd_lds", 2)
         L.snake_tune_set("hash_fwd_superchunk", 64)
         with pytest.raises(L.SnakeError):
             L.snake_tune_set("hash_fwd_superchunk", 65)

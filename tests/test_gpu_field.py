@@ -144,6 +144,62 @@ def test_hashgrid_fwd_superchunk_order(L, orc):
     assert_values(got, ref, 2 ** -8, 1e-6, "feat (sampled)")
 
 
+@pytest.mark.parametrize("name", ["tiny", "full", "f1", "f4"])
+@pytest.mark.parametrize("table_bf16", [False, True])
+def test_hashgrid_fwd_lds_path_matches_cache_path(L, orc, name, table_bf16):
+    """Levels whose slice fits in LDS are gathered from an LDS copy unless the
+    hash_fwd_lds tunable is 0.  Both paths give the same bits and corner
+    slots: tiles grouped in runs (as a window's partition leaves them, with
+    runs ending inside a block's samples), in random order, an id past the
+    last tile, an index array and a device count below the host bound, over
+    several blocks of samples and a ragged tail; sampled features against the
+    oracle."""
+    rng = np.random.default_rng(19)
+    K = 3
+    c, res, table = _grid_setup(L, orc, name, rng, K)
+    n = 5 * 4096 + 1234
+    pos = _ray_positions(rng, n)
+    runs = np.repeat(np.arange(K), [6000, 9000, n - 15000]).astype(np.uint8)
+    rand = rng.integers(0, K, size=n).astype(np.uint8)
+    rand[::101] = K                                  # no such tile
+    sel = rng.permutation(n).astype(np.int32)
+    flags = L.SNAKE_GRID_TABLE_BF16 if table_bf16 else 0
+    g = L.grid_desc(res, c["F"], c["log2T"], L.SNAKE_BF16, flags)
+    if table_bf16:
+        tab = torch.empty(table.shape, dtype=torch.bfloat16, device=DEV)
+        L.snake_convert_bf16(dev(table), table.size, tab)
+        reft = bf16_round(table)
+    else:
+        tab, reft = dev(table), table
+    nd = torch.tensor([n - 777], dtype=torch.int64, device=DEV)
+    cases = [(runs, None, None), (rand, None, None), (runs, sel, nd)]
+    saved = L.snake_tune_get("hash_fwd_lds")
+    try:
+        for tid, idxs, ndev in cases:
+            outs = []
+            for v in (0, 1):
+                L.snake_tune_set("hash_fwd_lds", v)
+                feat = torch.full((c["L"], n, c["F"]), 3.0, dtype=torch.bfloat16, device=DEV)
+                idx = torch.zeros((n, c["L"], 8), dtype=torch.int32, device=DEV)
+                L.snake_hashgrid_fwd(g, K, tab, dev(pos), dev(tid), None if idxs is None else dev(idxs), n, ndev,
+                                     feat, idx)
+                outs.append((feat, idx))
+            sync()
+            assert torch.equal(outs[0][0], outs[1][0])
+            assert torch.equal(outs[0][1], outs[1][1])
+            ne = n if ndev is None else n - 777
+            s = rng.choice(ne, size=1500, replace=False)
+            src = s if idxs is None else idxs[s]
+            ok = tid[src] < K
+            ref = orc.hashgrid_fwd(res, c["log2T"], reft, pos[src[ok]], tid[src[ok]], 32)
+            got = host(outs[1][0][:, torch.as_tensor(s[ok], device=DEV), :]).transpose(1, 0, 2).reshape(ok.sum(), -1)
+            assert_values(got, ref[:, :c["L"] * c["F"]], 2 ** -8, 1e-6, "feat (sampled, %s)" % name)
+            assert np.all(host(outs[1][0][:, torch.as_tensor(s[~ok], device=DEV), :]) == 0.0)
+    finally:
+        L.snake_tune_set("hash_fwd_lds", saved)
+    L.snake_check_device_error()
+
+
 def test_hashgrid_fwd_indexed_and_device_count(L, orc):
     rng = np.random.default_rng(11)
     c, res, table = _grid_setup(L, orc, "full", rng)
