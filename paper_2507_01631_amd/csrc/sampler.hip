@@ -26,10 +26,15 @@ struct Boxes {
     double z_lo, z_hi;
 };
 
-struct Seg {
-    double tn, tf;
-    int tile;
-    int n;
+// A ray's hit segments in entry order.  Every array is indexed with
+// compile-time indices only (unrolled loops and selects), so the list lives
+// in registers: an index computed at run time would put it in scratch memory.
+template <int KMAX>
+struct Segs {
+    double tn[KMAX], tf[KMAX];
+    int tile[KMAX];
+    int n[KMAX];
+    int ns;
 };
 
 // FP64 slab test; hit iff t_far > t_near after clamping t_near at 0.  An
@@ -58,15 +63,18 @@ __device__ __forceinline__ bool slab(const double o[3], const double d[3], const
     return true;
 }
 
-// Hit segments of one ray in entry order with their sample counts (sum S_r
-// when S_r > 0).  Returns the number of segments.
+// Hit segments of one ray in entry order (ties in the entry point by tile
+// index) with their sample counts (sum S_r when S_r > 0).
 template <int KMAX>
-__device__ int ray_segments(const double o[3], const double d[3], const Boxes &bx, int S_r,
-                            Seg *seg)
+__device__ __forceinline__ void ray_segments(const double o[3], const double d[3], const Boxes &bx, int S_r,
+                                             Segs<KMAX> &sg)
 {
-    int ns = 0;
+    double tn[KMAX], tf[KMAX];
+    bool hit[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
+        hit[k] = false;
+        tn[k] = tf[k] = 0.0;
         if (k < bx.K) {
             double lo[3] = {bx.b[k][0], bx.b[k][1], bx.b[k][2]};
             double hi[3] = {bx.b[k][3], bx.b[k][4], bx.b[k][5]};
@@ -74,36 +82,52 @@ __device__ int ray_segments(const double o[3], const double d[3], const Boxes &b
                 lo[2] = bx.z_lo > lo[2] ? bx.z_lo : lo[2];
                 hi[2] = bx.z_hi < hi[2] ? bx.z_hi : hi[2];
             }
-            double tn, tf;
-            if (slab(o, d, lo, hi, tn, tf)) {
-                // insert keeping (tn, tile) order
-                int j = ns;
-                while (j > 0 && seg[j - 1].tn > tn) {
-                    seg[j] = seg[j - 1];
-                    --j;
-                }
-                seg[j].tn = tn;
-                seg[j].tf = tf;
-                seg[j].tile = k;
-                seg[j].n = 0;
-                ++ns;
-            }
+            hit[k] = slab(o, d, lo, hi, tn[k], tf[k]);
         }
     }
-    if (ns == 0 || S_r <= 0) return ns;
+    // position of each hit box in (entry point, tile) order
+    int rank[KMAX];
+    int ns = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        rank[k] = 0;
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            rank[k] += (hit[i] && (tn[i] < tn[k] || (tn[i] == tn[k] && i < k))) ? 1 : 0;
+        ns += hit[k] ? 1 : 0;
+    }
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p) {
+        sg.tn[p] = sg.tf[p] = 0.0;
+        sg.tile[p] = 0;
+        sg.n[p] = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (hit[k] && rank[k] == p) {
+                sg.tn[p] = tn[k];
+                sg.tf[p] = tf[k];
+                sg.tile[p] = k;
+            }
+    }
+    sg.ns = ns;
+    if (ns == 0 || S_r <= 0) return;
     const int base = S_r >= ns ? 1 : 0;
     const int extra = S_r - base * ns;
     double total = 0.0;
-    for (int i = 0; i < ns; ++i) total += seg[i].tf - seg[i].tn;
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p)
+        if (p < ns) total += sg.tf[p] - sg.tn[p];
     double cum = 0.0;
     int prev = 0;
-    for (int i = 0; i < ns; ++i) {
-        cum += seg[i].tf - seg[i].tn;
-        int b = (i == ns - 1) ? extra : (int)rint((double)extra * cum / total);
-        seg[i].n = base + b - prev;
-        prev = b;
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p) {
+        if (p < ns) {
+            cum += sg.tf[p] - sg.tn[p];
+            const int b = (p == ns - 1) ? extra : (int)rint((double)extra * cum / total);
+            sg.n[p] = base + b - prev;
+            prev = b;
+        }
     }
-    return ns;
 }
 
 __device__ __forceinline__ void load_ray(const double *ro, const double *rd, int64_t r, double o[3],
@@ -128,11 +152,12 @@ __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ r
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
         double o[3], d[3];
         load_ray(ro, rd, r, o, d);
-        Seg seg[KMAX];
+        Segs<KMAX> sg;
         int S_r = spr ? spr[r] : S;
-        int ns = ray_segments<KMAX>(o, d, bx, S_r, seg);
+        ray_segments<KMAX>(o, d, bx, S_r, sg);
         int c = 0;
-        for (int i = 0; i < ns; ++i) c += seg[i].n;
+#pragma unroll
+        for (int p = 0; p < KMAX; ++p) c += sg.n[p];
         if (max_count) {
             int mc = max_count[r];
             mc = mc < 0 ? 0 : mc;
@@ -165,19 +190,38 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
         if (count == 0) continue;
         double o[3], d[3];
         load_ray(ro, rd, r, o, d);
-        Seg seg[KMAX];
+        Segs<KMAX> sg;
         int S_r = spr ? spr[r] : S;
-        int ns = ray_segments<KMAX>(o, d, bx, S_r, seg);
+        ray_segments<KMAX>(o, d, bx, S_r, sg);
+        const int ns = sg.ns;
         for (int j = lane; j < count; j += 64) {
-            // segment of packed sample j
+            // segment of packed sample j: the first whose end lies past j, or the last
             int s = 0, before = 0;
-            while (s < ns - 1 && j >= before + seg[s].n) {
-                before += seg[s].n;
-                ++s;
-            }
-            const int k = j - before, n = seg[s].n;
-            const double *b = bx.b[seg[s].tile];
-            float tn = (float)seg[s].tn, tf = (float)seg[s].tf;
+#pragma unroll
+            for (int p = 0; p + 1 < KMAX; ++p)
+                if (s == p && p < ns - 1 && j >= before + sg.n[p]) {
+                    before += sg.n[p];
+                    s = p + 1;
+                }
+            double stn = sg.tn[0], stf = sg.tf[0];
+            int n = sg.n[0], tile = sg.tile[0];
+#pragma unroll
+            for (int p = 1; p < KMAX; ++p)
+                if (s == p) {
+                    stn = sg.tn[p];
+                    stf = sg.tf[p];
+                    n = sg.n[p];
+                    tile = sg.tile[p];
+                }
+            double b[6] = {bx.b[0][0], bx.b[0][1], bx.b[0][2], bx.b[0][3], bx.b[0][4], bx.b[0][5]};
+#pragma unroll
+            for (int t = 1; t < KMAX; ++t)
+                if (tile == t) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) b[e] = bx.b[t][e];
+                }
+            const int k = j - before;
+            float tn = (float)stn, tf = (float)stf;
             float step = (tf - tn) / (float)n;
             float ta = tn + (float)k * step;
             float tb = (k + 1 == n) ? tf : tn + (float)(k + 1) * step;
@@ -197,7 +241,7 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
                 pos[3 * out + a] = x;
             }
             ray_id[out] = r;
-            if (tile_id) tile_id[out] = (uint8_t)seg[s].tile;
+            if (tile_id) tile_id[out] = (uint8_t)tile;
         }
     }
 }
