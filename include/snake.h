@@ -177,6 +177,30 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
                            void *workspace, size_t workspace_bytes, snake_stream_t stream);
 
 /*
+ * The sampler with its samples grouped by tile, for the window step (Sec.
+ * 4.4), where each loaded tile has its own networks: the same samples as
+ * snake_sample_segmented with the same arguments, and packed_info [R][2],
+ * t0, t1 and view as there (packed, ray by ray), but pos [][3], ray_id and
+ * tile_id (not NULL) written tile by tile, ray by ray within a tile, in t
+ * within a ray -- the order snake_tile_partition gives the packed samples.
+ * sample_map [n] int32 (device) maps a packed index to its grouped index
+ * (that partition's inv), and tile_start [K+2] int64 (device) bounds the
+ * groups: tile k holds grouped indices tile_start[k] .. tile_start[k+1]-1,
+ * and tile_start[K] = tile_start[K+1] = *n_out.  Replaces the sampler and
+ * the partition with one count, two scans and one fill.  R * K < 2^31.
+ * Workspace: snake_sample_grouped_workspace_bytes(R, K) (0 for bad R, K),
+ * 256-byte aligned.  Errors as snake_sample_segmented.
+ */
+size_t snake_sample_grouped_workspace_bytes(int32_t R, int32_t K);
+int snake_sample_grouped(const double *rays_o, const double *rays_d, int32_t R,
+                         const double *boxes, int32_t K, const double *zband,
+                         const int32_t *samples_per_ray, int32_t S, const int32_t *max_count,
+                         int32_t *packed_info, float *t0, float *t1, float *view,
+                         float *pos, int32_t *ray_id, uint8_t *tile_id, int32_t *sample_map,
+                         int64_t *tile_start, int64_t cap, int64_t *n_out,
+                         void *workspace, size_t workspace_bytes, snake_stream_t stream);
+
+/*
  * No-allocation variant of snake_sample_segmented, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  Same arguments and results, without the

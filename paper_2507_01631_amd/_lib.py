@@ -36,6 +36,7 @@ EXPORTS = (
     "snake_abi_version", "snake_last_error", "snake_check_device_error", "snake_tune_set", "snake_tune_get",
     "snake_stream_create_dedicated", "snake_stream_destroy",
     "snake_sample_workspace_bytes", "snake_sample_segmented", "snake_sample_segmented_static_max_rays",
+    "snake_sample_grouped_workspace_bytes", "snake_sample_grouped",
     "snake_sample_segmented_static", "snake_pack_alive",
     "snake_window_accept", "snake_tile_partition_workspace_bytes", "snake_tile_partition",
     "snake_occupancy_cells", "snake_occupancy_workspace_bytes", "snake_occupancy_update",
@@ -99,6 +100,9 @@ _SIGS = {
     "snake_sample_segmented": ([_P, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
                                 _I64, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_sample_segmented_static_max_rays": ([], _I32),
+    "snake_sample_grouped_workspace_bytes": ([_I32, _I32], _SZ),
+    "snake_sample_grouped": ([_P, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                              _I64, _P, _P, _SZ, _P], ctypes.c_int),
     "snake_sample_segmented_static": ([_P, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
                                        _I64, _P, _P], ctypes.c_int),
     "snake_pack_alive": ([_P, _P, _I32, _P, _I64, _P, _P, _SZ, _P], ctypes.c_int),
@@ -218,6 +222,23 @@ def snake_sample_segmented(rays_o, rays_d, R, boxes, zband, samples_per_ray, S, 
         int(cap), _ptr(n_out), _ptr(workspace), workspace.numel() * workspace.element_size(),
         _stream(stream))
     _check("snake_sample_segmented", rc)
+
+
+def snake_sample_grouped_workspace_bytes(R, K):
+    return int(lib().snake_sample_grouped_workspace_bytes(int(R), int(K)))
+
+
+def snake_sample_grouped(rays_o, rays_d, R, boxes, zband, samples_per_ray, S, max_count, packed_info, t0, t1,
+                         view, pos, ray_id, tile_id, sample_map, tile_start, cap, n_out, workspace, stream=None):
+    boxes = _host_f64(boxes).reshape(-1, 6)
+    zb = _host_f64(zband)
+    rc = lib().snake_sample_grouped(
+        _ptr(rays_o), _ptr(rays_d), int(R), boxes.ctypes.data, int(boxes.shape[0]),
+        None if zb is None else zb.ctypes.data, _ptr(samples_per_ray), int(S), _ptr(max_count),
+        _ptr(packed_info), _ptr(t0), _ptr(t1), _ptr(view), _ptr(pos), _ptr(ray_id), _ptr(tile_id),
+        _ptr(sample_map), _ptr(tile_start), int(cap), _ptr(n_out), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream))
+    _check("snake_sample_grouped", rc)
 
 
 def snake_sample_segmented_static_max_rays():

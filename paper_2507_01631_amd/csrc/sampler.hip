@@ -65,24 +65,70 @@ __device__ __forceinline__ bool slab(const double o[3], const double d[3], const
 
 // Hit segments of one ray in entry order (ties in the entry point by tile
 // index) with their sample counts (sum S_r when S_r > 0).
+__device__ __forceinline__ double read_lane(double v, int k)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(w.x, k), __builtin_amdgcn_readlane(w.y, k)));
+}
+
+// Box k of the list, clipped to the altitude band when one is set.
 template <int KMAX>
+__device__ __forceinline__ void box_of(const Boxes &bx, int k, double lo[3], double hi[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = bx.b[0][a];
+        hi[a] = bx.b[0][3 + a];
+    }
+#pragma unroll
+    for (int t = 1; t < KMAX; ++t)
+        if (k == t) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = bx.b[t][a];
+                hi[a] = bx.b[t][3 + a];
+            }
+        }
+    if (bx.use_band) {
+        lo[2] = bx.z_lo > lo[2] ? bx.z_lo : lo[2];
+        hi[2] = bx.z_hi < hi[2] ? bx.z_hi : hi[2];
+    }
+}
+
+// Wave = true: called by a whole wavefront for one ray (every lane active,
+// the same o and d); lane k tests box k and the others read its result.
+template <int KMAX, bool Wave = false>
 __device__ __forceinline__ void ray_segments(const double o[3], const double d[3], const Boxes &bx, int S_r,
                                              Segs<KMAX> &sg)
 {
     double tn[KMAX], tf[KMAX];
     bool hit[KMAX];
+    if constexpr (Wave && KMAX > 1) {
+        const int lane = lane_id();
+        double mtn = 0.0, mtf = 0.0;
+        bool mhit = false;
+        if (lane < bx.K) {
+            double lo[3], hi[3];
+            box_of<KMAX>(bx, lane, lo, hi);
+            mhit = slab(o, d, lo, hi, mtn, mtf);
+        }
+        const unsigned long long hits = __ballot(mhit);
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        hit[k] = false;
-        tn[k] = tf[k] = 0.0;
-        if (k < bx.K) {
-            double lo[3] = {bx.b[k][0], bx.b[k][1], bx.b[k][2]};
-            double hi[3] = {bx.b[k][3], bx.b[k][4], bx.b[k][5]};
-            if (bx.use_band) {
-                lo[2] = bx.z_lo > lo[2] ? bx.z_lo : lo[2];
-                hi[2] = bx.z_hi < hi[2] ? bx.z_hi : hi[2];
+        for (int k = 0; k < KMAX; ++k) {
+            hit[k] = (hits >> k) & 1ull;
+            tn[k] = read_lane(mtn, k);
+            tf[k] = read_lane(mtf, k);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            hit[k] = false;
+            tn[k] = tf[k] = 0.0;
+            if (k < bx.K) {
+                double lo[3], hi[3];
+                box_of<KMAX>(bx, k, lo, hi);
+                hit[k] = slab(o, d, lo, hi, tn[k], tf[k]);
             }
-            hit[k] = slab(o, d, lo, hi, tn[k], tf[k]);
         }
     }
     // position of each hit box in (entry point, tile) order
@@ -141,13 +187,14 @@ __device__ __forceinline__ void load_ray(const double *ro, const double *rd, int
 }
 
 // ---- count ----------------------------------------------------------------
-template <int KMAX>
+// Grouped = true also writes tcounts [K][R]: ray r's (kept) samples in tile k.
+template <int KMAX, bool Grouped>
 __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ ro,
                                                     const double *__restrict__ rd, int R, Boxes bx,
                                                     const int32_t *__restrict__ spr, int S,
                                                     const int32_t *__restrict__ max_count,
                                                     int32_t *__restrict__ counts,
-                                                    float *__restrict__ view)
+                                                    float *__restrict__ view, int32_t *__restrict__ tcounts)
 {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
         double o[3], d[3];
@@ -164,6 +211,24 @@ __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ r
             c = mc < c ? mc : c;
         }
         counts[r] = c;
+        if constexpr (Grouped) {
+            // the kept prefix of c samples, segment by segment in entry order
+            int per[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) per[k] = 0;
+            int left = c;
+#pragma unroll
+            for (int p = 0; p < KMAX; ++p) {
+                const int e = sg.n[p] < left ? sg.n[p] : left;
+                left -= e;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (p < sg.ns && sg.tile[p] == k) per[k] = e;
+            }
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < bx.K) tcounts[(int64_t)k * R + r] = per[k];
+        }
         if (view) {
             double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 #pragma unroll
@@ -172,15 +237,31 @@ __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ r
     }
 }
 
+// Where each tile's group starts: tile_start[k] = goffs[k][0] for k < K, and
+// tile_start[K] = tile_start[K+1] = the total (no sample has a tile id >= K).
+__global__ void tile_starts_kernel(const int32_t *__restrict__ goffs, int R, int K,
+                                   const int64_t *__restrict__ total, int64_t *__restrict__ tile_start)
+{
+    const int k = threadIdx.x;
+    if (k < K) tile_start[k] = R > 0 ? goffs[(int64_t)k * R] : 0;
+    if (k == K || k == K + 1) tile_start[k] = R > 0 ? *total : 0;
+}
+
 // ---- fill: one wavefront per ray, one lane per sample -----------------------
-template <int KMAX>
+//
+// Grouped = false writes every sample at its packed (ray-major) index.
+// Grouped = true writes t0/t1 there but pos, ray_id and tile_id grouped by
+// tile -- tile by tile, ray by ray, in t within a ray (goffs [K][R]: where
+// ray r's samples in tile k start) -- with smap[packed index] = grouped index.
+template <int KMAX, bool Grouped>
 __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro,
                                                    const double *__restrict__ rd, int R, Boxes bx,
                                                    const int32_t *__restrict__ spr, int S,
                                                    const int32_t *__restrict__ info, int64_t cap,
                                                    float *__restrict__ t0, float *__restrict__ t1,
                                                    float *__restrict__ pos, int32_t *__restrict__ ray_id,
-                                                   uint8_t *__restrict__ tile_id)
+                                                   uint8_t *__restrict__ tile_id,
+                                                   const int32_t *__restrict__ goffs, int32_t *__restrict__ smap)
 {
     const int lane = threadIdx.x & 63;
     const int waves = gridDim.x * (blockDim.x >> 6);
@@ -192,9 +273,37 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
         load_ray(ro, rd, r, o, d);
         Segs<KMAX> sg;
         int S_r = spr ? spr[r] : S;
-        ray_segments<KMAX>(o, d, bx, S_r, sg);
+        ray_segments<KMAX, true>(o, d, bx, S_r, sg);
         const int ns = sg.ns;
-        for (int j = lane; j < count; j += 64) {
+        // the tile-frame origin and direction of each segment's box: lane p
+        // computes segment p's, and a sample reads them from that lane
+        float olp[3], dlp[3];
+        {
+            int tp = sg.tile[0];
+#pragma unroll
+            for (int p = 1; p < KMAX; ++p)
+                if (KMAX > 1 && lane == p) tp = sg.tile[p];
+            // the whole box (the altitude band clips only the segment)
+            double b[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) b[e] = bx.b[0][e];
+#pragma unroll
+            for (int t = 1; t < KMAX; ++t)
+                if (tp == t) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) b[e] = bx.b[t][e];
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double ext = b[3 + a] - b[a];
+                olp[a] = (float)((o[a] - b[a]) / ext);
+                dlp[a] = (float)(d[a] / ext);
+            }
+        }
+        // every lane runs every trip, so that each one's segment values can
+        // be read from any lane; a lane past the ray's count stores nothing
+        for (int j0 = 0; j0 < count; j0 += 64) {
+            const int j = j0 + lane;
             // segment of packed sample j: the first whose end lies past j, or the last
             int s = 0, before = 0;
 #pragma unroll
@@ -213,13 +322,13 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
                     n = sg.n[p];
                     tile = sg.tile[p];
                 }
-            double b[6] = {bx.b[0][0], bx.b[0][1], bx.b[0][2], bx.b[0][3], bx.b[0][4], bx.b[0][5]};
+            float ol[3], dl[3];
 #pragma unroll
-            for (int t = 1; t < KMAX; ++t)
-                if (tile == t) {
-#pragma unroll
-                    for (int e = 0; e < 6; ++e) b[e] = bx.b[t][e];
-                }
+            for (int a = 0; a < 3; ++a) {
+                ol[a] = KMAX > 1 ? __shfl(olp[a], s, 64) : olp[a];
+                dl[a] = KMAX > 1 ? __shfl(dlp[a], s, 64) : dlp[a];
+            }
+            if (j >= count) continue;
             const int k = j - before;
             float tn = (float)stn, tf = (float)stf;
             float step = (tf - tn) / (float)n;
@@ -230,18 +339,21 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
             if (out >= cap) continue;
             t0[out] = ta;
             t1[out] = tb;
+            int64_t g = out;
+            if constexpr (Grouped) {
+                g = (int64_t)goffs[(int64_t)tile * R + r] + k;
+                smap[out] = (int32_t)g;
+                if (g >= cap) continue;
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                double ext = b[3 + a] - b[a];
-                float ol = (float)((o[a] - b[a]) / ext);
-                float dl = (float)(d[a] / ext);
-                float x = ol + m * dl;
+                float x = ol[a] + m * dl[a];
                 x = x < 0.0f ? 0.0f : x;
                 x = x > 1.0f ? 1.0f : x;
-                pos[3 * out + a] = x;
+                pos[3 * g + a] = x;
             }
-            ray_id[out] = r;
-            if (tile_id) tile_id[out] = (uint8_t)tile;
+            ray_id[g] = r;
+            if (tile_id) tile_id[g] = (uint8_t)tile;
         }
     }
 }
@@ -448,12 +560,21 @@ size_t snake_sample_workspace_bytes(int32_t R) { return scan_ws_bytes(R); }
 
 // The sampler on a given count/scan workspace; fn names the entry point in
 // error messages.
+static size_t grouped_ws_bytes(int32_t R, int32_t K)
+{
+    return scan_ws_bytes(R) + scan_ws_bytes(R * K) + 256;
+}
+
+// smap != NULL: the grouped form (pos, ray_id, tile_id grouped by tile,
+// smap and tile_start written; the workspace as grouped_ws_bytes).
 static int sample_impl(const char *fn, const double *rays_o, const double *rays_d, int32_t R, const double *boxes,
                        int32_t K, const double *zband, const int32_t *samples_per_ray, int32_t S,
                        const int32_t *max_count, int32_t *packed_info, float *t0, float *t1, float *pos,
                        int32_t *ray_id, uint8_t *tile_id, float *view, int64_t cap, int64_t *n_out,
-                       void *workspace, size_t workspace_bytes, snake_stream_t stream)
+                       void *workspace, size_t workspace_bytes, snake_stream_t stream, int32_t *smap = nullptr,
+                       int64_t *tile_start = nullptr)
 {
+    const bool grouped = smap != nullptr;
     SNAKE_REQUIRE(R >= 0, SNAKE_ERR_INVALID_ARG, "%s: R = %d < 0", fn, R);
     SNAKE_REQUIRE(K >= 1 && K <= kMaxTiles, SNAKE_ERR_INVALID_ARG, "%s: K = %d not in [1, %d]", fn, K, kMaxTiles);
     SNAKE_REQUIRE(K == 1 || tile_id != nullptr, SNAKE_ERR_NULL, "%s: tile_id is NULL with K = %d > 1", fn, K);
@@ -464,8 +585,15 @@ static int sample_impl(const char *fn, const double *rays_o, const double *rays_
     SNAKE_REQUIRE(R == 0 || (rays_o && rays_d && packed_info), SNAKE_ERR_NULL,
                   "%s: rays_o, rays_d or packed_info is NULL", fn);
     SNAKE_REQUIRE(cap == 0 || (t0 && t1 && pos && ray_id), SNAKE_ERR_NULL, "%s: t0, t1, pos or ray_id is NULL", fn);
-    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= scan_ws_bytes(R), SNAKE_ERR_WORKSPACE,
-                  "%s: workspace needs %zu bytes", fn, scan_ws_bytes(R));
+    if (grouped) {
+        SNAKE_REQUIRE((int64_t)R * K <= INT32_MAX, SNAKE_ERR_INVALID_ARG, "%s: R * K = %lld not below 2^31", fn,
+                      (long long)R * K);
+        SNAKE_REQUIRE(tile_start != nullptr && tile_id != nullptr, SNAKE_ERR_NULL, "%s: tile_start or tile_id is NULL",
+                      fn);
+    }
+    const size_t need = grouped ? grouped_ws_bytes(R, K) : scan_ws_bytes(R);
+    SNAKE_REQUIRE(workspace != nullptr && workspace_bytes >= need, SNAKE_ERR_WORKSPACE, "%s: workspace needs %zu bytes",
+                  fn, need);
     SNAKE_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % 256 == 0, SNAKE_ERR_ALIGN,
                   "%s: workspace is not 256-byte aligned", fn);
     Boxes bx{};
@@ -485,16 +613,35 @@ static int sample_impl(const char *fn, const double *rays_o, const double *rays_
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (R == 0) {
         set_i64_kernel<<<1, 1, 0, st>>>(n_out, 0);
+        if (grouped) tile_starts_kernel<<<1, 64, 0, st>>>(nullptr, 0, K, nullptr, tile_start);
         return launch_status(fn);
     }
     ScanWs w = carve(workspace, R);
+    // the grouped form's per-tile counts and their scan, after the ray scan's
+    ScanWs tw{};
+    int64_t *gtotal = nullptr;
+    if (grouped) {
+        char *p = static_cast<char *>(workspace) + scan_ws_bytes(R);
+        tw = carve(p, R * K);
+        gtotal = reinterpret_cast<int64_t *>(p + scan_ws_bytes(R * K));
+    }
     const unsigned gc = grid_for(R, 256, 8), gf = grid_for((int64_t)R * 64, 256, tune(SNAKE_TUNE_SAMPLER_BLOCKS_PER_CU));
-#define SNAKE_SAMPLER_LAUNCH(KM)                                                                   \
-    count_kernel<KM><<<gc, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, max_count,     \
-                                         w.counts, view);                                        \
-    launch_scan(w, R, packed_info, 2, packed_info + 1, cap, n_out, st);                          \
-    fill_kernel<KM><<<gf, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, packed_info,  \
-                                        cap, t0, t1, pos, ray_id, tile_id)
+#define SNAKE_SAMPLER_LAUNCH(KM)                                                                              \
+    if (grouped) {                                                                                            \
+        count_kernel<KM, true><<<gc, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, max_count,      \
+                                                   w.counts, view, tw.counts);                               \
+        launch_scan(w, R, packed_info, 2, packed_info + 1, cap, n_out, st);                                   \
+        launch_scan(tw, R * K, tw.offs, 1, nullptr, cap, gtotal, st);                                         \
+        tile_starts_kernel<<<1, 64, 0, st>>>(tw.offs, R, K, gtotal, tile_start);                              \
+        fill_kernel<KM, true><<<gf, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, packed_info,     \
+                                                  cap, t0, t1, pos, ray_id, tile_id, tw.offs, smap);          \
+    } else {                                                                                                  \
+        count_kernel<KM, false><<<gc, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, max_count,     \
+                                                    w.counts, view, nullptr);                                \
+        launch_scan(w, R, packed_info, 2, packed_info + 1, cap, n_out, st);                                   \
+        fill_kernel<KM, false><<<gf, 256, 0, st>>>(rays_o, rays_d, R, bx, samples_per_ray, S, packed_info,    \
+                                                   cap, t0, t1, pos, ray_id, tile_id, nullptr, nullptr);      \
+    }
     if (K == 1) {
         SNAKE_SAMPLER_LAUNCH(1);
     } else if (K <= 4) {
@@ -550,6 +697,25 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
 {
     return sample_impl(__func__, rays_o, rays_d, R, boxes, K, zband, samples_per_ray, S, max_count, packed_info, t0,
                        t1, pos, ray_id, tile_id, view, cap, n_out, workspace, workspace_bytes, stream);
+}
+
+size_t snake_sample_grouped_workspace_bytes(int32_t R, int32_t K)
+{
+    if (R < 0 || K < 1 || K > kMaxTiles || (int64_t)R * K > INT32_MAX) return 0;
+    return grouped_ws_bytes(R, K);
+}
+
+int snake_sample_grouped(const double *rays_o, const double *rays_d, int32_t R, const double *boxes, int32_t K,
+                         const double *zband, const int32_t *samples_per_ray, int32_t S, const int32_t *max_count,
+                         int32_t *packed_info, float *t0, float *t1, float *view, float *pos, int32_t *ray_id,
+                         uint8_t *tile_id, int32_t *sample_map, int64_t *tile_start, int64_t cap, int64_t *n_out,
+                         void *workspace, size_t workspace_bytes, snake_stream_t stream)
+{
+    SNAKE_REQUIRE(cap == 0 || sample_map != nullptr, SNAKE_ERR_NULL, "snake_sample_grouped: sample_map is NULL");
+    int32_t dummy = 0;
+    return sample_impl(__func__, rays_o, rays_d, R, boxes, K, zband, samples_per_ray, S, max_count, packed_info, t0,
+                       t1, pos, ray_id, tile_id, view, cap, n_out, workspace, workspace_bytes, stream,
+                       sample_map ? sample_map : &dummy, tile_start);
 }
 
 int32_t snake_sample_segmented_static_max_rays(void) { return kStaticRays; }

@@ -4,12 +4,12 @@ loaded window.
 
 One window step, every stage a libsnake kernel launched once for all tiles:
 
-    snake_sample_segmented (K boxes, per-ray budgets; rays cut at tile faces)
-    -> snake_tile_partition (samples grouped by tile, gathered copies)
+    snake_sample_grouped (K boxes, per-ray budgets; rays cut at tile faces;
+       samples written grouped by tile, with the map from packed order)
     -> snake_hashgrid_fwd (K tables, tile id per sample)
     -> snake_mlp_fwd (K weight sets, one per 64-sample unit)
     -> snake_composite_fwd / _bwd (per ray across tiles, sample map = inverse
-       partition, so the quadrature runs over the whole ray)
+       grouping, so the quadrature runs over the whole ray)
     -> snake_mlp_bwd (K weight sets) -> snake_hashgrid_bwd (K tables)
     -> snake_counter_add + snake_adam_step (all tables, all networks)
 
@@ -88,13 +88,9 @@ class WindowNeRF:
         self.packed_info = torch.zeros((R, 2), dtype=i32, device=dev)
         self.t0 = torch.empty(cap, dtype=f32, device=dev)
         self.t1 = torch.empty(cap, dtype=f32, device=dev)
-        self.pos = torch.empty((cap, 3), dtype=f32, device=dev)
-        self.ray_id = torch.empty(cap, dtype=i32, device=dev)
-        self.tile_id = torch.empty(cap, dtype=torch.uint8, device=dev)
         self.view = torch.empty((R, 3), dtype=f32, device=dev)
         self.n_out = torch.zeros(1, dtype=i64, device=dev)
-        # tile-partitioned copies
-        self.perm = torch.empty(cap, dtype=i32, device=dev)
+        # samples grouped by tile; inv maps a packed (ray-major) index to its grouped one
         self.inv = torch.empty(cap, dtype=i32, device=dev)
         self.tile_start = torch.zeros(self.K + 2, dtype=i64, device=dev)
         self.pos_s = torch.empty((cap, 3), dtype=f32, device=dev)
@@ -112,9 +108,8 @@ class WindowNeRF:
         self.dsigma = torch.empty(cap, dtype=f32, device=dev)
         self.drgb = torch.empty((cap, 3), dtype=f32, device=dev)
         self.dfeat = torch.empty((self.Lv, cap, self.F), dtype=f32, device=dev)
-        self.ws_sample = torch.empty(L.snake_sample_workspace_bytes(R), dtype=torch.uint8, device=dev)
-        self.ws_part = torch.empty(L.snake_tile_partition_workspace_bytes(self.K), dtype=torch.uint8,
-                                   device=dev)
+        self.ws_sample = torch.empty(L.snake_sample_grouped_workspace_bytes(R, self.K), dtype=torch.uint8,
+                                     device=dev)
         self.ws_mlp = torch.empty(L.snake_mlp_bwd_workspace_bytes(self.mlp, self.K), dtype=torch.uint8,
                                   device=dev)
         budget = int(self.hash_ws_gib * (1 << 30))
@@ -158,11 +153,9 @@ class WindowNeRF:
         cap, K = self.cap, self.K
         self.loss.zero_()
         scale = 1.0 / (3.0 * R)
-        L.snake_sample_segmented(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S, None,
-                                 self.packed_info, self.t0, self.t1, self.pos, self.ray_id, self.tile_id,
-                                 self.view, cap, self.n_out, self.ws_sample, stream)
-        L.snake_tile_partition(self.tile_id, self.pos, self.ray_id, cap, self.n_out, K, self.perm, self.inv,
-                               self.tile_start, self.pos_s, self.tile_s, self.ray_s, self.ws_part, stream)
+        L.snake_sample_grouped(rays_o, rays_d, R, self.boxes, self.zband, samples_per_ray, self.S, None,
+                               self.packed_info, self.t0, self.t1, self.view, self.pos_s, self.ray_s, self.tile_s,
+                               self.inv, self.tile_start, cap, self.n_out, self.ws_sample, stream)
         if self.table_bf16:
             L.snake_convert_bf16(self.table, self.table.numel(), self.table_h, stream)
         L.snake_hashgrid_fwd(self.grid_fwd, K, self.table_h if self.table_bf16 else self.table, self.pos_s,
@@ -206,7 +199,7 @@ class WindowNeRF:
 
     # -- rendering ---------------------------------------------------------
     def render_depth(self, rays_o, rays_d, samples_per_ray=None, sun=None, stream=None):
-        """Forward-only pass (sampler, partition, encoding, networks,
+        """Forward-only pass (grouped sampler, encoding, networks,
         quadrature) over any number of rays, in batches of the buffer size;
         returns the expected depth t of each ray (device FP32)."""
         N = int(rays_o.shape[0])
@@ -216,11 +209,9 @@ class WindowNeRF:
             b1 = min(N, b0 + self.R)
             R = b1 - b0
             spr = None if samples_per_ray is None else samples_per_ray[b0:b1]
-            L.snake_sample_segmented(rays_o[b0:b1], rays_d[b0:b1], R, self.boxes, self.zband, spr, self.S, None,
-                                     self.packed_info, self.t0, self.t1, self.pos, self.ray_id, self.tile_id,
-                                     self.view, cap, self.n_out, self.ws_sample, stream)
-            L.snake_tile_partition(self.tile_id, self.pos, self.ray_id, cap, self.n_out, K, self.perm, self.inv,
-                                   self.tile_start, self.pos_s, self.tile_s, self.ray_s, self.ws_part, stream)
+            L.snake_sample_grouped(rays_o[b0:b1], rays_d[b0:b1], R, self.boxes, self.zband, spr, self.S, None,
+                                   self.packed_info, self.t0, self.t1, self.view, self.pos_s, self.ray_s,
+                                   self.tile_s, self.inv, self.tile_start, cap, self.n_out, self.ws_sample, stream)
             L.snake_hashgrid_fwd(self.grid, K, self.table, self.pos_s, self.tile_s, None, cap, self.n_out,
                                  self.feat, None, stream)
             L.snake_mlp_fwd(self.mlp, self.params, self.feat, self.view, None if sun is None else sun[b0:b1],

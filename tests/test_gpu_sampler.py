@@ -190,3 +190,84 @@ def test_tile_partition_is_stable_sort(L, K):
         assert np.array_equal(host(ro)[:ne], rid[ref])
         err = L.snake_check_device_error()
         assert bool(err & L.SNAKE_DEVERR_TILE_ID) == (K > 1)
+
+
+def _run_grouped(L, rays_o, rays_d, boxes, S, zband=None, spr=None, max_count=None):
+    R = int(np.asarray(rays_o).shape[0])
+    K = np.asarray(boxes).reshape(-1, 6).shape[0]
+    cap = max(int(np.sum(spr)) if spr is not None else R * int(S), 1)
+    Rb = max(R, 1)
+    out = dict(packed_info=torch.full((Rb, 2), -1, dtype=torch.int32, device=DEV),
+               t0=torch.zeros(cap, device=DEV), t1=torch.zeros(cap, device=DEV),
+               view=torch.zeros((Rb, 3), device=DEV), pos=torch.zeros((cap, 3), device=DEV),
+               ray_id=torch.full((cap,), -1, dtype=torch.int32, device=DEV),
+               tile_id=torch.full((cap,), 255, dtype=torch.uint8, device=DEV),
+               smap=torch.full((cap,), -1, dtype=torch.int32, device=DEV),
+               tile_start=torch.full((K + 2,), -1, dtype=torch.int64, device=DEV),
+               n_out=torch.full((1,), -1, dtype=torch.int64, device=DEV))
+    ws = torch.empty(L.snake_sample_grouped_workspace_bytes(R, K), dtype=torch.uint8, device=DEV)
+    ro = dev(np.asarray(rays_o, np.float64).reshape(-1, 3)) if R else None
+    rd = dev(np.asarray(rays_d, np.float64).reshape(-1, 3)) if R else None
+    L.snake_sample_grouped(ro, rd, R, boxes, zband, None if spr is None else dev(spr, torch.int32), S,
+                           None if max_count is None else dev(max_count, torch.int32), out["packed_info"],
+                           out["t0"], out["t1"], out["view"], out["pos"], out["ray_id"], out["tile_id"],
+                           out["smap"], out["tile_start"], cap, out["n_out"], ws)
+    sync()
+    res = {k: host(v) for k, v in out.items()}
+    n = int(res["n_out"][0])
+    res["n"] = n
+    for k in ("t0", "t1", "pos", "ray_id", "tile_id", "smap"):
+        res[k] = res[k][:n]
+    res["packed_info"], res["view"] = res["packed_info"][:R], res["view"][:R]
+    return res
+
+
+def _check_grouped(g, o, K):
+    """The grouped outputs are the oracle's packed samples stably sorted by
+    tile; t0/t1, packed_info and view stay in packed order."""
+    n = o["n"]
+    assert g["n"] == n
+    assert np.array_equal(g["packed_info"], o["packed_info"])
+    assert np.array_equal(g["view"], o["view"])
+    assert np.array_equal(g["t0"], o["t0"]) and np.array_equal(g["t1"], o["t1"])
+    tid = o["tile_id"] if o.get("tile_id") is not None else np.zeros(n, np.uint8)
+    perm = np.argsort(tid, kind="stable")
+    assert np.array_equal(g["pos"], o["pos"][perm])
+    assert np.array_equal(g["ray_id"], o["ray_id"][perm])
+    assert np.array_equal(g["tile_id"], tid[perm])
+    assert np.array_equal(g["smap"][perm], np.arange(n))
+    bounds = np.searchsorted(tid[perm], np.arange(K + 1))
+    assert np.array_equal(g["tile_start"], np.concatenate([bounds, [n]]))
+
+
+def test_grouped_sampler_matches_oracle(L, orc):
+    """snake_sample_grouped: the packed samples of the oracle, written grouped
+    by tile, over 2x2 windows (ragged budgets, misses, axis and vertical
+    rays; world coordinates with an altitude band), five tiles (the 16-box
+    kernels), one tile, truncation by max_count, and no rays."""
+    rng = np.random.default_rng(2)
+    boxes = _grid_boxes(2, 2)
+    o, d = _slanted(rng, 4000, -0.3, 2.3, z_top=1.6)
+    o[:8] = [[0.5, 0.5, 2], [1.0, 0.5, 2], [1.0, 1.0, 2], [3, 3, 2], [0.25, 0.75, 0.5],
+             [-1, 0.5, 0.5], [0.5, -1, 0.25], [1.5, 1.5, 1.0]]
+    d[:8] = [[0, 0, -1], [0, 0, -1], [0, 0, -1], [0, 0, -1], [0, 0, -1], [1, 0, 0], [0, 1, 0],
+             [0.3, -0.2, -0.9]]
+    spr = rng.integers(0, 129, size=4000).astype(np.int32)
+    spr[:3] = [1, 2, 3]
+    _check_grouped(_run_grouped(L, o, d, boxes, 0, spr=spr), orc.sample_segmented(o, d, boxes, 0, samples_per_ray=spr), 4)
+    mc = rng.integers(-2, 90, size=4000).astype(np.int32)
+    _check_grouped(_run_grouped(L, o, d, boxes, 0, spr=spr, max_count=mc),
+                   orc.sample_segmented(o, d, boxes, 0, samples_per_ray=spr, max_count=mc), 4)
+    boxes2 = _grid_boxes(2, 2, side=153.6, z=(0.0, 200.0), x0=412345.0, y0=3312345.0)
+    o2 = o * np.array([153.6, 153.6, 200.0]) + np.array([412345.0, 3312345.0, 0.0])
+    d2 = d * np.array([153.6, 153.6, 200.0])
+    _check_grouped(_run_grouped(L, o2, d2, boxes2, 96, zband=[20.0, 180.0]),
+                   orc.sample_segmented(o2, d2, boxes2, 96, zband=[20.0, 180.0]), 4)
+    boxes5 = _grid_boxes(3, 2)[:5]
+    o5, d5 = _slanted(rng, 3000, -0.3, 3.3, z_top=1.6)
+    _check_grouped(_run_grouped(L, o5, d5, boxes5, 64), orc.sample_segmented(o5, d5, boxes5, 64), 5)
+    w = synth.tiny_tile(seed=0)
+    _check_grouped(_run_grouped(L, w.rays_o, w.rays_d, w.boxes, 64),
+                   orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 64), 1)
+    g = _run_grouped(L, np.zeros((0, 3)), np.zeros((0, 3)), boxes, 16)
+    assert g["n"] == 0 and np.all(g["tile_start"] == 0)

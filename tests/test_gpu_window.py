@@ -78,9 +78,18 @@ def test_window_step_matches_oracle(orc, shared, prec):
     n = int(host(nerf.n_out)[0])
     assert n == smp["n"]
     assert np.array_equal(host(nerf.packed_info), smp["packed_info"])
-    assert np.array_equal(host(nerf.tile_id)[:n], smp["tile_id"])
     inv = host(nerf.inv)[:n]
     assert np.array_equal(np.sort(inv), np.arange(n))
+    # grouped by tile (packed order within a tile), and the same samples
+    assert np.all(np.diff(host(nerf.tile_s)[:n].astype(np.int64)) >= 0)
+    perm = np.empty(n, np.int64)
+    perm[inv] = np.arange(n)
+    ts = host(nerf.tile_start)
+    for k in range(4):
+        assert np.all(np.diff(perm[ts[k]:ts[k + 1]]) > 0)
+    assert np.array_equal(host(nerf.tile_s)[inv], smp["tile_id"])
+    assert np.array_equal(host(nerf.pos_s)[inv], smp["pos"])
+    assert np.array_equal(host(nerf.ray_s)[inv], np.repeat(np.arange(R), smp["packed_info"][:, 1]))
     ts = host(nerf.tile_start)
     assert np.array_equal(np.diff(ts[:5]), np.bincount(smp["tile_id"], minlength=4))
     sig, rgb, rgb_out = host(nerf.sigma)[inv], host(nerf.rgb)[inv], host(nerf.rgb_out)[:R]
