@@ -25,6 +25,10 @@ ARCH = os.environ.get("SNAKE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary vector registers: without this the
+    # compiler accumulates in AGPRs and copies every result value out with
+    # one more instruction (the network kernels are bound by such work)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]

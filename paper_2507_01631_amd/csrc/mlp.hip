@@ -221,13 +221,19 @@ __device__ __forceinline__ void apply(const typename FragT<PREC>::T *frag, const
     }
 }
 
+// max(v, 0) as an integer maximum of the bits (a negative float is a
+// negative integer): one instruction, where fmaxf first quiets a possible
+// signalling NaN with a second one.  -0 becomes +0.
 template <int T>
 __device__ __forceinline__ void relu(float (&v)[T][4])
 {
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[t][r] = fmaxf(v[t][r], 0.0f);
+        for (int r = 0; r < 4; ++r) {
+            const int b = __builtin_bit_cast(int, v[t][r]);
+            v[t][r] = __builtin_bit_cast(float, b > 0 ? b : 0);
+        }
 }
 
 template <int T>
@@ -601,17 +607,54 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_pipe_kernel(MlpArgs a, const f
         RawFeat<FT> raw;
         float dirs[4];
     };
+    // Addressing that does not change from unit to unit, set up once: the
+    // level slices of this lane's four feature rows (rows 2 lvl, 2 lvl + 1
+    // of level lvl = 8t + 2q + h; slice 0 for rows past the input), the
+    // sources of its four direction rows (view or sun, 3 floats per ray; a
+    // row that is neither reads view[0]), and its output word (lane q = 0:
+    // sigma, q = 1..3: colour channel q-1).
+    const FT *fb[2][2];
+    uint32_t fuse = 0u;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int lvl = 8 * t + 2 * q + h;
+            const bool u = 2 * lvl < a.n_feat;
+            fb[t][h] = feat + (u ? (int64_t)lvl * n : 0) * 2;
+            fuse |= (u ? 1u : 0u) << (2 * t + h);
+        }
+    const float *db[4];
+    uint32_t dm = 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int kd = 4 * q + r;
+        const bool from_view = kd < 3, from_sun = kd >= 3 && kd < a.n_dir && sun != nullptr;
+        db[r] = from_sun ? sun + (kd - 3) : view + (from_view ? kd : 0);
+        dm |= (from_view || from_sun ? 1u : 0u) << r;
+    }
+    float *const ob = q == 0 ? sigma : rgb + (q - 1);
+    const int64_t ostride = q == 0 ? 1 : 3;
     auto issue = [&](int64_t u, In &in) {
         int64_t s0, s1;
         locate(U, a.K, u, in.k, s0, s1);
         in.s = s0 + 16 * wv + i;
         in.valid = in.s < s1;
         in.ray = ray_id[in.valid ? in.s : s0];               // a sample that exists
-        issue_features<FT>(feat, n, in.s, in.valid, a, in.raw, in.use);
+        // every lane loads from a valid address; unwanted rows are masked
+        const int64_t se = in.valid ? in.s : 0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) in.raw.load(fb[t][h] + se * 2, t, h);
+        in.use = in.valid ? fuse : 0u;
     };
     auto issue_dirs_of = [&](In &in) {
         const bool ok = in.valid && in.k < a.K && in.ray >= 0 && in.ray < a.R;
-        issue_dirs(view, sun, ok ? in.ray : 0, a, in.dirs, in.dmask);
+        const int64_t r3 = 3 * (int64_t)(ok ? in.ray : 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) in.dirs[r] = db[r][((dm >> r) & 1u) ? r3 : 0];
+        in.dmask = dm;
     };
     int cur = -1;
     // one unit: compute `in`, loading unit u + grid into `nx` meanwhile (two
@@ -624,10 +667,7 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_pipe_kernel(MlpArgs a, const f
         const bool ok = valid && in.ray >= 0 && in.ray < a.R;   // a bad ray id drops the sample
         if (valid && !ok && q == 0 && a.err) atomicOr(a.err, (unsigned)SNAKE_DEVERR_RAY_ID);
         if (in.k == a.K) {                                   // invalid tile id: dropped
-            if (q == 0 && in.valid) {
-                sigma[s] = 0.0f;
-                rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
-            }
+            if (in.valid) ob[s * ostride] = 0.0f;
             if (more) issue_dirs_of(nx);
             return;
         }
@@ -665,19 +705,20 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_pipe_kernel(MlpArgs a, const f
         if constexpr (STORE) {
             if (ok) store_acts<PREC, CL>(act + s * ActLayout<CL>::W, A);
         }
-        if (q == 0 && valid && !ok) {
-            sigma[s] = 0.0f;
-            rgb[3 * s] = rgb[3 * s + 1] = rgb[3 * s + 2] = 0.0f;
-        } else if (q == 0 && valid) {
-            sigma[s] = expf(A.o[0][0]);
-            if (a.CO == 3) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]);
-            } else {
-                const float vis = sigmoidf(A.out[0][3]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) rgb[3 * s + c] = sigmoidf(A.out[0][c]) * vis;
-            }
+        // The four lanes of a sample share its outputs: lane q = 0 writes
+        // sigma = exp(o_0), lane q = 1..3 colour channel q-1 (its logit read
+        // from lane q = 0), so each lane evaluates one exponential.
+        {
+            // every lane takes part in every shuffle (a lane reading from an
+            // inactive one would get 0), so they come first, unconditionally
+            const float f0 = __shfl(A.out[0][0], i, 64), f1 = __shfl(A.out[0][1], i, 64),
+                        f2 = __shfl(A.out[0][2], i, 64), f3 = __shfl(A.out[0][3], i, 64);
+            const float logit = q == 1 ? f0 : (q == 2 ? f1 : f2);
+            const float e = expf(q == 0 ? A.o[0][0] : -logit);
+            const float sg = 1.0f / (1.0f + e);
+            float v = q == 0 ? e : sg;
+            if (a.CO != 3 && q != 0) v = v * sigmoidf(f3);
+            if (valid) ob[s * ostride] = ok ? v : 0.0f;
         }
         if (more) issue_dirs_of(nx);
     };
