@@ -680,7 +680,7 @@ def main():
     ap.add_argument("--conv-orders", type=int, default=6,
                     help="batch orders for the FP32 and BF16 forms")
     ap.add_argument("--conv-orders-t16", type=int, default=2, help="batch orders for the BF16-table form")
-    ap.add_argument("--atomic-orders", type=int, default=4)
+    ap.add_argument("--atomic-orders", type=int, default=3)
     ap.add_argument("--conv-occupancy", type=int, default=1,
                     help="add a BF16 convergence run with a 128^3 occupancy grid")
     ap.add_argument("--conv-occ-start", type=int, default=256, help="first step that updates the grid")
