@@ -269,6 +269,13 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
         const int64_t start = info[2 * (int64_t)r];
         const int count = info[2 * (int64_t)r + 1];
         if (count == 0) continue;
+        // grouped form: where this ray's samples start in each tile's group,
+        // tile k's in lane k (loaded first, so the load overlaps the segment
+        // work; a sample reads its tile's with a lane shuffle)
+        int32_t gl = 0;
+        if constexpr (Grouped) {
+            if (lane < bx.K) gl = goffs[(int64_t)lane * R + r];
+        }
         double o[3], d[3];
         load_ray(ro, rd, r, o, d);
         Segs<KMAX> sg;
@@ -328,6 +335,7 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
                 ol[a] = KMAX > 1 ? __shfl(olp[a], s, 64) : olp[a];
                 dl[a] = KMAX > 1 ? __shfl(dlp[a], s, 64) : dlp[a];
             }
+            const int32_t gstart = Grouped ? __shfl(gl, tile, 64) : 0;
             if (j >= count) continue;
             const int k = j - before;
             float tn = (float)stn, tf = (float)stf;
@@ -341,7 +349,7 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
             t1[out] = tb;
             int64_t g = out;
             if constexpr (Grouped) {
-                g = (int64_t)goffs[(int64_t)tile * R + r] + k;
+                g = (int64_t)gstart + k;
                 smap[out] = (int32_t)g;
                 if (g >= cap) continue;
             }
