@@ -779,12 +779,13 @@ __device__ __forceinline__ void val_accumulate(uint32_t code, int k0, unsigned l
     const uint32_t m = code ? ((code & 0x7ffffu) | 0x80000u) : 0u;
     const bool isbig = k <= 22;
     const int sh = (isbig ? 22 : 44) - k;        // -19 .. 21 for the values (k = 1..63)
-    const int shl = sh > 0 ? sh : 0, shr = sh < 0 ? -sh : 0;
-    // below 2^(Et-44) (shr > 0): rounded to the unit, halves away from 0
-    const uint32_t mr = (m + ((1u << shr) >> 1)) >> shr;
-    const uint64_t t = (uint64_t)mr << shl;
-    const uint64_t sgn = (uint64_t)(int64_t)((int32_t)(code << 6) >> 31);   // all ones when negative
-    atomicAdd(isbig ? big : small, (unsigned long long)((t ^ sgn) - sgn));
+    // the signed value +-m 2^sh in the unit, below 2^(Et-44) (sh < 0) rounded
+    // to it, halves away from 0: x = +-m 2^(sh+21) is exact in 64 bits, and
+    // (x + 2^20 - [x < 0]) >> 21, shifting arithmetically, is that rounding
+    const int32_t s = (int32_t)(code << 6) >> 31;                      // -1 when negative
+    const int32_t ms = (int32_t)((m ^ (uint32_t)s) - (uint32_t)s);
+    const int64_t x = (int64_t)((uint64_t)(int64_t)ms << (sh + 21));
+    atomicAdd(isbig ? big : small, (unsigned long long)((x + ((int64_t)1 << 20) + s) >> 21));
 }
 
 // Samples of this count/scatter block: a contiguous range of whole 64-sample
