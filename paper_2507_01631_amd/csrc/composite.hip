@@ -122,14 +122,34 @@ __global__ __launch_bounds__(kLossThreads) void loss_kernel(const float *__restr
 {
     __shared__ float red[kLossThreads / 64];
     float s = 0.0f, comp = 0.0f;                 // Kahan sum of this thread's rays
-    for (int r = threadIdx.x; r < R; r += kLossThreads) {
-        const float e0 = rgb_out[3 * (int64_t)r] - target[3 * (int64_t)r];
-        const float e1 = rgb_out[3 * (int64_t)r + 1] - target[3 * (int64_t)r + 1];
-        const float e2 = rgb_out[3 * (int64_t)r + 2] - target[3 * (int64_t)r + 2];
-        const float y = (e0 * e0 + e1 * e1 + e2 * e2) - comp;
-        const float t = s + y;
-        comp = (t - s) - y;
-        s = t;
+    // rays r = tid, tid + kLossThreads, ... in that order; kLossU of them
+    // loaded at once (a ray past R re-reads ray R - 1 and is not added), so
+    // the loads overlap instead of each waiting for the one before
+    constexpr int kLossU = 8;
+    for (int r0 = threadIdx.x; r0 < R; r0 += kLossU * kLossThreads) {
+        float o[kLossU][3], g[kLossU][3];
+#pragma unroll
+        for (int u = 0; u < kLossU; ++u) {
+            const int r = r0 + u * kLossThreads < R ? r0 + u * kLossThreads : R - 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                o[u][c] = rgb_out[3 * (int64_t)r + c];
+                g[u][c] = target[3 * (int64_t)r + c];
+            }
+        }
+        // every load issued before any is used (the selects below keep the
+        // compiler from moving a load into a branch of its own)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kLossU; ++u) {
+            const bool ok = r0 + u * kLossThreads < R;
+            const float e0 = o[u][0] - g[u][0], e1 = o[u][1] - g[u][1], e2 = o[u][2] - g[u][2];
+            const float y = (e0 * e0 + e1 * e1 + e2 * e2) - comp;
+            const float t = s + y;
+            const float c = (t - s) - y;
+            s = ok ? t : s;
+            comp = ok ? c : comp;
+        }
     }
     s = wave_sum(s);
     if (lane_id() == 0) red[threadIdx.x >> 6] = s;
