@@ -18,21 +18,11 @@
 // transpose: per wavefront in the FP32 form, split across the block's four
 // wavefronts in the BF16 form (which then fits two wavefronts per SIMD).
 // Per-block partial sums are reduced in a fixed order by a second kernel.
+#include <type_traits>
+
 #include "common.h"
 
 namespace snake {
-namespace {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
-
-constexpr int kBlock = 256;   // 4 wavefronts
-constexpr int kMaxBwdBlocks = 512;
-
-enum Prec { P_F32 = 0, P_BF16 = 1 };
-enum Mat { M_D1 = 0, M_D2, M_C1, M_C2, M_CO };
 
 struct MlpArgs {
     int L, F, n_feat;       // encoding levels, features per level, L*F
@@ -47,6 +37,38 @@ struct MlpArgs {
     int shared_colour;      // 1: density nets per tile, one colour net for all
     int32_t Pd;             // density parameters of one set (D1 + D2)
 };
+
+// The BF16 pipelined adjoint (mlp_bwd_pipe_kernel<P_BF16, ...>) is compiled in
+// a translation unit of its own, mlp_bwd16.hip (this file with SNAKE_MLP_BWD16
+// defined), whose scheduler minimises registers: the kernel holds about 400
+// values at two wavefronts per SIMD, and fewer spills pay more than the
+// latency the other schedule hides.  cl: colour hidden layers; feat_bf16:
+// features stored as BF16 (else FP32).
+void launch_bwd_pipe_bf16(const MlpArgs &a, int cl, bool feat_bf16, unsigned grid, const float *w, const void *feat,
+                          int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
+                          const int32_t *sidx, int64_t n, const int64_t *n_dev, const float *dsigma,
+                          const float *drgb, float *dfeat, float *partial, const void *frag, hipStream_t st);
+
+namespace {
+
+#ifdef SNAKE_MLP_BWD16
+constexpr bool kBwd16Unit = true;
+#else
+constexpr bool kBwd16Unit = false;
+#endif
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;   // 4 wavefronts
+constexpr int kMaxBwdBlocks = 512;
+
+enum Prec { P_F32 = 0, P_BF16 = 1 };
+enum Mat { M_D1 = 0, M_D2, M_C1, M_C2, M_CO };
+
+
 
 // Base pointers of tile k's density and colour weights, so that
 // wd + off[0..1] and wc + off[2..4] address its matrices.  Per-tile sets are
@@ -1625,6 +1647,21 @@ void launch_fwd(const MlpArgs &a, const float *w, const void *feat, const float 
 }
 
 template <int PREC, int CL, typename FT>
+void launch_bwd_pipe(const MlpArgs &a, unsigned grid, const float *w, const void *feat, int64_t feat_ld,
+                     const float *view, const float *sun, const int32_t *ray_id, const int32_t *sidx, int64_t n,
+                     const int64_t *n_dev, const float *dsigma, const float *drgb, float *dfeat, float *partial,
+                     const void *frag, hipStream_t st)
+{
+    if constexpr (PREC == P_BF16 && !kBwd16Unit) {
+        // compiled in mlp_bwd16.hip; launch_bwd calls launch_bwd_pipe_bf16
+    } else {
+        mlp_bwd_pipe_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(
+            a, w, static_cast<const FT *>(feat), feat_ld, view, sun, ray_id, sidx, n, n_dev, dsigma, drgb, dfeat,
+            partial, static_cast<const typename FragT<PREC>::T *>(frag));
+    }
+}
+
+template <int PREC, int CL, typename FT>
 void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat_ld, const float *view,
                 const float *sun, const int32_t *ray_id, const int32_t *sidx, int64_t n, const int64_t *n_dev,
                 const float *dsigma, const float *drgb, const float *act, float *dW, float *dfeat, float *partial,
@@ -1636,10 +1673,12 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
     typedef typename FragT<PREC>::T FragEl;
     FragEl *frag = reinterpret_cast<FragEl *>(reinterpret_cast<char *>(partial) + partial_bytes(a));
     mlp_frag_kernel<PREC, CL><<<a.K, kBlock, 0, st>>>(a, w, frag);
-    if (!act && a.F == 2)
-        mlp_bwd_pipe_kernel<PREC, CL, FT><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view,
-                                                                   sun, ray_id, sidx, n, n_dev, dsigma, drgb, dfeat,
-                                                                   partial, frag);
+    if (!act && a.F == 2 && PREC == P_BF16)
+        launch_bwd_pipe_bf16(a, CL, std::is_same<FT, __hip_bfloat16>::value, grid, w, feat, feat_ld, view, sun, ray_id,
+                             sidx, n, n_dev, dsigma, drgb, dfeat, partial, frag, st);
+    else if (!act && a.F == 2)
+        launch_bwd_pipe<PREC, CL, FT>(a, grid, w, feat, feat_ld, view, sun, ray_id, sidx, n, n_dev, dsigma, drgb,
+                                      dfeat, partial, frag, st);
     else if (act)
         mlp_bwd_kernel<PREC, CL, FT, true><<<grid, kBlock, 0, st>>>(a, w, static_cast<const FT *>(feat), feat_ld, view,
                                                                     sun, ray_id, sidx, n, n_dev, dsigma, drgb, act,
@@ -1654,8 +1693,27 @@ void launch_bwd(const MlpArgs &a, const float *w, const void *feat, int64_t feat
 }
 
 }  // namespace
+
+#ifdef SNAKE_MLP_BWD16
+void launch_bwd_pipe_bf16(const MlpArgs &a, int cl, bool feat_bf16, unsigned grid, const float *w, const void *feat,
+                          int64_t feat_ld, const float *view, const float *sun, const int32_t *ray_id,
+                          const int32_t *sidx, int64_t n, const int64_t *n_dev, const float *dsigma,
+                          const float *drgb, float *dfeat, float *partial, const void *frag, hipStream_t st)
+{
+#define SNAKE_BWD16(C, FT)                                                                                     \
+    launch_bwd_pipe<P_BF16, C, FT>(a, grid, w, feat, feat_ld, view, sun, ray_id, sidx, n, n_dev, dsigma, drgb, \
+                                   dfeat, partial, frag, st)
+    if (cl == 2) {
+        if (feat_bf16) SNAKE_BWD16(2, __hip_bfloat16); else SNAKE_BWD16(2, float);
+    } else {
+        if (feat_bf16) SNAKE_BWD16(1, __hip_bfloat16); else SNAKE_BWD16(1, float);
+    }
+#undef SNAKE_BWD16
+}
+#endif
 }  // namespace snake
 
+#ifndef SNAKE_MLP_BWD16
 using namespace snake;
 
 extern "C" {
@@ -1794,3 +1852,4 @@ int snake_mlp_bwd(const snake_mlp_desc *m, int32_t K, const float *weights, cons
 }
 
 }  // extern "C"
+#endif  // SNAKE_MLP_BWD16
