@@ -391,7 +391,6 @@ __global__ __launch_bounds__(kLdsThreads) void hashgrid_fwd_lds_kernel(Grid g, c
 {
     extern __shared__ uint4 sslice[];
     __shared__ int srange[2];
-    typedef typename Vec<F>::T VT;
     const TabT *lev = reinterpret_cast<const TabT *>(sslice);
     const int64_t ne = effective_n(n, n_dev);
     const int64_t per = (int64_t)kLdsThreads * kLdsR;
@@ -1180,7 +1179,6 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(BinPlan bp, 
     __shared__ unsigned long long small[kAccWords];
     const int64_t total = *n_items;
     const int slots = 1 << bp.binshift;
-    const uint32_t smask = (uint32_t)slots - 1;
     constexpr int NW = ItemFmt<F>::NW;
     // one contiguous, equal share of the pass's items per block (the grid is
     // what the chip holds at once, so there is no tail of late blocks)
