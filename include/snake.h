@@ -188,6 +188,9 @@ int snake_sample_segmented(const double *rays_o, const double *rays_d, int32_t R
  * groups: tile k holds grouped indices tile_start[k] .. tile_start[k+1]-1,
  * and tile_start[K] = tile_start[K+1] = *n_out.  Replaces the sampler and
  * the partition with one count, two scans and one fill.  R * K < 2^31.
+ * When the total exceeds cap (SNAKE_DEVERR_CAPACITY), a sample whose grouped
+ * index would be cap or more is not written and its sample_map entry is
+ * cap - 1, so that no consumer of the map reads past the arrays.
  * Workspace: snake_sample_grouped_workspace_bytes(R, K) (0 for bad R, K),
  * 256-byte aligned.  Errors as snake_sample_segmented.
  */

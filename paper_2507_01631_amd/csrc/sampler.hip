@@ -350,7 +350,9 @@ __global__ __launch_bounds__(256) void fill_kernel(const double *__restrict__ ro
             int64_t g = out;
             if constexpr (Grouped) {
                 g = (int64_t)gstart + k;
-                smap[out] = (int32_t)g;
+                // past the capacity (an overflow, flagged by the scan) the
+                // map still points inside the arrays
+                smap[out] = (int32_t)(g < cap ? g : cap - 1);
                 if (g >= cap) continue;
             }
 #pragma unroll

@@ -271,3 +271,25 @@ def test_grouped_sampler_matches_oracle(L, orc):
                    orc.sample_segmented(w.rays_o, w.rays_d, w.boxes, 64), 1)
     g = _run_grouped(L, np.zeros((0, 3)), np.zeros((0, 3)), boxes, 16)
     assert g["n"] == 0 and np.all(g["tile_start"] == 0)
+
+
+def test_grouped_sampler_capacity_overflow(L):
+    """Too small a capacity: the overflow is flagged, and every map entry of the
+    kept packed samples still points inside the arrays."""
+    rng = np.random.default_rng(3)
+    boxes = _grid_boxes(2, 2)
+    o, d = _slanted(rng, 3000, -0.3, 2.3, z_top=1.6)
+    R, K, cap = 3000, 4, 20000
+    ws = torch.empty(L.snake_sample_grouped_workspace_bytes(R, K), dtype=torch.uint8, device=DEV)
+    f = lambda *s, dt=torch.float32: torch.zeros(s, dtype=dt, device=DEV)
+    smap = torch.full((cap,), -1, dtype=torch.int32, device=DEV)
+    n_out = f(1, dt=torch.int64)
+    L.snake_check_device_error()
+    L.snake_sample_grouped(dev(o), dev(d), R, boxes, None, None, 64, None, f(R, 2, dt=torch.int32), f(cap), f(cap),
+                           f(R, 3), f(cap, 3), f(cap, dt=torch.int32), f(cap, dt=torch.uint8), smap,
+                           f(K + 2, dt=torch.int64), cap, n_out, ws)
+    sync()
+    assert int(n_out.item()) > cap
+    assert L.snake_check_device_error() & L.SNAKE_DEVERR_CAPACITY
+    m = host(smap)
+    assert np.all((m >= 0) & (m < cap))
