@@ -246,6 +246,24 @@ __device__ __forceinline__ void apply(const typename FragT<PREC>::T *frag, const
 // max(v, 0) as an integer maximum of the bits (a negative float is a
 // negative integer): one instruction, where fmaxf first quiets a possible
 // signalling NaN with a second one.  -0 becomes +0.
+// A BF16 layer with K = 32 whose operand is given as four words of two bf16
+// each (the bf8 operand apply() would pack from x[2][4]); the same products.
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+template <int MO>
+__device__ __forceinline__ void apply_bf16_words(const __bf16 *frag, const uint32_t (&w)[4], float (&y)[MO / 16][4])
+{
+    const int lane = lane_id();
+    const bf8 *fr = reinterpret_cast<const bf8 *>(frag);
+    const bf8 b = __builtin_bit_cast(bf8, u4v{w[0], w[1], w[2], w[3]});
+#pragma unroll
+    for (int to = 0; to < MO / 16; ++to) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[to * 64 + lane], b, acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[to][r] = acc[r];
+    }
+}
+
 template <int T>
 __device__ __forceinline__ void relu(float (&v)[T][4])
 {
@@ -705,8 +723,21 @@ __global__ __launch_bounds__(kBlock) void mlp_fwd_pipe_kernel(MlpArgs a, const f
         // keep the scheduler from reading loaded values before their layer
         // (the wait for a load sits at its first use)
         __builtin_amdgcn_sched_barrier(0);
-        take_features<FT>(in.raw, in.use, ok, A.x);
-        apply<PREC, 64, 32>(lds + Lt::D1, A.x, A.h1);
+        if constexpr (PREC == P_BF16 && std::is_same<FT, __hip_bfloat16>::value) {
+            // BF16 features are already the first layer's operand: lane
+            // (i, q) holds rows 4q..4q+3 and 16+4q..16+4q+3 of sample i, the
+            // four feature-pair words it loaded, in that order
+            uint32_t w[4];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    w[2 * t + h] = ok && ((in.use >> (2 * t + h)) & 1u) ? in.raw.w[t][h] : 0u;
+            apply_bf16_words<64>(lds + Lt::D1, w, A.h1);
+        } else {
+            take_features<FT>(in.raw, in.use, ok, A.x);
+            apply<PREC, 64, 32>(lds + Lt::D1, A.x, A.h1);
+        }
         relu(A.h1);
         apply<PREC, 16, 64>(lds + Lt::D2, A.h1, A.o);
         __builtin_amdgcn_sched_barrier(0);
