@@ -114,7 +114,7 @@ def run_form(wl, precision, args, pool, steps=None, tune=None, nerf=None):
         def one():
             nerf.train_step(*batch(cnt[0]))
             cnt[0] += 1
-        tuned, ms, _ = autotune.tune(one, reps=3, warmup=1)
+        tuned, ms, _ = autotune.tune(one, reps=5, warmup=1)
         log("  %s: tuned launch shapes %s (%.2f ms)" % (precision, tuned, ms))
     else:
         from paper_2507_01631_amd import autotune

@@ -109,7 +109,7 @@ int snake_check_device_error(snake_stream_t stream, uint32_t *bits);
  */
 typedef enum {
     SNAKE_TUNE_HASH_FWD_BLOCKS_PER_CU = 0,  /* hash-grid forward grid, 1..64 (16) */
-    SNAKE_TUNE_MLP_FWD_BLOCKS_PER_CU = 1,   /* network forward grid, 1..16 (4) */
+    SNAKE_TUNE_MLP_FWD_BLOCKS_PER_CU = 1,   /* network forward grid, 1..16 (8) */
     SNAKE_TUNE_MLP_BWD_BLOCKS_PER_CU = 2,   /* network adjoint grid, 0..2 (0: 2 for BF16,
                                                1 for FP32); changes the dW summation order */
     SNAKE_TUNE_COMPOSITE_BLOCKS_PER_CU = 3, /* rendering grid, 1..64 (8) */

@@ -73,10 +73,10 @@ int lds_bytes(bool per_cu)
 }
 
 // Launch-shape tunables (the only process-wide setting).
-static const int32_t kTuneDefault[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 2048, 0, 16, 0, 1};
+static const int32_t kTuneDefault[SNAKE_TUNE_COUNT] = {16, 8, 0, 8, 2048, 0, 16, 0, 1};
 static const int32_t kTuneMin[SNAKE_TUNE_COUNT] = {1, 1, 0, 1, 64, 0, 1, 0, 0};
 static const int32_t kTuneMax[SNAKE_TUNE_COUNT] = {64, 16, 2, 64, 2048, 32, 64, 64, 1};
-static int32_t g_tune[SNAKE_TUNE_COUNT] = {16, 4, 0, 8, 2048, 0, 16, 0, 1};
+static int32_t g_tune[SNAKE_TUNE_COUNT] = {16, 8, 0, 8, 2048, 0, 16, 0, 1};
 
 int tune(int which) { return g_tune[which]; }
 
