@@ -1,6 +1,7 @@
-"""Host-side logic that needs no GPU: the snake path and the swap plan of the
-sweep, the coordinate-descent autotuner (with a synthetic cost), the bench's
-roofline bookkeeping and its refusal of more than one GPU."""
+"""Host-side logic that needs no GPU: the snake path (with the per-tile window
+count of Sec. 4.4 as a fixture) and the swap plan of the sweep, the
+coordinate-descent autotuner (with a synthetic cost), the bench's roofline
+bookkeeping and its refusal of more than one GPU."""
 import os
 import subprocess
 import sys
@@ -19,6 +20,37 @@ def test_snake_path_visits_every_window_by_single_moves(nx, ny):
     assert sorted(path) == sorted((x, y) for x in range(nx - 1) for y in range(ny - 1))
     for a, b in zip(path, path[1:]):
         assert abs(a[0] - b[0]) + abs(a[1] - b[1]) == 1        # neighbouring windows
+
+
+def _golden_multiplicity():
+    grids, cur = [], None
+    with open(os.path.join(ROOT, "tests", "golden", "snake_window_multiplicity.txt")) as f:
+        for line in f:
+            words = line.split("#", 1)[0].split()
+            if not words:
+                continue
+            if words[0] == "grid":
+                cur = (int(words[1]), int(words[2]), [])
+                grids.append(cur)
+            else:
+                cur[2].append([int(w) for w in words])
+    return grids
+
+
+def test_snake_path_trains_corners_once_edges_twice_interior_four_times():
+    """Sec. 4.4: over one sweep a corner tile sits in 1 window, an edge tile in 2,
+    an interior tile in 4 (fixture written from that rule, north row first)."""
+    from paper_2507_01631_amd.sweep import snake_path
+    grids = _golden_multiplicity()
+    assert {(3, 3), (4, 4), (8, 8)} <= {(nx, ny) for nx, ny, _ in grids}
+    for nx, ny, rows in grids:
+        assert len(rows) == ny and all(len(r) == nx for r in rows)
+        want = np.array(rows[::-1]).T                 # indexed [x][y]
+        got = np.zeros((nx, ny), dtype=np.int64)
+        for wx, wy in snake_path(nx, ny):
+            got[wx:wx + 2, wy:wy + 2] += 1
+        np.testing.assert_array_equal(got, want, err_msg=f"{nx}x{ny}")
+        assert got.sum() == 4 * (nx - 1) * (ny - 1)
 
 
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4), (8, 8)])
